@@ -1,0 +1,1019 @@
+/*
+ * ORACLE -- test infrastructure only.
+ *
+ * A plain, slow, FP64 CPU implementation of the discrete-velocity BGK
+ * primal and adjoint solvers and the wall shape sensitivity of Yuan & Wu,
+ * "Adjoint shape optimization from the continuum to free-molecular gas
+ * flows" (arXiv 2501.00923).  It exists to check the GPU library; only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no source with the GPU library.
+ *
+ * What each part follows (sections / equations of the paper):
+ *   conservative moments W = sum_k w_k Psi_k . f_k     Sec. 2.2, eq. (macint_reduce)
+ *   reduced Maxwellian g1, g2 = RT/2 g1               Sec. 2.2, eq. (maxwell_reduce)
+ *   relaxation time tau = mu/p, hard sphere           Sec. 2.1
+ *   Kn -> tau_inf                                     Sec. 2.1, eq. (kndefine)
+ *   far-field Dirichlet inflow                        Sec. 2.3, eq. (bc_drlt)
+ *   diffuse wall, F_rho_w and normalised g_w          Sec. 2.3 / 3.2, eqs. (formula_bgk_fdw), (barg)
+ *   objective J (drag m_J = v1, heat m_J = v^2/2)     Sec. 2.4, eq. (formula_opt); Sec. 3.2 eq. (numer_J)
+ *   primal finite-volume DVM balance                  Sec. 3.1, eq. (numerpr_gov)
+ *   adjoint equation, collision terms, wall BC        Sec. 2.5, eqs. (formula_adjointbgk),
+ *                                                     (adjoint_eqdefines), (adjoint_macdefines);
+ *                                                     Sec. 3.1, eq. (numerad_gov)
+ *   wall-element derivatives of J and B_w             Sec. 3.2, eqs. (sens_J_itf), (gaussgrad), (sens_B_itf)
+ *   element -> node transform                         Sec. 3.2, eq. (sens_nod)
+ *
+ * Readings where the paper is silent (the paper omits its solver scheme,
+ * Sec. 3.1):
+ *   - first-order upwind face values, Jacobi point-implicit iteration
+ *     f^{n+1} = (inflow + V g^n / tau^n) / (outflow + V / tau^n), every
+ *     per-cell quantity (W, tau, g, wall flux F) taken from f^n;
+ *   - nondimensional units rho_inf = 1, theta = RT with theta_inf = 1/2
+ *     (velocity unit sqrt(2 R T_inf)), gamma = 5/3 (three translational
+ *     degrees of freedom, as the reduction from 3-D velocity implies),
+ *     u_inf = Ma sqrt(gamma theta_inf) along x;
+ *   - tau_inf = (5 sqrt(pi) / 8) Kn l_ref with l_ref = 1;
+ *   - velocities with v.n = 0 count as incoming (Xi^-); every flux carries
+ *     the factor v.n so the choice is immaterial;
+ *   - the adjoint is the exact transpose of the discrete primal map under
+ *     the inner product sum_k w_k (.); with first-order upwinding it
+ *     coincides term by term with the upwind discretisation of the paper's
+ *     continuous adjoint equation and its wall condition;
+ *   - eq. (sens_B_itf) for dB/dn carries the element length A_l like the
+ *     other two lines; the inner sums run over a separate dummy index;
+ *   - the surface-element value of f on Xi^+ is the wall cell's value (first
+ *     order), on Xi^- it is F_l * gbar (the discrete diffuse condition).
+ *
+ * Pins (tests/test_oracle_*.py): velocity quadrature exactness and symmetry;
+ * Maxwellian moments against closed forms; dg/dW and dtau/dW by complex
+ * step; zero wall mass flux; a uniform Maxwellian at rest is stationary;
+ * free-molecular drag against the closed form; dot-product identity of the
+ * adjoint operator against a complex-step linearisation of the primal
+ * residual; adjoint dJ/dp against central finite differences for Kn, Ma
+ * and T_w; wall-element derivatives against finite differences of the
+ * discrete J and B_w expressions; node transform against finite
+ * differences of the element geometry; mirror symmetry of the
+ * sensitivities.  The end-to-end shape derivative itself is the paper's
+ * wall-only approximation (Sec. 2.5: volume-mesh motion is not
+ * differentiated); its agreement with finite differences is a
+ * discretisation-level trend, not an identity (parity unpinned beyond the
+ * element-level pins above).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+
+/* face order per cell: 0 = j-, 1 = i+, 2 = j+, 3 = i- ; neighbour code:
+ * >= 0 interior cell, -1 far field, -2 - l wall element l */
+
+typedef struct {
+    int topo, ni, nj, nwake, nc, nw;
+    int *nbr;          /* [nc][4] */
+    double *S;         /* [nc][4][2]  A n, outward of the cell */
+    double *vol;       /* [nc] */
+    double *cen;       /* [nc][2] */
+    int *wall_cell;    /* [nw] */
+    int *wall_face;    /* [nw] face slot of the wall cell */
+    double *wA, *wn, *wx;   /* [nw], [nw][2], [nw][2] */
+    double *wa, *wb;   /* element end nodes x_{l,1}, x_{l,2} [nw][2] */
+
+    int n1, n2, nv;
+    double *v;         /* [nv][2] */
+    double *w;         /* [nv] */
+
+    double Kn, Ma, Tw, inv_tau_inf, theta_inf, theta_w, u_inf;
+    int objective;
+    double *fd;        /* [nv][2] far-field Maxwellian */
+    double *gM;        /* [nv] g_M1(1, 0, T_w) */
+    double *D;         /* [nw] normalisation of eq. (barg) */
+    double *mJ;        /* [nv] */
+
+    double *f, *fn;    /* [nc][nv][2] */
+    double *W;         /* [nc][4] moments of f */
+    double *F;         /* [nw] wall incoming mass flux of f */
+    double *phi, *phin;
+    double *cellred;   /* [nc][2] residual partials */
+    int nthreads;
+} or_problem;
+
+/* ------------------------------------------------------------------ */
+/* velocity grids                                                      */
+/* ------------------------------------------------------------------ */
+
+/* 1-D rules on [-vmax, vmax]. kind 0: n midpoint cells; kind 1: n-point
+ * composite Newton-Cotes (Simpson on both sides of one centred 3/8 panel,
+ * n divisible by 4); kind 2: x = vmax sinh(b s)/sinh(b), s at the n cell
+ * midpoints of (-1, 1), weight = width of the mapped cell. Returns 0 or -1. */
+int or_vgrid_1d(int kind, int n, double vmax, double param, double *x, double *w)
+{
+    if (n < 2 || vmax <= 0) return -1;
+    if (kind == 0) {
+        double h = 2.0 * vmax / n;
+        for (int a = 0; a < n; a++) { x[a] = -vmax + (a + 0.5) * h; w[a] = h; }
+        return 0;
+    }
+    if (kind == 1) {
+        if (n % 4 != 0) return -1;
+        int m = n - 1;               /* intervals */
+        int ms = (m - 3) / 2;        /* Simpson intervals on each side (even) */
+        double h = 2.0 * vmax / m;
+        for (int a = 0; a < n; a++) { x[a] = -vmax + a * h; w[a] = 0.0; }
+        for (int a = 0; a < ms; a += 2) {            /* left Simpson panels */
+            w[a] += h / 3.0; w[a + 1] += 4.0 * h / 3.0; w[a + 2] += h / 3.0;
+        }
+        w[ms] += 3.0 * h / 8.0; w[ms + 1] += 9.0 * h / 8.0;
+        w[ms + 2] += 9.0 * h / 8.0; w[ms + 3] += 3.0 * h / 8.0;
+        for (int a = ms + 3; a < m; a += 2) {        /* right Simpson panels */
+            w[a] += h / 3.0; w[a + 1] += 4.0 * h / 3.0; w[a + 2] += h / 3.0;
+        }
+        return 0;
+    }
+    if (kind == 2) {
+        double b = param > 0 ? param : 2.0;
+        double sb = sinh(b);
+        for (int a = 0; a < n; a++) {
+            double s = -1.0 + (a + 0.5) * 2.0 / n;
+            double sl = -1.0 + a * 2.0 / n, sr = -1.0 + (a + 1) * 2.0 / n;
+            x[a] = vmax * sinh(b * s) / sb;
+            w[a] = vmax * (sinh(b * sr) - sinh(b * sl)) / sb;   /* mapped cell width */
+        }
+        return 0;
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Maxwellian and moments                                              */
+/* ------------------------------------------------------------------ */
+
+/* reduced Maxwellian, eq. (maxwell_reduce), theta = RT */
+static double maxwell1(double rho, double u1, double u2, double th, double v1, double v2)
+{
+    double c1 = v1 - u1, c2 = v2 - u2;
+    return rho / (2.0 * OR_PI * th) * exp(-(c1 * c1 + c2 * c2) / (2.0 * th));
+}
+
+/* primitive variables from W = (rho, rho u1, rho u2, rho E), Sec. 2.1 with
+ * 1/(gamma-1) = 3/2 */
+static void prim(const double *W, double *rho, double *u1, double *u2, double *th)
+{
+    *rho = W[0];
+    *u1 = W[1] / W[0];
+    *u2 = W[2] / W[0];
+    *th = (2.0 / 3.0) * (W[3] / W[0] - 0.5 * ((*u1) * (*u1) + (*u2) * (*u2)));
+}
+
+void or_maxwell(double rho, double u1, double u2, double th, int nv, const double *v, double *g)
+{
+    for (int k = 0; k < nv; k++) {
+        double g1 = maxwell1(rho, u1, u2, th, v[2 * k], v[2 * k + 1]);
+        g[2 * k] = g1;
+        g[2 * k + 1] = 0.5 * th * g1;
+    }
+}
+
+/* W = sum_k w_k Psi_k . f_k with Psi = [[1,0],[v,0],[v^2/2,1]] */
+void or_moments(int nv, const double *v, const double *w, const double *f, double *W)
+{
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int k = 0; k < nv; k++) {
+        double v1 = v[2 * k], v2 = v[2 * k + 1];
+        double f1 = f[2 * k], f2 = f[2 * k + 1];
+        s0 += w[k] * f1;
+        s1 += w[k] * v1 * f1;
+        s2 += w[k] * v2 * f1;
+        s3 += w[k] * (0.5 * (v1 * v1 + v2 * v2) * f1 + f2);
+    }
+    W[0] = s0; W[1] = s1; W[2] = s2; W[3] = s3;
+}
+
+/* 1/tau for a cell: tau = tau_inf * (rho_inf sqrt(theta_inf)) / (rho sqrt(theta)),
+ * rho_inf = 1, theta_inf = 1/2 */
+static double inv_tau_of(const or_problem *p, double rho, double th)
+{
+    return p->inv_tau_inf * rho * sqrt(2.0 * th);
+}
+
+/* d g_c / d W (2 x 4) for a cell state W at velocity v; chain rule through
+ * (rho, u1, u2, theta).  Also returns (1/tau) d tau / d W. */
+static void dg_dW(double rho, double u1, double u2, double th, double E,
+                  double v1, double v2, double dg[2][4], double dtau_over_tau[4])
+{
+    double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+    double c1 = v1 - u1, c2 = v2 - u2, cc = c1 * c1 + c2 * c2;
+    /* d g1 / d(rho, u1, u2, theta) */
+    double dP[4] = { g1 / rho, g1 * c1 / th, g1 * c2 / th, g1 * (cc / (2 * th * th) - 1.0 / th) };
+    /* d g2 / d(prim) = th/2 dg1 + g1/2 on theta */
+    double dP2[4] = { 0.5 * th * dP[0], 0.5 * th * dP[1], 0.5 * th * dP[2], 0.5 * th * dP[3] + 0.5 * g1 };
+    /* d prim / d W */
+    double J[4][4] = {
+        { 1.0, 0.0, 0.0, 0.0 },
+        { -u1 / rho, 1.0 / rho, 0.0, 0.0 },
+        { -u2 / rho, 0.0, 1.0 / rho, 0.0 },
+        { (2.0 / 3.0) * (u1 * u1 + u2 * u2 - E) / rho, -(2.0 / 3.0) * u1 / rho,
+          -(2.0 / 3.0) * u2 / rho, (2.0 / 3.0) / rho } };
+    for (int m = 0; m < 4; m++) {
+        double a = 0, b = 0;
+        for (int q = 0; q < 4; q++) { a += dP[q] * J[q][m]; b += dP2[q] * J[q][m]; }
+        dg[0][m] = a; dg[1][m] = b;
+        /* tau ~ 1 / (rho sqrt(theta)) */
+        dtau_over_tau[m] = -J[0][m] / rho - 0.5 * J[3][m] / th;
+    }
+}
+
+void or_dg_dW(double rho, double u1, double u2, double th, double v1, double v2,
+              double *dg /*[2][4]*/, double *dtt /*[4]*/)
+{
+    double E = 0.5 * (u1 * u1 + u2 * u2) + 1.5 * th;
+    double a[2][4], b[4];
+    dg_dW(rho, u1, u2, th, E, v1, v2, a, b);
+    memcpy(dg, a, sizeof(a));
+    memcpy(dtt, b, sizeof(b));
+}
+
+/* ------------------------------------------------------------------ */
+/* mesh                                                                */
+/* ------------------------------------------------------------------ */
+
+static int node_id(const or_problem *p, int i, int j) { return i + (p->ni + 1) * j; }
+
+static int build_mesh(or_problem *p, const double *nodes)
+{
+    int ni = p->ni, nj = p->nj;
+    p->nc = ni * nj;
+    p->nw = ni - 2 * p->nwake;
+    p->nbr = malloc(sizeof(int) * 4 * p->nc);
+    p->S = malloc(sizeof(double) * 8 * p->nc);
+    p->vol = malloc(sizeof(double) * p->nc);
+    p->cen = malloc(sizeof(double) * 2 * p->nc);
+    p->wall_cell = malloc(sizeof(int) * p->nw);
+    p->wall_face = malloc(sizeof(int) * p->nw);
+    p->wA = malloc(sizeof(double) * p->nw);
+    p->wn = malloc(sizeof(double) * 2 * p->nw);
+    p->wx = malloc(sizeof(double) * 2 * p->nw);
+    p->wa = malloc(sizeof(double) * 2 * p->nw);
+    p->wb = malloc(sizeof(double) * 2 * p->nw);
+    for (int j = 0; j < nj; j++) {
+        for (int i = 0; i < ni; i++) {
+            int c = i + ni * j;
+            /* counter-clockwise corners */
+            int cid[4] = { node_id(p, i, j), node_id(p, i + 1, j), node_id(p, i + 1, j + 1), node_id(p, i, j + 1) };
+            double X[4], Y[4];
+            for (int q = 0; q < 4; q++) { X[q] = nodes[2 * cid[q]]; Y[q] = nodes[2 * cid[q] + 1]; }
+            /* shoelace area and centroid */
+            double A2 = 0, cx = 0, cy = 0;
+            for (int q = 0; q < 4; q++) {
+                int r = (q + 1) % 4;
+                double cr = X[q] * Y[r] - X[r] * Y[q];
+                A2 += cr;
+                cx += (X[q] + X[r]) * cr;
+                cy += (Y[q] + Y[r]) * cr;
+            }
+            if (!(A2 > 0)) return -1;
+            p->vol[c] = 0.5 * A2;
+            p->cen[2 * c] = cx / (3.0 * A2);
+            p->cen[2 * c + 1] = cy / (3.0 * A2);
+            /* face q is the edge corner q -> corner q+1; outward normal
+             * (dy, -dx) for a counter-clockwise walk */
+            for (int q = 0; q < 4; q++) {
+                int r = (q + 1) % 4;
+                p->S[8 * c + 2 * q] = Y[r] - Y[q];
+                p->S[8 * c + 2 * q + 1] = -(X[r] - X[q]);
+            }
+            /* neighbours */
+            int *nb = p->nbr + 4 * c;
+            /* j- */
+            if (j > 0) nb[0] = i + ni * (j - 1);
+            else if (p->topo == 1 && (i < p->nwake || i >= ni - p->nwake)) nb[0] = (ni - 1 - i);
+            else nb[0] = -2 - (i - p->nwake);
+            /* i+ */
+            if (i < ni - 1) nb[1] = c + 1;
+            else nb[1] = (p->topo == 0) ? ni * j : -1;
+            /* j+ */
+            nb[2] = (j < nj - 1) ? c + ni : -1;
+            /* i- */
+            if (i > 0) nb[3] = c - 1;
+            else nb[3] = (p->topo == 0) ? (ni - 1) + ni * j : -1;
+        }
+    }
+    for (int l = 0; l < p->nw; l++) {
+        int i = l + p->nwake;
+        int c = i;                       /* j = 0 */
+        p->wall_cell[l] = c;
+        p->wall_face[l] = 0;
+        double Sx = p->S[8 * c], Sy = p->S[8 * c + 1];
+        double A = sqrt(Sx * Sx + Sy * Sy);
+        p->wA[l] = A;
+        p->wn[2 * l] = Sx / A;
+        p->wn[2 * l + 1] = Sy / A;
+        int na = node_id(p, i, 0), nb = node_id(p, i + 1, 0);
+        p->wa[2 * l] = nodes[2 * na]; p->wa[2 * l + 1] = nodes[2 * na + 1];
+        p->wb[2 * l] = nodes[2 * nb]; p->wb[2 * l + 1] = nodes[2 * nb + 1];
+        p->wx[2 * l] = 0.5 * (p->wa[2 * l] + p->wb[2 * l]);
+        p->wx[2 * l + 1] = 0.5 * (p->wa[2 * l + 1] + p->wb[2 * l + 1]);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* setup                                                               */
+/* ------------------------------------------------------------------ */
+
+static void setup_flow(or_problem *p)
+{
+    const int nv = p->nv;
+    p->theta_inf = 0.5;
+    p->theta_w = 0.5 * p->Tw;             /* T_w in units of T_inf */
+    p->u_inf = p->Ma * sqrt((5.0 / 3.0) * p->theta_inf);
+    /* eq. (kndefine) with theta_inf = 1/2, l_ref = 1 */
+    double tau_inf = 5.0 * sqrt(OR_PI) / 8.0 * p->Kn;
+    p->inv_tau_inf = isinf(p->Kn) ? 0.0 : 1.0 / tau_inf;
+    for (int k = 0; k < nv; k++) {
+        double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+        double g1 = maxwell1(1.0, p->u_inf, 0.0, p->theta_inf, v1, v2);
+        p->fd[2 * k] = g1;
+        p->fd[2 * k + 1] = 0.5 * p->theta_inf * g1;
+        p->gM[k] = maxwell1(1.0, 0.0, 0.0, p->theta_w, v1, v2);
+        p->mJ[k] = (p->objective == 0) ? v1 : 0.5 * (v1 * v1 + v2 * v2);
+    }
+    for (int l = 0; l < p->nw; l++) {
+        double n1 = p->wn[2 * l], n2 = p->wn[2 * l + 1], d = 0;
+        for (int k = 0; k < nv; k++) {
+            double vn = p->v[2 * k] * n1 + p->v[2 * k + 1] * n2;
+            if (vn <= 0) d -= p->w[k] * vn * p->gM[k];
+        }
+        p->D[l] = d;
+    }
+}
+
+or_problem *or_create(int topo, int ni, int nj, int nwake, const double *nodes,
+                      int vkind, int n1, int n2, double vmax, double vparam,
+                      double Kn, double Ma, double Tw, int objective, int nthreads)
+{
+    if (ni < 2 || nj < 1 || (topo != 0 && topo != 1)) return NULL;
+    if (topo == 0 && nwake != 0) return NULL;
+    if (topo == 1 && (nwake < 1 || 2 * nwake >= ni)) return NULL;
+    or_problem *p = calloc(1, sizeof(or_problem));
+    p->topo = topo; p->ni = ni; p->nj = nj; p->nwake = nwake;
+    p->nthreads = nthreads > 0 ? nthreads : 1;
+    if (build_mesh(p, nodes) != 0) { free(p); return NULL; }
+    p->n1 = n1; p->n2 = n2; p->nv = n1 * n2;
+    double *x1 = malloc(sizeof(double) * n1), *w1 = malloc(sizeof(double) * n1);
+    double *x2 = malloc(sizeof(double) * n2), *w2 = malloc(sizeof(double) * n2);
+    if (or_vgrid_1d(vkind, n1, vmax, vparam, x1, w1) || or_vgrid_1d(vkind, n2, vmax, vparam, x2, w2)) {
+        free(x1); free(w1); free(x2); free(w2); free(p); return NULL;
+    }
+    p->v = malloc(sizeof(double) * 2 * p->nv);
+    p->w = malloc(sizeof(double) * p->nv);
+    for (int b = 0; b < n2; b++)
+        for (int a = 0; a < n1; a++) {
+            int k = a + n1 * b;
+            p->v[2 * k] = x1[a]; p->v[2 * k + 1] = x2[b];
+            p->w[k] = w1[a] * w2[b];
+        }
+    free(x1); free(w1); free(x2); free(w2);
+    p->Kn = Kn; p->Ma = Ma; p->Tw = Tw; p->objective = objective;
+    p->fd = malloc(sizeof(double) * 2 * p->nv);
+    p->gM = malloc(sizeof(double) * p->nv);
+    p->mJ = malloc(sizeof(double) * p->nv);
+    p->D = malloc(sizeof(double) * p->nw);
+    setup_flow(p);
+    size_t n = (size_t)p->nc * p->nv * 2;
+    p->f = malloc(sizeof(double) * n);
+    p->fn = malloc(sizeof(double) * n);
+    p->phi = calloc(n, sizeof(double));
+    p->phin = calloc(n, sizeof(double));
+    p->W = malloc(sizeof(double) * 4 * p->nc);
+    p->F = malloc(sizeof(double) * p->nw);
+    p->cellred = malloc(sizeof(double) * 2 * p->nc);
+    if (!p->f || !p->fn || !p->phi || !p->phin) return NULL;
+    return p;
+}
+
+void or_destroy(or_problem *p)
+{
+    if (!p) return;
+    free(p->nbr); free(p->S); free(p->vol); free(p->cen); free(p->wall_cell); free(p->wall_face);
+    free(p->wA); free(p->wn); free(p->wx); free(p->wa); free(p->wb);
+    free(p->v); free(p->w); free(p->fd); free(p->gM); free(p->D); free(p->mJ);
+    free(p->f); free(p->fn); free(p->W); free(p->F); free(p->phi); free(p->phin); free(p->cellred);
+    free(p);
+}
+
+void or_sizes(const or_problem *p, int64_t *out)
+{
+    out[0] = p->nc; out[1] = p->nw; out[2] = p->nv; out[3] = p->n1; out[4] = p->n2;
+    out[5] = p->ni; out[6] = p->nj; out[7] = p->nwake;
+}
+
+void or_export_mesh(const or_problem *p, int32_t *nbr, int32_t *wall_cell, double *S, double *vol,
+                    double *wA, double *wn, double *wx, double *cen)
+{
+    for (int c = 0; c < 4 * p->nc; c++) nbr[c] = p->nbr[c];
+    for (int l = 0; l < p->nw; l++) wall_cell[l] = p->wall_cell[l];
+    memcpy(S, p->S, sizeof(double) * 8 * p->nc);
+    memcpy(vol, p->vol, sizeof(double) * p->nc);
+    memcpy(wA, p->wA, sizeof(double) * p->nw);
+    memcpy(wn, p->wn, sizeof(double) * 2 * p->nw);
+    memcpy(wx, p->wx, sizeof(double) * 2 * p->nw);
+    memcpy(cen, p->cen, sizeof(double) * 2 * p->nc);
+}
+
+void or_export_vgrid(const or_problem *p, double *v, double *w)
+{
+    memcpy(v, p->v, sizeof(double) * 2 * p->nv);
+    memcpy(w, p->w, sizeof(double) * p->nv);
+}
+
+void or_export_flow(const or_problem *p, double *out /* tau_inf_inv, u_inf, theta_w, fd..., gM..., D... */)
+{
+    out[0] = p->inv_tau_inf; out[1] = p->u_inf; out[2] = p->theta_w;
+}
+
+void or_export_wall(const or_problem *p, double *D, double *F)
+{
+    memcpy(D, p->D, sizeof(double) * p->nw);
+    memcpy(F, p->F, sizeof(double) * p->nw);
+}
+
+/* ------------------------------------------------------------------ */
+/* primal                                                              */
+/* ------------------------------------------------------------------ */
+
+/* W and wall flux F_l = sum_{v.n > 0} w (v.n) f1 (eq. formula_bgk_fdw,
+ * discrete form of Sec. 3.2) for the current f */
+static void update_W_F(or_problem *p, const double *f)
+{
+    const int nv = p->nv;
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+    for (int c = 0; c < p->nc; c++)
+        or_moments(nv, p->v, p->w, f + (size_t)c * nv * 2, p->W + 4 * c);
+    for (int l = 0; l < p->nw; l++) {
+        const double *fc = f + (size_t)p->wall_cell[l] * nv * 2;
+        double n1 = p->wn[2 * l], n2 = p->wn[2 * l + 1], s = 0;
+        for (int k = 0; k < nv; k++) {
+            double vn = p->v[2 * k] * n1 + p->v[2 * k + 1] * n2;
+            if (vn > 0) s += p->w[k] * vn * fc[2 * k];
+        }
+        p->F[l] = s;
+    }
+}
+
+void or_primal_init(or_problem *p)
+{
+    size_t nv = p->nv;
+    for (int c = 0; c < p->nc; c++)
+        memcpy(p->f + (size_t)c * nv * 2, p->fd, sizeof(double) * 2 * nv);
+    update_W_F(p, p->f);
+}
+
+/* value of f carried into cell c through face q at velocity k (s <= 0) */
+static void inflow_value(const or_problem *p, const double *f, int c, int q, int k, double *o1, double *o2)
+{
+    int nb = p->nbr[4 * c + q];
+    if (nb >= 0) {
+        const double *fj = f + ((size_t)nb * p->nv + k) * 2;
+        *o1 = fj[0]; *o2 = fj[1];
+    } else if (nb == -1) {
+        *o1 = p->fd[2 * k]; *o2 = p->fd[2 * k + 1];
+    } else {
+        int l = -2 - nb;
+        double gb1 = p->gM[k] / p->D[l];           /* eq. (barg) */
+        *o1 = p->F[l] * gb1;
+        *o2 = p->F[l] * 0.5 * p->theta_w * gb1;
+    }
+}
+
+/* One Jacobi sweep of eq. (numerpr_gov), every cell from f^n.  Returns the
+ * relative change of W in the 2-norm. */
+double or_primal_iterate(or_problem *p, int niter)
+{
+    const int nv = p->nv;
+    double r = 0;
+    for (int it = 0; it < niter; it++) {
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+        for (int c = 0; c < p->nc; c++) {
+            double rho, u1, u2, th;
+            prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+            double itau = inv_tau_of(p, rho, th);
+            double V = p->vol[c];
+            for (int k = 0; k < nv; k++) {
+                double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+                double in1 = 0, in2 = 0, out = 0;
+                for (int q = 0; q < 4; q++) {
+                    double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                    if (s > 0) out += s;
+                    else {
+                        double a1, a2;
+                        inflow_value(p, p->f, c, q, k, &a1, &a2);
+                        in1 -= s * a1; in2 -= s * a2;
+                    }
+                }
+                double g1 = maxwell1(rho, u1, u2, th, v1, v2), g2 = 0.5 * th * g1;
+                double den = out + V * itau;
+                double *fo = p->fn + ((size_t)c * nv + k) * 2;
+                fo[0] = (in1 + V * itau * g1) / den;
+                fo[1] = (in2 + V * itau * g2) / den;
+            }
+        }
+        /* residual on W */
+        double *Wold = malloc(sizeof(double) * 4 * p->nc);
+        memcpy(Wold, p->W, sizeof(double) * 4 * p->nc);
+        double *t = p->f; p->f = p->fn; p->fn = t;
+        update_W_F(p, p->f);
+        double num = 0, den = 0;
+        for (int c = 0; c < 4 * p->nc; c++) {
+            double d = p->W[c] - Wold[c];
+            num += d * d;
+            den += Wold[c] * Wold[c];
+        }
+        free(Wold);
+        r = sqrt(num / den);
+    }
+    return r;
+}
+
+void or_get_f(const or_problem *p, double *out) { memcpy(out, p->f, sizeof(double) * (size_t)p->nc * p->nv * 2); }
+void or_set_f(or_problem *p, const double *in) { memcpy(p->f, in, sizeof(double) * (size_t)p->nc * p->nv * 2); update_W_F(p, p->f); }
+void or_get_W(const or_problem *p, double *out) { memcpy(out, p->W, sizeof(double) * 4 * p->nc); }
+void or_get_phi(const or_problem *p, double *out) { memcpy(out, p->phi, sizeof(double) * (size_t)p->nc * p->nv * 2); }
+void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); }
+
+/* wall value f1_{l,k}: cell value on Xi^+, F_l gbar1 on Xi^- (Sec. 3.2) */
+static double wall_f1(const or_problem *p, const double *f, int l, int k)
+{
+    double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
+    if (vn > 0) return f[((size_t)p->wall_cell[l] * p->nv + k) * 2];
+    return p->F[l] * p->gM[k] / p->D[l];
+}
+
+/* J = sum_l A_l sum_k w m_J (v.n) f1_{l,k}, eq. (numer_J); per element into Jl */
+double or_objective(const or_problem *p, double *Jl)
+{
+    double J = 0;
+    for (int l = 0; l < p->nw; l++) {
+        double s = 0;
+        for (int k = 0; k < p->nv; k++) {
+            double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
+            s += p->w[k] * p->mJ[k] * vn * wall_f1(p, p->f, l, k);
+        }
+        if (Jl) Jl[l] = p->wA[l] * s;
+        J += p->wA[l] * s;
+    }
+    return J;
+}
+
+double or_cd_scale(const or_problem *p)
+{
+    /* C_d = J / (rho_inf |u_inf|^2 / 2 * L); L = chord (1) or circle diameter (2) */
+    double L = (p->topo == 0) ? 2.0 : 1.0;
+    return 0.5 * p->u_inf * p->u_inf * L;
+}
+
+/* discrete residual R(f) of eq. (numerpr_gov), moved to one side:
+ * R = sum_q (v.S_q) f_q + V (f - g(W(f))) / tau(W(f)); W and F of the
+ * argument f are used.  out [nc][nv][2]. */
+void or_primal_residual(or_problem *p, const double *f, double *out)
+{
+    const int nv = p->nv;
+    double *Wsave = malloc(sizeof(double) * 4 * p->nc), *Fsave = malloc(sizeof(double) * p->nw);
+    memcpy(Wsave, p->W, sizeof(double) * 4 * p->nc);
+    memcpy(Fsave, p->F, sizeof(double) * p->nw);
+    update_W_F(p, f);
+    for (int c = 0; c < p->nc; c++) {
+        double rho, u1, u2, th;
+        prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+        double itau = inv_tau_of(p, rho, th), V = p->vol[c];
+        for (int k = 0; k < nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+            const double *fc = f + ((size_t)c * nv + k) * 2;
+            double r1 = 0, r2 = 0;
+            for (int q = 0; q < 4; q++) {
+                double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                if (s > 0) { r1 += s * fc[0]; r2 += s * fc[1]; }
+                else { double a1, a2; inflow_value(p, f, c, q, k, &a1, &a2); r1 += s * a1; r2 += s * a2; }
+            }
+            double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+            out[((size_t)c * nv + k) * 2] = r1 + V * itau * (fc[0] - g1);
+            out[((size_t)c * nv + k) * 2 + 1] = r2 + V * itau * (fc[1] - 0.5 * th * g1);
+        }
+    }
+    memcpy(p->W, Wsave, sizeof(double) * 4 * p->nc);
+    memcpy(p->F, Fsave, sizeof(double) * p->nw);
+    free(Wsave); free(Fsave);
+}
+
+/* ------------------------------------------------------------------ */
+/* complex-step twin of the residual and of J (pins only)              */
+/* ------------------------------------------------------------------ */
+
+/* Evaluates R and J with f -> f + i h u and one parameter shifted by i h
+ * (which: 0 none, 1 Kn, 2 Ma, 3 Tw); returns Im(.)/h in dR (may be NULL)
+ * and *dJ.  Written independently of the real-valued solver above. */
+void or_complex_step(or_problem *p, const double *u, double h, int which, double *dR, double *dJ)
+{
+    const int nv = p->nv, nc = p->nc, nw = p->nw;
+    double complex Kn = p->Kn + (which == 1 ? I * h : 0);
+    double complex Ma = p->Ma + (which == 2 ? I * h : 0);
+    double complex Tw = p->Tw + (which == 3 ? I * h : 0);
+    double complex thw = 0.5 * Tw, thinf = 0.5;
+    double complex uinf = Ma * csqrt((5.0 / 3.0) * thinf);
+    double complex itinf = isinf(p->Kn) ? 0 : 1.0 / (5.0 * sqrt(OR_PI) / 8.0 * Kn);
+    double complex *fz = malloc(sizeof(double complex) * (size_t)nc * nv * 2);
+    for (size_t q = 0; q < (size_t)nc * nv * 2; q++) fz[q] = p->f[q] + (u ? I * h * u[q] : 0);
+    double complex *fdz = malloc(sizeof(double complex) * nv * 2), *gMz = malloc(sizeof(double complex) * nv);
+    for (int k = 0; k < nv; k++) {
+        double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+        double complex c1 = v1 - uinf;
+        double complex g = 1.0 / (2 * OR_PI * thinf) * cexp(-(c1 * c1 + v2 * v2) / (2 * thinf));
+        fdz[2 * k] = g; fdz[2 * k + 1] = 0.5 * thinf * g;
+        gMz[k] = 1.0 / (2 * OR_PI * thw) * cexp(-(v1 * v1 + v2 * v2) / (2 * thw));
+    }
+    double complex *Dz = malloc(sizeof(double complex) * nw), *Fz = malloc(sizeof(double complex) * nw);
+    for (int l = 0; l < nw; l++) {
+        const double complex *fc = fz + (size_t)p->wall_cell[l] * nv * 2;
+        double complex d = 0, F = 0;
+        for (int k = 0; k < nv; k++) {
+            double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
+            if (vn > 0) F += p->w[k] * vn * fc[2 * k];
+            else d -= p->w[k] * vn * gMz[k];
+        }
+        Dz[l] = d; Fz[l] = F;
+    }
+    /* J */
+    double complex J = 0;
+    for (int l = 0; l < nw; l++) {
+        const double complex *fc = fz + (size_t)p->wall_cell[l] * nv * 2;
+        for (int k = 0; k < nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+            double vn = v1 * p->wn[2 * l] + v2 * p->wn[2 * l + 1];
+            double complex f1 = vn > 0 ? fc[2 * k] : Fz[l] * gMz[k] / Dz[l];
+            double mj = p->objective == 0 ? v1 : 0.5 * (v1 * v1 + v2 * v2);
+            J += p->wA[l] * p->w[k] * mj * vn * f1;
+        }
+    }
+    *dJ = cimag(J) / h;
+    if (dR) {
+        for (int c = 0; c < nc; c++) {
+            const double complex *fc = fz + (size_t)c * nv * 2;
+            double complex W0 = 0, W1 = 0, W2 = 0, W3 = 0;
+            for (int k = 0; k < nv; k++) {
+                double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+                W0 += p->w[k] * fc[2 * k];
+                W1 += p->w[k] * v1 * fc[2 * k];
+                W2 += p->w[k] * v2 * fc[2 * k];
+                W3 += p->w[k] * (0.5 * (v1 * v1 + v2 * v2) * fc[2 * k] + fc[2 * k + 1]);
+            }
+            double complex rho = W0, u1 = W1 / W0, u2 = W2 / W0;
+            double complex th = (2.0 / 3.0) * (W3 / W0 - 0.5 * (u1 * u1 + u2 * u2));
+            double complex itau = itinf * rho * csqrt(2.0 * th);
+            double V = p->vol[c];
+            for (int k = 0; k < nv; k++) {
+                double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+                double complex r1 = 0, r2 = 0;
+                for (int q = 0; q < 4; q++) {
+                    double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                    double complex a1, a2;
+                    if (s > 0) { a1 = fc[2 * k]; a2 = fc[2 * k + 1]; }
+                    else {
+                        int nb = p->nbr[4 * c + q];
+                        if (nb >= 0) { a1 = fz[((size_t)nb * nv + k) * 2]; a2 = fz[((size_t)nb * nv + k) * 2 + 1]; }
+                        else if (nb == -1) { a1 = fdz[2 * k]; a2 = fdz[2 * k + 1]; }
+                        else { int l = -2 - nb; a1 = Fz[l] * gMz[k] / Dz[l]; a2 = 0.5 * thw * a1; }
+                    }
+                    r1 += s * a1; r2 += s * a2;
+                }
+                double complex c1 = v1 - u1, c2 = v2 - u2;
+                double complex g1 = rho / (2 * OR_PI * th) * cexp(-(c1 * c1 + c2 * c2) / (2 * th));
+                r1 += V * itau * (fc[2 * k] - g1);
+                r2 += V * itau * (fc[2 * k + 1] - 0.5 * th * g1);
+                dR[((size_t)c * nv + k) * 2] = cimag(r1) / h;
+                dR[((size_t)c * nv + k) * 2 + 1] = cimag(r2) / h;
+            }
+        }
+    }
+    free(fz); free(fdz); free(gMz); free(Dz); free(Fz);
+}
+
+/* ------------------------------------------------------------------ */
+/* adjoint                                                             */
+/* ------------------------------------------------------------------ */
+
+/* per-cell adjoint moments of eq. (adjoint_macdefines):
+ * What = sum_k w phi . dg/dW (4), rho_tau = sum_k w phi . (g - f) / tau;
+ * and per wall element the multiplier of eq. (formula_adjointbgk),
+ * Phi_l = int_{Xi^-} varphi_w . dg_w/dF = -sum_{v.n<=0} w (v.n)[(phi1 + m_J) gbar1 + phi2 gbar2]. */
+static void adjoint_moments(or_problem *p, const double *phi, double *What, double *rtau, double *Phi)
+{
+    const int nv = p->nv;
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+    for (int c = 0; c < p->nc; c++) {
+        double rho, u1, u2, th;
+        const double *W = p->W + 4 * c;
+        prim(W, &rho, &u1, &u2, &th);
+        double E = W[3] / W[0];
+        double itau = inv_tau_of(p, rho, th);
+        double acc[4] = { 0, 0, 0, 0 }, rt = 0;
+        for (int k = 0; k < nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+            double dg[2][4], dtt[4];
+            dg_dW(rho, u1, u2, th, E, v1, v2, dg, dtt);
+            const double *ph = phi + ((size_t)c * nv + k) * 2;
+            const double *fc = p->f + ((size_t)c * nv + k) * 2;
+            for (int m = 0; m < 4; m++) acc[m] += p->w[k] * (ph[0] * dg[0][m] + ph[1] * dg[1][m]);
+            double g1 = maxwell1(rho, u1, u2, th, v1, v2), g2 = 0.5 * th * g1;
+            rt += p->w[k] * (ph[0] * (g1 - fc[0]) + ph[1] * (g2 - fc[1])) * itau;
+        }
+        for (int m = 0; m < 4; m++) What[4 * c + m] = acc[m];
+        rtau[c] = rt;
+    }
+    for (int l = 0; l < p->nw; l++) {
+        const double *ph = phi + (size_t)p->wall_cell[l] * nv * 2;
+        double s = 0;
+        for (int k = 0; k < nv; k++) {
+            double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
+            if (vn <= 0) {
+                double gb1 = p->gM[k] / p->D[l], gb2 = 0.5 * p->theta_w * gb1;
+                s -= p->w[k] * vn * ((ph[2 * k] + p->mJ[k]) * gb1 + ph[2 * k + 1] * gb2);
+            }
+        }
+        Phi[l] = s;
+    }
+}
+
+/* source terms phi_eq / tau + phi_tau of eq. (numerad_gov) at cell c,
+ * velocity k (eq. adjoint_eqdefines) */
+static void adjoint_source(const or_problem *p, int c, int k, const double *What, const double *rtau,
+                           double *s1, double *s2, double *itau_out)
+{
+    double rho, u1, u2, th;
+    const double *W = p->W + 4 * c;
+    prim(W, &rho, &u1, &u2, &th);
+    double E = W[3] / W[0];
+    double itau = inv_tau_of(p, rho, th);
+    double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+    double dg[2][4], dtt[4];
+    dg_dW(rho, u1, u2, th, E, v1, v2, dg, dtt);
+    const double *Wh = What + 4 * c;
+    double psi1[4] = { 1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2) };  /* first column of Psi */
+    double eq1 = 0, tt1 = 0;
+    for (int m = 0; m < 4; m++) { eq1 += Wh[m] * psi1[m]; tt1 += dtt[m] * psi1[m]; }
+    double eq2 = Wh[3], tt2 = dtt[3];               /* second column (0,0,0,1) */
+    /* phi_tau = -rho_tau (1/tau) dtau/dW . Psi, with dtt = (1/tau) dtau/dW */
+    *s1 = eq1 * itau - rtau[c] * tt1;
+    *s2 = eq2 * itau - rtau[c] * tt2;
+    *itau_out = itau;
+}
+
+/* adjoint value carried into cell c from the downstream side of face q
+ * (s > 0): neighbour, far field 0, wall (Phi_l - m_J, 0) */
+static void outflow_adjoint(const or_problem *p, const double *phi, const double *Phi, int c, int q, int k,
+                            int with_source, double *o1, double *o2)
+{
+    int nb = p->nbr[4 * c + q];
+    if (nb >= 0) { const double *pj = phi + ((size_t)nb * p->nv + k) * 2; *o1 = pj[0]; *o2 = pj[1]; }
+    else if (nb == -1) { *o1 = 0; *o2 = 0; }
+    else { int l = -2 - nb; *o1 = Phi[l] - (with_source ? p->mJ[k] : 0.0); *o2 = 0; }
+}
+
+void or_adjoint_init(or_problem *p)
+{
+    memset(p->phi, 0, sizeof(double) * (size_t)p->nc * p->nv * 2);
+}
+
+/* Jacobi sweeps of eq. (numerad_gov) with the converged f frozen.  Returns
+ * the relative weighted change of phi in the last sweep. */
+double or_adjoint_iterate(or_problem *p, int niter)
+{
+    const int nv = p->nv;
+    double *What = malloc(sizeof(double) * 4 * p->nc), *rtau = malloc(sizeof(double) * p->nc);
+    double *Phi = malloc(sizeof(double) * p->nw);
+    double r = 0;
+    for (int it = 0; it < niter; it++) {
+        adjoint_moments(p, p->phi, What, rtau, Phi);
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+        for (int c = 0; c < p->nc; c++) {
+            double V = p->vol[c];
+            double dn = 0, dd = 0;
+            for (int k = 0; k < nv; k++) {
+                double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+                double a1 = 0, a2 = 0, out = 0;
+                for (int q = 0; q < 4; q++) {
+                    double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                    if (s > 0) {
+                        double b1, b2;
+                        outflow_adjoint(p, p->phi, Phi, c, q, k, 1, &b1, &b2);
+                        a1 += s * b1; a2 += s * b2; out += s;
+                    }
+                }
+                double s1, s2, itau;
+                adjoint_source(p, c, k, What, rtau, &s1, &s2, &itau);
+                double den = out + V * itau;
+                double *po = p->phin + ((size_t)c * nv + k) * 2;
+                const double *pi = p->phi + ((size_t)c * nv + k) * 2;
+                po[0] = (a1 + V * s1) / den;
+                po[1] = (a2 + V * s2) / den;
+                double d0 = po[0] - pi[0], d1 = po[1] - pi[1];
+                dn += p->w[k] * (d0 * d0 + d1 * d1);
+                dd += p->w[k] * (po[0] * po[0] + po[1] * po[1]);
+            }
+            p->cellred[2 * c] = dn;
+            p->cellred[2 * c + 1] = dd;
+        }
+        double num = 0, den = 0;
+        for (int c = 0; c < p->nc; c++) { num += p->cellred[2 * c]; den += p->cellred[2 * c + 1]; }
+        r = den > 0 ? sqrt(num / den) : 0.0;
+        double *t = p->phi; p->phi = p->phin; p->phin = t;
+    }
+    free(What); free(rtau); free(Phi);
+    return r;
+}
+
+/* The adjoint operator A*(phi) = sum_{s>0} s (phi - phi_down) + V (phi - phi_eq)/tau - V phi_tau
+ * (with_source = 1 includes the objective's m_J terms at the wall; 0 gives
+ * the homogeneous operator, the transpose of dR/df under sum_k w_k). */
+void or_adjoint_operator(or_problem *p, const double *phi, int with_source, double *out)
+{
+    const int nv = p->nv;
+    double *What = malloc(sizeof(double) * 4 * p->nc), *rtau = malloc(sizeof(double) * p->nc);
+    double *Phi = malloc(sizeof(double) * p->nw);
+    double *mJsave = NULL;
+    if (!with_source) { mJsave = p->mJ; p->mJ = calloc(nv, sizeof(double)); }
+    adjoint_moments(p, phi, What, rtau, Phi);
+    for (int c = 0; c < p->nc; c++) {
+        double V = p->vol[c];
+        for (int k = 0; k < nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+            const double *pi = phi + ((size_t)c * nv + k) * 2;
+            double r1 = 0, r2 = 0;
+            for (int q = 0; q < 4; q++) {
+                double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                if (s > 0) {
+                    double b1, b2;
+                    outflow_adjoint(p, phi, Phi, c, q, k, 1, &b1, &b2);
+                    r1 += s * (pi[0] - b1); r2 += s * (pi[1] - b2);
+                }
+            }
+            double s1, s2, itau;
+            adjoint_source(p, c, k, What, rtau, &s1, &s2, &itau);
+            out[((size_t)c * nv + k) * 2] = r1 + V * (pi[0] * itau - s1);
+            out[((size_t)c * nv + k) * 2 + 1] = r2 + V * (pi[1] * itau - s2);
+        }
+    }
+    if (!with_source) { free(p->mJ); p->mJ = mJsave; }
+    free(What); free(rtau); free(Phi);
+}
+
+/* dJ/dp = dJ/dp|_f + sum_{i,k,c} w_k phi . dR/dp (Lagrangian of Sec. 2.5 in
+ * discrete form) for p = Kn (1), Ma (2), T_w (3); the partials come from
+ * the complex-step twin. */
+double or_adjoint_dJdp(or_problem *p, int which)
+{
+    const int nv = p->nv;
+    size_t n = (size_t)p->nc * nv * 2;
+    double *dR = malloc(sizeof(double) * n), dJ;
+    or_complex_step(p, NULL, 1e-30, which, dR, &dJ);
+    double s = dJ;
+    for (int c = 0; c < p->nc; c++)
+        for (int k = 0; k < nv; k++) {
+            size_t q = ((size_t)c * nv + k) * 2;
+            s += p->w[k] * (p->phi[q] * dR[q] + p->phi[q + 1] * dR[q + 1]);
+        }
+    free(dR);
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* wall sensitivity                                                    */
+/* ------------------------------------------------------------------ */
+
+/* Green-Gauss gradient of eq. (gaussgrad) at cell c, velocity k, with the
+ * first-order upwind face values of the primal scheme */
+static void gauss_grad(const or_problem *p, int c, int k, double g[2][2])
+{
+    double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+    const double *fc = p->f + ((size_t)c * p->nv + k) * 2;
+    double V = p->vol[c];
+    g[0][0] = g[0][1] = g[1][0] = g[1][1] = 0;
+    for (int q = 0; q < 4; q++) {
+        double Sx = p->S[8 * c + 2 * q], Sy = p->S[8 * c + 2 * q + 1];
+        double s = v1 * Sx + v2 * Sy, a1, a2;
+        if (s > 0) { a1 = fc[0]; a2 = fc[1]; }
+        else inflow_value(p, p->f, c, q, k, &a1, &a2);
+        g[0][0] += a1 * Sx; g[0][1] += a1 * Sy;
+        g[1][0] += a2 * Sx; g[1][1] += a2 * Sy;
+    }
+    for (int a = 0; a < 2; a++) for (int b = 0; b < 2; b++) g[a][b] /= V;
+}
+
+/* Element derivatives dL/dA_l, dL/dx_l, dL/dn_l (eqs. sens_J_itf, sens_B_itf)
+ * and their transform to the wall nodes (eq. sens_nod).  Wall node m is
+ * x_{l,1} of element l = m and x_{l,2} of element m - 1 (closed loop). */
+void or_wall_sensitivity(or_problem *p, double *SA, double *Sx, double *Sn, double *dJdnodes)
+{
+    const int nv = p->nv, nw = p->nw;
+    for (int l = 0; l < nw; l++) {
+        int c = p->wall_cell[l];
+        double n1 = p->wn[2 * l], n2 = p->wn[2 * l + 1], A = p->wA[l];
+        const double *ph = p->phi + (size_t)c * nv * 2;
+        double sa = 0, jx[2] = { 0, 0 }, bx[2] = { 0, 0 }, G[2] = { 0, 0 }, M[2] = { 0, 0 };
+        double Phi = 0, jn[2] = { 0, 0 };
+        for (int k = 0; k < nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], vn = v1 * n1 + v2 * n2, wk = p->w[k];
+            double f1 = wall_f1(p, p->f, l, k);
+            double gr[2][2];
+            gauss_grad(p, c, k, gr);
+            sa += wk * p->mJ[k] * vn * f1;
+            jx[0] += wk * p->mJ[k] * vn * gr[0][0];
+            jx[1] += wk * p->mJ[k] * vn * gr[0][1];
+            jn[0] += wk * p->mJ[k] * v1 * f1;
+            jn[1] += wk * p->mJ[k] * v2 * f1;
+            M[0] += wk * v1 * f1;
+            M[1] += wk * v2 * f1;
+            if (vn > 0) {
+                G[0] += wk * vn * gr[0][0];
+                G[1] += wk * vn * gr[0][1];
+            } else {
+                double pw1 = -vn * (ph[2 * k] + p->mJ[k]), pw2 = -vn * ph[2 * k + 1];
+                double gb1 = p->gM[k] / p->D[l], gb2 = 0.5 * p->theta_w * gb1;
+                bx[0] += wk * (pw1 * gr[0][0] + pw2 * gr[1][0]);
+                bx[1] += wk * (pw1 * gr[0][1] + pw2 * gr[1][1]);
+                Phi += wk * (pw1 * gb1 + pw2 * gb2);
+            }
+        }
+        SA[l] = sa;
+        Sx[2 * l] = A * (jx[0] + bx[0] - Phi * G[0]);
+        Sx[2 * l + 1] = A * (jx[1] + bx[1] - Phi * G[1]);
+        Sn[2 * l] = A * (jn[0] - Phi * M[0]);
+        Sn[2 * l + 1] = A * (jn[1] - Phi * M[1]);
+    }
+    if (!dJdnodes) return;
+    for (int m = 0; m < 2 * nw; m++) dJdnodes[m] = 0;
+    for (int l = 0; l < nw; l++) {
+        double ax = p->wa[2 * l], ay = p->wa[2 * l + 1], bxn = p->wb[2 * l], byn = p->wb[2 * l + 1];
+        double A = p->wA[l], n1 = p->wn[2 * l], n2 = p->wn[2 * l + 1];
+        double dAa[2] = { (ax - bxn) / A, (ay - byn) / A };
+        double cross = (ax - bxn) * n2 - (ay - byn) * n1;
+        double sg = cross > 0 ? 1.0 : -1.0;
+        /* dn/da: rows = components of n, columns = coordinates of a */
+        double Na[2][2] = { { -n1 * n2 * sg / A, -n2 * n2 * sg / A }, { n1 * n1 * sg / A, n1 * n2 * sg / A } };
+        double ga[2], gb[2];
+        for (int d = 0; d < 2; d++) {
+            double tn = Sn[2 * l] * Na[0][d] + Sn[2 * l + 1] * Na[1][d];
+            ga[d] = SA[l] * dAa[d] + 0.5 * Sx[2 * l + d] + tn;
+            gb[d] = -SA[l] * dAa[d] + 0.5 * Sx[2 * l + d] - tn;
+        }
+        int ma = l, mb = (l + 1) % nw;
+        dJdnodes[2 * ma] += ga[0]; dJdnodes[2 * ma + 1] += ga[1];
+        dJdnodes[2 * mb] += gb[0]; dJdnodes[2 * mb + 1] += gb[1];
+    }
+}
+
+/* Discrete J_l + B_w,l of eqs. (numer_J), (numer_B) for element l at
+ * perturbed element attributes (A, x, n) with f and phi frozen: f on the
+ * element follows the linear reconstruction f_l + grad f . (x - x_l); the
+ * integration ranges stay those of the unperturbed normal (Sec. 3.2).
+ * Pins the element derivatives. */
+double or_wall_JB(or_problem *p, int l, double A, double x1, double x2, double n1, double n2)
+{
+    const int nv = p->nv;
+    int c = p->wall_cell[l];
+    double on1 = p->wn[2 * l], on2 = p->wn[2 * l + 1];
+    double dx1 = x1 - p->wx[2 * l], dx2 = x2 - p->wx[2 * l + 1];
+    const double *ph = p->phi + (size_t)c * nv * 2;
+    /* F and D at (x, n) */
+    double F = 0, D = 0;
+    for (int k = 0; k < nv; k++) {
+        double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+        double vn0 = v1 * on1 + v2 * on2, vn = v1 * n1 + v2 * n2;
+        double gr[2][2];
+        gauss_grad(p, c, k, gr);
+        if (vn0 > 0) F += p->w[k] * vn * (wall_f1(p, p->f, l, k) + gr[0][0] * dx1 + gr[0][1] * dx2);
+        else D -= p->w[k] * vn * p->gM[k];
+    }
+    double J = 0, B = 0;
+    for (int k = 0; k < nv; k++) {
+        double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+        double vn0 = v1 * on1 + v2 * on2, vn = v1 * n1 + v2 * n2;
+        double gr[2][2];
+        gauss_grad(p, c, k, gr);
+        double f1l = wall_f1(p, p->f, l, k);
+        double f2l = vn0 > 0 ? p->f[((size_t)c * nv + k) * 2 + 1] : 0.5 * p->theta_w * f1l;
+        double f1x = f1l + gr[0][0] * dx1 + gr[0][1] * dx2;
+        double f2x = f2l + gr[1][0] * dx1 + gr[1][1] * dx2;
+        J += p->w[k] * p->mJ[k] * vn * f1x;
+        if (vn0 <= 0) {
+            double pw1 = -vn0 * (ph[2 * k] + p->mJ[k]), pw2 = -vn0 * ph[2 * k + 1];
+            double gb1 = p->gM[k] / D, gb2 = 0.5 * p->theta_w * gb1;
+            B += p->w[k] * (pw1 * (f1x - F * gb1) + pw2 * (f2x - F * gb2));
+        }
+    }
+    return A * (J + B);
+}

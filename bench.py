@@ -1,0 +1,209 @@
+"""Benchmark: discrete-velocity BGK primal + adjoint sweeps on one MI355X.
+
+Workload (default): NACA0012 C-grid 256x128 (32768 cells), 48x48
+Newton-Cotes velocity grid on [-6, 6] (2304 velocities), Kn 0.1, Ma 0.8,
+diffuse wall T_w = 1, 16 Hicks-Henne shape parameters; FP64.
+
+One step = one fixed-budget solve through the whole hot path: far-field
+initialisation, S primal Jacobi sweeps (moments, Maxwellian, upwind fluxes,
+wall flux, residual partials), drag, adjoint initialisation, S adjoint
+sweeps (adjoint moments, wall multiplier), wall sensitivity, node transform
+and the chain to the shape parameters.  Inputs (mesh, velocity tables) are
+resident in HBM before timing starts.
+
+Metric: cell-velocity updates per second, primal + adjoint
+(= cells * velocities * 2S / step time).  Printed as one JSON line with the
+roofline of the dominant kernel (adjoint sweep), the mixed-precision path
+on the same workload, and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
+KERNEL_SRC = os.path.join(ROOT, "paper_2501_00923_amd", "csrc", "dvm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def bytes_per_update(kind: str, mixed: bool) -> int:
+    """Algorithmic HBM bytes per (cell, velocity) per sweep: own row read +
+    written once (2 values), plus the frozen primal row for the adjoint."""
+    e = 4 if mixed else 8
+    return (4 if kind == "primal" else 6) * e
+
+
+def run_gpu(wl, precision, sweeps, steps, warmup):
+    import numpy as np
+    import torch
+
+    from paper_2501_00923_amd import dvm
+
+    s = dvm.Solver.from_workload(wl, precision=precision)
+    jac = wl.grid.wall_jac
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    tp, ta = [], []
+    out = {}
+
+    def step(record):
+        s.primal_init()
+        ev[0].record()
+        s.primal_sweeps(sweeps)
+        ev[1].record()
+        J, Cd = s.objective()
+        s.adjoint_init()
+        ev[2].record()
+        s.adjoint_sweeps(sweeps)
+        ev[3].record()
+        dJ = s.param_sensitivity(jac)
+        if record:
+            torch.cuda.synchronize()
+            tp.append(ev[0].elapsed_time(ev[1]) / sweeps)
+            ta.append(ev[2].elapsed_time(ev[3]) / sweeps)
+        out["J"], out["Cd"], out["dJ"] = J, Cd, dJ
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pairs = s.nc * s.nv
+    ms_step = (t1 - t0) * 1e3 / steps
+    out.update(pairs=pairs, ms_per_step=ms_step,
+               updates_per_s=pairs * 2 * sweeps / (ms_step * 1e-3),
+               primal_sweep_ms=float(np.mean(tp)), adjoint_sweep_ms=float(np.mean(ta)))
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(wl, seconds):
+    import oracle
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    p = oracle.Problem.from_workload(wl, nthreads=nthreads)
+    p.primal_init()
+    pairs = p.nc * p.nv
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        p.primal_iterate(1)
+        done += 1
+        if time.perf_counter() - t0 > seconds / 2:
+            break
+    tp = time.perf_counter() - t0
+    np_ = done
+    p.adjoint_init()
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        p.adjoint_iterate(1)
+        done += 1
+        if time.perf_counter() - t0 > seconds / 2:
+            break
+    ta = time.perf_counter() - t0
+    na = done
+    rate = pairs * (np_ + na) / (tp + ta)
+    return {"value": rate, "unit": "cell-velocity updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{wl.name}: {np_} primal + {na} adjoint Jacobi sweeps of the full grid "
+                      f"({pairs} pairs) from the free stream, FP64, OpenMP over cells "
+                      f"({tp + ta:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=20, help="primal and adjoint sweeps per step")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); independent solves would shard one per GPU with no exchange.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2501_00923_amd import dvm
+    from paper_2501_00923_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    dvm.lib()
+    wl = I.c2_naca(seed=0)
+    print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",
+          file=sys.stderr, flush=True)
+    r64 = run_gpu(wl, dvm.FP64, args.sweeps, args.steps, args.warmup)
+    print(f"[bench] fp64 {r64['updates_per_s']:.3e} upd/s, primal {r64['primal_sweep_ms']:.3f} ms, "
+          f"adjoint {r64['adjoint_sweep_ms']:.3f} ms", file=sys.stderr, flush=True)
+    mixed = None
+    if not args.no_mixed:
+        rm = run_gpu(wl, dvm.MIXED, args.sweeps, args.steps, args.warmup)
+        mixed = {"value": rm["updates_per_s"], "ms_per_step": rm["ms_per_step"],
+                 "speedup_vs_fp64": rm["updates_per_s"] / r64["updates_per_s"],
+                 "primal_sweep_ms": rm["primal_sweep_ms"], "adjoint_sweep_ms": rm["adjoint_sweep_ms"],
+                 "J_rel_err_vs_fp64": abs(rm["J"] - r64["J"]) / abs(r64["J"]),
+                 "dtype": "f32 state / f64 moments"}
+        print(f"[bench] mixed {rm['updates_per_s']:.3e} upd/s", file=sys.stderr, flush=True)
+
+    pairs = r64["pairs"]
+    t_adj = r64["adjoint_sweep_ms"] * 1e-3
+    t_pri = r64["primal_sweep_ms"] * 1e-3
+    b_adj = bytes_per_update("adjoint", False) * pairs
+    b_pri = bytes_per_update("primal", False) * pairs
+    achieved = b_adj / t_adj / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_sha") == kernel_hash():
+            traffic = tr.get("adjoint_fp64_bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_adjoint_sweep<double>",
+            "algorithmic_bytes_per_launch": b_adj,
+            "avg_launch_ms": r64["adjoint_sweep_ms"],
+            "primal": {"kernel": "k_primal_sweep<double>", "achieved": b_pri / t_pri / 1e9,
+                       "frac": b_pri / t_pri / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": r64["primal_sweep_ms"],
+                       "algorithmic_bytes_per_launch": b_pri}}
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+    line = {
+        "metric": "cell-velocity updates/s (primal+adjoint) vs plain FP64 path; p50/p99 solve ms",
+        "value": r64["updates_per_s"], "unit": "cell-velocity updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded NACA0012 C-grid and Hicks-Henne bump positions)",
+        "config": {"workload": wl.name, "cells": 32768, "velocities": 2304, "pairs": pairs,
+                   "sweeps_per_step": {"primal": args.sweeps, "adjoint": args.sweeps},
+                   "Kn": wl.flow.Kn, "Ma": wl.flow.Ma, "shape_params": int(wl.grid.wall_jac.shape[-1]),
+                   "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed,
+        "J": r64["J"], "Cd": r64["Cd"],
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

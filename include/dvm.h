@@ -1,0 +1,208 @@
+/*
+ * libdvm -- discrete-velocity BGK primal / adjoint solver and wall shape
+ * sensitivity for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yuan & Wu, "Adjoint shape optimization from the continuum to
+ * free-molecular gas flows" (arXiv 2501.00923).  The calls follow the
+ * paper's statement of the problem:
+ *   mesh and velocity grid ........ Sec. 3.1 (cells i, faces A_ij n_ij, volumes V_i;
+ *                                   discrete velocities v_k with weights dXi_k)
+ *   flow state and objective ...... Sec. 2.3 (far field f_d, diffuse wall at T_w),
+ *                                   Sec. 2.4 eq. (formula_opt) (m_J = v1 drag, v^2/2 heat)
+ *   primal solve .................. Sec. 3.1 eq. (numerpr_gov) with the BCs of Sec. 2.3
+ *   adjoint solve ................. Sec. 2.5 eq. (formula_adjointbgk), Sec. 3.1 eq. (numerad_gov)
+ *   objective ..................... Sec. 3.2 eq. (numer_J)
+ *   wall sensitivity .............. Sec. 3.2 eqs. (sens_J_itf), (gaussgrad), (sens_B_itf), (sens_nod)
+ *
+ * Discretisation (the paper omits its scheme): first-order upwind finite
+ * volume, Jacobi point-implicit iteration; the adjoint is the exact
+ * transpose of the discrete primal map.  Units: rho_inf = 1, theta = RT with
+ * theta_inf = 1/2, gamma = 5/3, u_inf = Ma sqrt(5/6) along +x,
+ * tau_inf = (5 sqrt(pi) / 8) Kn (Kn = +inf gives collisionless flow).
+ *
+ * Conventions
+ *   - Host arrays are FP64 or int32, row-major, 0-based; the caller owns
+ *     every array and every device buffer it passes in.  The library owns
+ *     only its opaque handles; destroy(NULL) is a no-op.
+ *   - No exception or exit() crosses this boundary.  Every int-returning
+ *     call returns a DVM_* status; on failure dvm_last_error() returns a
+ *     thread-local message.
+ *   - Device work is enqueued on the HIP stream given to dvm_solver_bind
+ *     (or to a batch call).  Calls that return host values synchronise that
+ *     stream.
+ *   - Call order is enforced: solve calls before bind, adjoint before a
+ *     primal state exists, sensitivity before an adjoint state exists
+ *     return DVM_ESTATE.
+ *   - Limits: 2 <= n1, n2 <= 128 velocity nodes per direction.
+ */
+#ifndef DVM_H
+#define DVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dvm_mesh dvm_mesh;
+typedef struct dvm_vgrid dvm_vgrid;
+typedef struct dvm_solver dvm_solver;
+
+enum {
+    DVM_OK = 0,
+    DVM_EINVAL = -1,    /* bad argument (sizes, pointers, geometry) */
+    DVM_ENOMEM = -2,    /* host allocation failed or device buffer too small */
+    DVM_EHIP = -3,      /* a HIP runtime call failed */
+    DVM_ENOTCONV = -4,  /* iteration cap reached above tolerance; state stays valid */
+    DVM_ENAN = -5,      /* NaN / Inf / non-positive density or temperature detected */
+    DVM_ESTATE = -6     /* call out of order */
+};
+enum { DVM_TOPO_O = 0, DVM_TOPO_C = 1 };
+enum { DVM_FP64 = 0, DVM_MIXED = 1 };   /* MIXED: f, phi and per-pair arithmetic in FP32;
+                                           moments, Maxwellian parameters, residuals,
+                                           wall fluxes, J and sensitivities in FP64 */
+enum { DVM_OBJ_DRAG = 0, DVM_OBJ_HEAT = 1 };
+enum { DVM_VG_MIDPOINT = 0, DVM_VG_NEWTON_COTES = 1, DVM_VG_SINH = 2 };
+enum { DVM_STATE_F = 0, DVM_STATE_PHI = 1 };
+#define DVM_MAX_PARAMS 64
+
+typedef struct {
+    double Kn;       /* Knudsen number on l_ref = 1 (eq. kndefine); +inf allowed */
+    double Ma;       /* free-stream Mach number, flow along +x */
+    double Tw;       /* wall temperature / free-stream temperature */
+    int objective;   /* DVM_OBJ_DRAG (m_J = v1) or DVM_OBJ_HEAT (m_J = |v|^2/2) */
+} dvm_flow;
+
+/* ---- mesh (Sec. 3.1) ------------------------------------------------
+ * Structured body-fitted grid given by its nodes: nodes_xy[(j*(ni+1)+i)*2+{0,1}]
+ * for i in [0, ni], j in [0, nj]; j = 0 is the wall (and the wake cut of a
+ * C-grid), j = nj the far field.  The wall is walked clockwise as i grows so
+ * that every cell (i,j),(i+1,j),(i+1,j+1),(i,j+1) is counter-clockwise; a
+ * cell with non-positive area gives DVM_EINVAL.  O-grid: periodic in i,
+ * column ni repeats column 0, n_wake = 0.  C-grid: cells i < n_wake and
+ * i >= ni - n_wake of row 0 face each other across the wake cut (cell i
+ * pairs with ni - 1 - i); faces i = 0 and i = ni are far field.
+ * Cell c = i + ni*j; faces per cell in the order (j-, i+, j+, i-).  The mesh
+ * copies nodes_xy. */
+int dvm_mesh_create(int topology, int ni, int nj, int n_wake, const double *nodes_xy,
+                    dvm_mesh **out);
+int dvm_mesh_info(const dvm_mesh *m, int32_t *n_cells, int32_t *n_wall);
+/* Exports (any pointer may be NULL): nbr[nc][4] (>= 0 neighbour cell, -1 far
+ * field, -2-l wall element l), wall_cell[nw], face vectors S[nc][4][2] =
+ * A_ij n_ij (outward of the cell), vol[nc], wall_A[nw], wall_n[nw][2] (unit
+ * normal into the solid, Sec. 3.2), wall_x[nw][2] (element midpoint).
+ * Wall element l joins wall nodes l (x_{l,1}) and (l+1) mod nw (x_{l,2}). */
+int dvm_mesh_export(const dvm_mesh *m, int32_t *nbr, int32_t *wall_cell, double *S, double *vol,
+                    double *wall_A, double *wall_n, double *wall_x);
+void dvm_mesh_destroy(dvm_mesh *m);
+
+/* ---- velocity grid (Sec. 2.2, d Xi = dv1 dv2) ------------------------
+ * Tensor product of two 1-D rules on [-vmax, vmax]; velocity k = a + n1*b has
+ * v = (x_a, y_b), weight w_a w_b.  MIDPOINT: n cells; NEWTON_COTES: n nodes,
+ * n % 4 == 0, composite Simpson either side of one centred 3/8 panel;
+ * SINH: x = vmax sinh(p s)/sinh(p) at the n cell midpoints s of (-1, 1),
+ * weight = mapped cell width (param p > 0, default 2). */
+int dvm_vgrid_create(int kind, int n1, int n2, double vmax, double param, dvm_vgrid **out);
+int dvm_vgrid_info(const dvm_vgrid *g, int32_t *nv);
+int dvm_vgrid_export(const dvm_vgrid *g, double *v /*[nv][2]*/, double *w /*[nv]*/);
+void dvm_vgrid_destroy(dvm_vgrid *g);
+
+/* ---- solver ----------------------------------------------------------
+ * The solver copies what it needs from mesh and vgrid (both may be
+ * destroyed afterwards).  precision: DVM_FP64 or DVM_MIXED.  want_adjoint
+ * = 0 leaves the adjoint buffers out of the workspace. */
+int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flow, int precision,
+                      int want_adjoint, dvm_solver **out);
+/* Exact device bytes the solver needs (used for admission by footprint). */
+size_t dvm_solver_workspace_bytes(const dvm_solver *s);
+/* Bind a caller-owned device buffer (>= workspace bytes, 256-byte aligned)
+ * and a HIP stream (NULL = default stream) on the current device; uploads
+ * the geometry and velocity tables.  May be called again to move the solver
+ * to another buffer (state is not carried over; call *_init again). */
+int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream);
+int dvm_solver_set_stream(dvm_solver *s, void *hip_stream);
+
+/* f = far-field Maxwellian in every cell (Sec. 2.3); moments and wall
+ * fluxes of it. */
+int dvm_primal_init(dvm_solver *s);
+/* Up to max_iter Jacobi sweeps of eq. (numerpr_gov).  Every check_every
+ * sweeps (and after the last) the relative change of the moments
+ * r = ||W^{n+1} - W^n||_2 / ||W^n||_2 is read back; stops when r < tol
+ * (tol <= 0: run exactly max_iter sweeps).  *iters / *resid (may be NULL)
+ * receive the sweeps done and the last r.  DVM_ENOTCONV if tol > 0 was not
+ * reached, DVM_ENAN on NaN/Inf. */
+int dvm_primal_iterate(dvm_solver *s, int max_iter, double tol, int check_every, int *iters,
+                       double *resid);
+/* Enqueue exactly n sweeps with no read-back (for timing and graphs). */
+int dvm_primal_sweeps(dvm_solver *s, int n);
+/* J of eq. (numer_J) for the current f, FP64; C_d = J / (u_inf^2 L / 2) with
+ * L = 2 (O-grid: circle diameter) or 1 (C-grid: chord).  Synchronises. */
+int dvm_objective(dvm_solver *s, double *J, double *Cd);
+/* Conservative moments W[nc][4] of the current f (FP64). Synchronises. */
+int dvm_read_moments(dvm_solver *s, double *W);
+
+/* Freeze the current f as the primal solution and set phi = 0. */
+int dvm_adjoint_init(dvm_solver *s);
+/* Jacobi sweeps of eq. (numerad_gov); r = ||phi^{n+1} - phi^n||_w / ||phi^{n+1}||_w
+ * with weights w_k.  Same stopping contract as dvm_primal_iterate. */
+int dvm_adjoint_iterate(dvm_solver *s, int max_iter, double tol, int check_every, int *iters,
+                        double *resid);
+int dvm_adjoint_sweeps(dvm_solver *s, int n);
+
+/* Per wall element l: S_A[l] = dL/dA_l, S_x[l][2] = dL/dx_l, S_n[l][2] = dL/dn_l
+ * (eqs. sens_J_itf + sens_B_itf, Green-Gauss gradient of eq. gaussgrad with
+ * the scheme's upwind face values, dB/dn carrying A_l), and dJ_dnodes[nw][2]
+ * through eq. (sens_nod) (wall node m = x_{m,1} of element m and x_{m,2} of
+ * element m-1).  Any output may be NULL.  Synchronises. */
+int dvm_wall_sensitivity(dvm_solver *s, double *S_A, double *S_x, double *S_n, double *dJ_dnodes);
+/* dJ/dalpha_p = sum_m dJ/dx_m . dx_m/dalpha_p for a wall-node Jacobian
+ * wall_jac[nw][2][n_params] (host, FP64), n_params <= DVM_MAX_PARAMS.  Runs
+ * the sensitivity kernels first.  Synchronises. */
+int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, double *dJ_dalpha);
+
+/* Checkpoint / restore as raw bytes.  DVM_STATE_F: f in the storage
+ * precision ([nc][nv][2]); loading it recomputes its moments and wall
+ * fluxes (bitwise as the sweep computes them) and starts a primal phase.
+ * DVM_STATE_PHI: phi followed by its FP64 adjoint moments ([nc][8]) and wall
+ * multipliers ([nw]); needs an adjoint phase.  Resuming from a snapshot
+ * reproduces the iterates bitwise.  save synchronises. */
+size_t dvm_state_bytes(const dvm_solver *s, int which);
+int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes);
+int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes);
+
+/* ---- batched serving --------------------------------------------------
+ * A batch groups n bound solvers of one precision.  Each member takes part
+ * in the phase it is in when the batch is created: primal (after
+ * dvm_primal_init) or adjoint (after dvm_adjoint_init).  dvm_batch_run
+ * advances every member by `iters` Jacobi sweeps with one kernel launch
+ * per sweep over all member cells, on the batch's stream; a member's sweep
+ * computes exactly what its own dvm_*_sweeps computes alone (same kernels,
+ * same reduction order, no floating-point atomics).  work_dev is a
+ * caller-owned device buffer of at least dvm_batch_work_bytes(n, total
+ * cells) bytes holding the launch tables, written once at create (which
+ * synchronises the stream).  While a batch exists its members must not be
+ * re-initialised, re-bound, destroyed or swept outside the batch; destroy
+ * the batch first.  Admission (which solves share a batch) is the caller's
+ * policy; dvm_solver_workspace_bytes gives each solve's exact footprint. */
+typedef struct dvm_batch dvm_batch;
+size_t dvm_batch_work_bytes(int n, int64_t total_cells);
+int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t work_bytes,
+                     void *hip_stream, dvm_batch **out);
+int dvm_batch_run(dvm_batch *b, int iters);
+/* Residual (as in *_iterate) of each member's last sweep into resid[n].
+ * Synchronises the batch's stream. */
+int dvm_batch_residual(dvm_batch *b, double *resid);
+void dvm_batch_destroy(dvm_batch *b);
+/* Sweeps done so far in the solver's current phase (0 primal, 1 adjoint). */
+int dvm_solver_iterations(const dvm_solver *s, int phase);
+/* Current phase: -1 no state, 0 primal, 1 adjoint. */
+int dvm_solver_phase(const dvm_solver *s);
+
+const char *dvm_last_error(void);
+void dvm_solver_destroy(dvm_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVM_H */

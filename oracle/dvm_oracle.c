@@ -267,19 +267,23 @@ static int build_mesh(or_problem *p, const double *nodes)
             int cid[4] = { node_id(p, i, j), node_id(p, i + 1, j), node_id(p, i + 1, j + 1), node_id(p, i, j + 1) };
             double X[4], Y[4];
             for (int q = 0; q < 4; q++) { X[q] = nodes[2 * cid[q]]; Y[q] = nodes[2 * cid[q] + 1]; }
-            /* shoelace area and centroid */
+            /* shoelace area and centroid, in coordinates relative to the first
+             * corner (thin wall cells far from the origin would otherwise
+             * lose digits to cancellation) */
+            double X0 = X[0], Y0 = Y[0], Xr[4], Yr[4];
+            for (int q = 0; q < 4; q++) { Xr[q] = X[q] - X0; Yr[q] = Y[q] - Y0; }
             double A2 = 0, cx = 0, cy = 0;
             for (int q = 0; q < 4; q++) {
                 int r = (q + 1) % 4;
-                double cr = X[q] * Y[r] - X[r] * Y[q];
+                double cr = Xr[q] * Yr[r] - Xr[r] * Yr[q];
                 A2 += cr;
-                cx += (X[q] + X[r]) * cr;
-                cy += (Y[q] + Y[r]) * cr;
+                cx += (Xr[q] + Xr[r]) * cr;
+                cy += (Yr[q] + Yr[r]) * cr;
             }
             if (!(A2 > 0)) return -1;
             p->vol[c] = 0.5 * A2;
-            p->cen[2 * c] = cx / (3.0 * A2);
-            p->cen[2 * c + 1] = cy / (3.0 * A2);
+            p->cen[2 * c] = X0 + cx / (3.0 * A2);
+            p->cen[2 * c + 1] = Y0 + cy / (3.0 * A2);
             /* face q is the edge corner q -> corner q+1; outward normal
              * (dy, -dx) for a counter-clockwise walk */
             for (int q = 0; q < 4; q++) {

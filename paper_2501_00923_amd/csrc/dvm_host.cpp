@@ -1,0 +1,1039 @@
+// Host side of libdvm: structured-grid connectivity and geometry, velocity
+// quadrature, flow constants, the device workspace layout, the solve state
+// machine and the C ABI declared in include/dvm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dvm.h"
+#include "dvm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(DVM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// mesh
+// ---------------------------------------------------------------------------
+struct dvm_mesh {
+    int topo = 0, ni = 0, nj = 0, nwake = 0, nc = 0, nw = 0;
+    std::vector<double> nodes;       // [(nj+1)(ni+1)][2]
+    std::vector<int32_t> nbr;        // [nc][4]
+    std::vector<int32_t> wall_cell;  // [nw]
+    std::vector<double> S;           // [nc][4][2]
+    std::vector<double> vol;         // [nc]
+    std::vector<double> wA, wn, wx, wa, wb;
+};
+
+namespace {
+
+using P2 = std::array<double, 2>;
+
+int build_mesh(dvm_mesh &m)
+{
+    const int ni = m.ni, nj = m.nj;
+    auto node = [&](int i, int j) -> P2 {
+        const double *p = &m.nodes[2 * ((size_t)j * (ni + 1) + i)];
+        return {p[0], p[1]};
+    };
+    auto cell = [&](int i, int j) { return i + ni * j; };
+    const bool cgrid = m.topo == DVM_TOPO_C;
+    m.nc = ni * nj;
+    m.nw = ni - 2 * m.nwake;
+    m.nbr.assign((size_t)4 * m.nc, 0);
+    m.S.assign((size_t)8 * m.nc, 0.0);
+    m.vol.assign(m.nc, 0.0);
+    for (int j = 0; j < nj; j++) {
+        for (int i = 0; i < ni; i++) {
+            const int c = cell(i, j);
+            const P2 q[4] = {node(i, j), node(i + 1, j), node(i + 1, j + 1), node(i, j + 1)};
+            // planar quadrilateral area = half the cross product of its diagonals
+            const double d1x = q[2][0] - q[0][0], d1y = q[2][1] - q[0][1];
+            const double d2x = q[3][0] - q[1][0], d2y = q[3][1] - q[1][1];
+            const double area = 0.5 * (d1x * d2y - d1y * d2x);
+            if (!(area > 0.0)) return fail(DVM_EINVAL, "cell (%d,%d) has non-positive area %g", i, j, area);
+            m.vol[c] = area;
+            for (int e = 0; e < 4; e++) {
+                const P2 &s = q[e], &t = q[(e + 1) & 3];
+                m.S[8 * c + 2 * e] = t[1] - s[1];       // (dy, -dx): outward for a CCW walk
+                m.S[8 * c + 2 * e + 1] = s[0] - t[0];
+            }
+            int32_t *nb = &m.nbr[4 * c];
+            // face 0: j-   (wall, wake cut or interior)
+            if (j > 0)
+                nb[0] = cell(i, j - 1);
+            else if (cgrid && (i < m.nwake || i >= ni - m.nwake))
+                nb[0] = cell(ni - 1 - i, 0);
+            else
+                nb[0] = -2 - (i - m.nwake);
+            // face 1: i+
+            nb[1] = (i + 1 < ni) ? cell(i + 1, j) : (cgrid ? -1 : cell(0, j));
+            // face 2: j+
+            nb[2] = (j + 1 < nj) ? cell(i, j + 1) : -1;
+            // face 3: i-
+            nb[3] = (i > 0) ? cell(i - 1, j) : (cgrid ? -1 : cell(ni - 1, j));
+        }
+    }
+    m.wall_cell.resize(m.nw);
+    m.wA.resize(m.nw);
+    m.wn.resize(2 * m.nw);
+    m.wx.resize(2 * m.nw);
+    m.wa.resize(2 * m.nw);
+    m.wb.resize(2 * m.nw);
+    for (int l = 0; l < m.nw; l++) {
+        const int i = m.nwake + l;
+        const int c = cell(i, 0);
+        m.wall_cell[l] = c;
+        const P2 a = node(i, 0), b = node(i + 1, 0);
+        const double sx = m.S[8 * c], sy = m.S[8 * c + 1];
+        const double A = std::hypot(sx, sy);
+        m.wA[l] = A;
+        m.wn[2 * l] = sx / A;
+        m.wn[2 * l + 1] = sy / A;
+        m.wa[2 * l] = a[0];
+        m.wa[2 * l + 1] = a[1];
+        m.wb[2 * l] = b[0];
+        m.wb[2 * l + 1] = b[1];
+        m.wx[2 * l] = 0.5 * (a[0] + b[0]);
+        m.wx[2 * l + 1] = 0.5 * (a[1] + b[1]);
+    }
+    return DVM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// velocity grid
+// ---------------------------------------------------------------------------
+struct dvm_vgrid {
+    int kind = 0, n1 = 0, n2 = 0;
+    double vmax = 0, param = 0;
+    std::vector<double> x1, w1, x2, w2;
+};
+
+namespace {
+
+int rule_1d(int kind, int n, double vmax, double param, std::vector<double> &x, std::vector<double> &w)
+{
+    if (n < 2 || n > dvm::kMaxN1D) return fail(DVM_EINVAL, "velocity nodes per direction must be in [2, %d]", dvm::kMaxN1D);
+    if (!(vmax > 0)) return fail(DVM_EINVAL, "vmax must be positive");
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    switch (kind) {
+    case DVM_VG_MIDPOINT: {
+        const double h = 2.0 * vmax / n;
+        for (int a = 0; a < n; a++) {
+            x[a] = (a + 0.5 - 0.5 * n) * h;
+            w[a] = h;
+        }
+        return DVM_OK;
+    }
+    case DVM_VG_NEWTON_COTES: {
+        if (n % 4) return fail(DVM_EINVAL, "Newton-Cotes grid needs n divisible by 4 (got %d)", n);
+        const int m = n - 1;                  // intervals
+        const double h = 2.0 * vmax / m;
+        for (int a = 0; a < n; a++) x[a] = (a - 0.5 * m) * h;
+        const int left = (m - 3) / 2;         // Simpson intervals left of the 3/8 panel
+        auto simpson = [&](int from, int to) {
+            for (int p = from; p < to; p += 2) {
+                w[p] += h / 3.0;
+                w[p + 1] += 4.0 * h / 3.0;
+                w[p + 2] += h / 3.0;
+            }
+        };
+        simpson(0, left);
+        const double e = 3.0 * h / 8.0;
+        const double mid[4] = {e, 3.0 * e, 3.0 * e, e};
+        for (int t = 0; t < 4; t++) w[left + t] += mid[t];
+        simpson(left + 3, m);
+        return DVM_OK;
+    }
+    case DVM_VG_SINH: {
+        const double p = param > 0 ? param : 2.0;
+        const double sp = std::sinh(p);
+        auto map = [&](double s) { return vmax * std::sinh(p * s) / sp; };
+        for (int a = 0; a < n; a++) {
+            const double s0 = -1.0 + 2.0 * a / n, s1 = -1.0 + 2.0 * (a + 1) / n;
+            x[a] = map(0.5 * (s0 + s1));
+            w[a] = map(s1) - map(s0);
+        }
+        return DVM_OK;
+    }
+    default:
+        return fail(DVM_EINVAL, "unknown velocity grid kind %d", kind);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// solver
+// ---------------------------------------------------------------------------
+struct dvm_solver {
+    // problem
+    int topo, nc, nw, n1, n2, nv, mixed, want_adjoint, objective;
+    std::vector<int32_t> nbr, wall_cell;
+    std::vector<double> S, vol, wA, wn, wa, wb, D;
+    std::vector<double> x1, w1, x2, w2;
+    std::vector<double> fd;   // [nv][2]
+    std::vector<double> gM;   // [nv]
+    double inv_tau_inf, u_inf, theta_w, cd_scale;
+    // workspace
+    struct {
+        size_t nbr, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM;
+        size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, out, total;
+    } off;
+    char *base = nullptr;
+    hipStream_t stream = nullptr;
+    dvm::DevSolve dev{};
+    // state
+    int phase = -1;   // -1 none, 0 primal, 1 adjoint
+    int fpar = 0, ppar = 0, frozen_fpar = 0;
+    int iters[2] = {0, 0};
+    int in_batch = 0;
+};
+
+namespace {
+
+size_t elt_bytes(const dvm_solver &s) { return s.mixed ? sizeof(float) : sizeof(double); }
+
+void layout(dvm_solver &s)
+{
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = cur;
+        cur = align_up(cur + bytes);
+        return o;
+    };
+    const size_t nc = s.nc, nw = s.nw, nv = s.nv, e = elt_bytes(s);
+    auto &o = s.off;
+    o.nbr = take(4 * nc * sizeof(int32_t));
+    o.S = take(8 * nc * sizeof(double));
+    o.vol = take(nc * sizeof(double));
+    o.wall_cell = take(nw * sizeof(int32_t));
+    o.wA = take(nw * sizeof(double));
+    o.wn = take(2 * nw * sizeof(double));
+    o.wa = take(2 * nw * sizeof(double));
+    o.wb = take(2 * nw * sizeof(double));
+    o.D = take(nw * sizeof(double));
+    o.vx = take(s.n1 * sizeof(double));
+    o.vy = take(s.n2 * sizeof(double));
+    o.wx = take(s.n1 * sizeof(double));
+    o.wy = take(s.n2 * sizeof(double));
+    o.fd = take(2 * nv * e);
+    o.gM = take(nv * e);
+    for (int p = 0; p < 2; p++) {
+        o.f[p] = take(2 * nc * nv * e);
+        o.W[p] = take(4 * nc * sizeof(double));
+        o.F[p] = take(nw * sizeof(double));
+    }
+    o.red = take(2 * nc * sizeof(double));
+    if (s.want_adjoint) {
+        for (int p = 0; p < 2; p++) {
+            o.phi[p] = take(2 * nc * nv * e);
+            o.aW[p] = take(8 * nc * sizeof(double));
+            o.Phi[p] = take(nw * sizeof(double));
+        }
+        o.acoef = take(16 * nc * sizeof(double));
+        o.sens = take(5 * nw * sizeof(double));
+        o.dJdn = take(2 * nw * sizeof(double));
+        o.jac = take(2 * nw * dvm::kMaxParams * sizeof(double));
+        o.dJda = take(dvm::kMaxParams * sizeof(double));
+    } else {
+        o.phi[0] = o.phi[1] = o.aW[0] = o.aW[1] = o.Phi[0] = o.Phi[1] = o.acoef = o.sens = o.dJdn = o.jac =
+            o.dJda = (size_t)-1;
+    }
+    o.Jl = take(nw * sizeof(double));
+    o.out = take(16 * sizeof(double));
+    o.total = cur;
+}
+
+template <typename P>
+P *at(const dvm_solver &s, size_t off)
+{
+    return off == (size_t)-1 ? nullptr : reinterpret_cast<P *>(s.base + off);
+}
+
+void fill_dev(dvm_solver &s)
+{
+    dvm::DevSolve &d = s.dev;
+    d.nc = s.nc;
+    d.nw = s.nw;
+    d.nv = s.nv;
+    d.n1 = s.n1;
+    d.n2 = s.n2;
+    d.topo = s.topo;
+    d.objective = s.objective;
+    d.mixed = s.mixed;
+    d.nbr = at<int32_t>(s, s.off.nbr);
+    d.S = at<double>(s, s.off.S);
+    d.vol = at<double>(s, s.off.vol);
+    d.wall_cell = at<int32_t>(s, s.off.wall_cell);
+    d.wall_A = at<double>(s, s.off.wA);
+    d.wall_n = at<double>(s, s.off.wn);
+    d.wall_a = at<double>(s, s.off.wa);
+    d.wall_b = at<double>(s, s.off.wb);
+    d.D = at<double>(s, s.off.D);
+    d.vx = at<double>(s, s.off.vx);
+    d.vy = at<double>(s, s.off.vy);
+    d.wx = at<double>(s, s.off.wx);
+    d.wy = at<double>(s, s.off.wy);
+    d.fd = at<void>(s, s.off.fd);
+    d.gM = at<void>(s, s.off.gM);
+    d.inv_tau_inf = s.inv_tau_inf;
+    d.u_inf = s.u_inf;
+    d.theta_w = s.theta_w;
+    d.cd_scale = s.cd_scale;
+    for (int p = 0; p < 2; p++) {
+        d.f[p] = at<void>(s, s.off.f[p]);
+        d.W[p] = at<double>(s, s.off.W[p]);
+        d.F[p] = at<double>(s, s.off.F[p]);
+        d.phi[p] = at<void>(s, s.off.phi[p]);
+        d.aW[p] = at<double>(s, s.off.aW[p]);
+        d.Phi[p] = at<double>(s, s.off.Phi[p]);
+    }
+    d.red = at<double>(s, s.off.red);
+    d.fstar = d.f[s.frozen_fpar];
+    d.acoef = at<double>(s, s.off.acoef);
+    d.Jl = at<double>(s, s.off.Jl);
+    d.sens = at<double>(s, s.off.sens);
+    d.dJdn = at<double>(s, s.off.dJdn);
+    d.jac = at<double>(s, s.off.jac);
+    d.dJda = at<double>(s, s.off.dJda);
+    d.out = at<double>(s, s.off.out);
+}
+
+int upload(dvm_solver &s, size_t off, const void *src, size_t bytes)
+{
+    HIP_OK(hipMemcpyAsync(s.base + off, src, bytes, hipMemcpyHostToDevice, s.stream));
+    return DVM_OK;
+}
+
+int read_back(dvm_solver &s, const double *dev_src, double *dst, size_t n)
+{
+    HIP_OK(hipMemcpyAsync(dst, dev_src, n * sizeof(double), hipMemcpyDeviceToHost, s.stream));
+    HIP_OK(hipStreamSynchronize(s.stream));
+    return DVM_OK;
+}
+
+double rel_norm(double num, double den)
+{
+    if (!(den > 0)) return num == 0 ? 0.0 : INFINITY;
+    return std::sqrt(num / den);
+}
+
+int read_residual(dvm_solver &s, int adjoint, double *r)
+{
+    HIP_OK(dvm::launch_residual(s.dev, adjoint, s.stream));
+    double v[2];
+    if (int e = read_back(s, s.dev.out + (adjoint ? 4 : 2), v, 2)) return e;
+    *r = rel_norm(v[0], v[1]);
+    return DVM_OK;
+}
+
+int check_bound(const dvm_solver *s)
+{
+    if (!s) return fail(DVM_EINVAL, "null solver");
+    if (!s->base) return fail(DVM_ESTATE, "solver is not bound to a device buffer");
+    if (s->in_batch) return fail(DVM_ESTATE, "solver is a member of a live batch");
+    return DVM_OK;
+}
+
+int sweeps(dvm_solver &s, int adjoint, int n)
+{
+    for (int i = 0; i < n; i++) {
+        if (adjoint) {
+            HIP_OK(dvm::launch_adjoint_sweep(s.dev, s.ppar, s.stream));
+            s.ppar ^= 1;
+        } else {
+            HIP_OK(dvm::launch_primal_sweep(s.dev, s.fpar, s.stream));
+            s.fpar ^= 1;
+        }
+    }
+    s.iters[adjoint] += n;
+    return DVM_OK;
+}
+
+int iterate(dvm_solver &s, int adjoint, int max_iter, double tol, int check_every, int *iters, double *resid)
+{
+    if (max_iter < 0) return fail(DVM_EINVAL, "max_iter < 0");
+    if (check_every <= 0) check_every = max_iter > 0 ? max_iter : 1;
+    int done = 0;
+    double r = NAN;
+    while (done < max_iter) {
+        const int m = std::min(check_every, max_iter - done);
+        if (int e = sweeps(s, adjoint, m)) return e;
+        done += m;
+        if (tol > 0 || done == max_iter) {
+            if (int e = read_residual(s, adjoint, &r)) return e;
+            if (!std::isfinite(r)) {
+                if (iters) *iters = done;
+                if (resid) *resid = r;
+                return fail(DVM_ENAN, "%s residual is not finite after %d sweeps", adjoint ? "adjoint" : "primal",
+                            done);
+            }
+            if (tol > 0 && r < tol) break;
+        }
+    }
+    if (iters) *iters = done;
+    if (resid) *resid = r;
+    if (tol > 0 && !(r < tol))
+        return fail(DVM_ENOTCONV, "%s residual %.3e above tolerance %.3e after %d sweeps",
+                    adjoint ? "adjoint" : "primal", r, tol, done);
+    return DVM_OK;
+}
+
+int setup_flow(dvm_solver &s, const dvm_flow &fl)
+{
+    if (!(fl.Tw > 0) || !(fl.Ma >= 0) || !(fl.Kn > 0) || std::isnan(fl.Kn))
+        return fail(DVM_EINVAL, "flow state needs Kn > 0, Ma >= 0, Tw > 0");
+    if (fl.objective != DVM_OBJ_DRAG && fl.objective != DVM_OBJ_HEAT) return fail(DVM_EINVAL, "unknown objective");
+    const double th_inf = 0.5;                        // theta = RT, velocity unit sqrt(2 R T_inf)
+    s.theta_w = th_inf * fl.Tw;
+    s.u_inf = fl.Ma * std::sqrt(5.0 / 3.0 * th_inf);  // gamma = 5/3
+    // Kn = (16/5) (tau / l_ref) sqrt(RT / (2 pi)), l_ref = 1, theta_inf = 1/2
+    s.inv_tau_inf = std::isinf(fl.Kn) ? 0.0 : 1.0 / (0.625 * std::sqrt(kPi) * fl.Kn);
+    s.cd_scale = 0.5 * s.u_inf * s.u_inf * (s.topo == DVM_TOPO_O ? 2.0 : 1.0);
+    s.objective = fl.objective;
+    s.fd.resize(2 * s.nv);
+    s.gM.resize(s.nv);
+    for (int b = 0; b < s.n2; b++) {
+        for (int a = 0; a < s.n1; a++) {
+            const int k = a + s.n1 * b;
+            const double c1 = s.x1[a] - s.u_inf, c2 = s.x2[b];
+            const double g = std::exp(-(c1 * c1 + c2 * c2) / (2.0 * th_inf)) / (2.0 * kPi * th_inf);
+            s.fd[2 * k] = g;
+            s.fd[2 * k + 1] = 0.5 * th_inf * g;
+            const double r2 = s.x1[a] * s.x1[a] + s.x2[b] * s.x2[b];
+            s.gM[k] = std::exp(-r2 / (2.0 * s.theta_w)) / (2.0 * kPi * s.theta_w);
+        }
+    }
+    // eq. (barg): D_l = -sum_{v.n <= 0} w (v.n) g_M1(1, 0, T_w)
+    s.D.assign(s.nw, 0.0);
+    for (int l = 0; l < s.nw; l++) {
+        double acc = 0;
+        for (int b = 0; b < s.n2; b++)
+            for (int a = 0; a < s.n1; a++) {
+                const double vn = s.x1[a] * s.wn[2 * l] + s.x2[b] * s.wn[2 * l + 1];
+                if (vn <= 0) acc -= s.w1[a] * s.w2[b] * vn * s.gM[a + s.n1 * b];
+            }
+        if (!(acc > 0)) return fail(DVM_EINVAL, "wall element %d has no incoming velocities", l);
+        s.D[l] = acc;
+    }
+    return DVM_OK;
+}
+
+template <typename T>
+std::vector<T> convert(const std::vector<double> &v)
+{
+    return std::vector<T>(v.begin(), v.end());
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+struct dvm_batch {
+    std::vector<dvm_solver *> members;
+    char *work = nullptr;
+    hipStream_t stream = nullptr;
+    int nblocks = 0, mixed = 0;
+    int step = 0;
+    size_t off_tab = 0, off_par = 0, off_phase = 0, off_bs = 0, off_bc = 0, off_out = 0;
+};
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *dvm_last_error(void) { return g_err.c_str(); }
+
+int dvm_mesh_create(int topology, int ni, int nj, int n_wake, const double *nodes_xy, dvm_mesh **out)
+{
+    if (!out || !nodes_xy) return fail(DVM_EINVAL, "null argument");
+    *out = nullptr;
+    if (topology != DVM_TOPO_O && topology != DVM_TOPO_C) return fail(DVM_EINVAL, "unknown topology %d", topology);
+    if (ni < 3 || nj < 1) return fail(DVM_EINVAL, "grid too small (ni=%d, nj=%d)", ni, nj);
+    if (topology == DVM_TOPO_O && n_wake != 0) return fail(DVM_EINVAL, "O-grid takes n_wake = 0");
+    if (topology == DVM_TOPO_C && (n_wake < 1 || 2 * n_wake >= ni - 1))
+        return fail(DVM_EINVAL, "C-grid needs 1 <= n_wake and 2 n_wake < ni - 1");
+    if ((int64_t)ni * nj > (int64_t)1 << 30) return fail(DVM_EINVAL, "grid too large");
+    try {
+        auto *m = new dvm_mesh;
+        m->topo = topology;
+        m->ni = ni;
+        m->nj = nj;
+        m->nwake = n_wake;
+        m->nodes.assign(nodes_xy, nodes_xy + 2 * (size_t)(ni + 1) * (nj + 1));
+        if (int e = build_mesh(*m)) {
+            delete m;
+            return e;
+        }
+        *out = m;
+        return DVM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DVM_ENOMEM, "out of host memory");
+    }
+}
+
+int dvm_mesh_info(const dvm_mesh *m, int32_t *n_cells, int32_t *n_wall)
+{
+    if (!m) return fail(DVM_EINVAL, "null mesh");
+    if (n_cells) *n_cells = m->nc;
+    if (n_wall) *n_wall = m->nw;
+    return DVM_OK;
+}
+
+int dvm_mesh_export(const dvm_mesh *m, int32_t *nbr, int32_t *wall_cell, double *S, double *vol, double *wall_A,
+                    double *wall_n, double *wall_x)
+{
+    if (!m) return fail(DVM_EINVAL, "null mesh");
+    if (nbr) std::copy(m->nbr.begin(), m->nbr.end(), nbr);
+    if (wall_cell) std::copy(m->wall_cell.begin(), m->wall_cell.end(), wall_cell);
+    if (S) std::copy(m->S.begin(), m->S.end(), S);
+    if (vol) std::copy(m->vol.begin(), m->vol.end(), vol);
+    if (wall_A) std::copy(m->wA.begin(), m->wA.end(), wall_A);
+    if (wall_n) std::copy(m->wn.begin(), m->wn.end(), wall_n);
+    if (wall_x) std::copy(m->wx.begin(), m->wx.end(), wall_x);
+    return DVM_OK;
+}
+
+void dvm_mesh_destroy(dvm_mesh *m) { delete m; }
+
+int dvm_vgrid_create(int kind, int n1, int n2, double vmax, double param, dvm_vgrid **out)
+{
+    if (!out) return fail(DVM_EINVAL, "null argument");
+    *out = nullptr;
+    try {
+        auto *g = new dvm_vgrid;
+        g->kind = kind;
+        g->n1 = n1;
+        g->n2 = n2;
+        g->vmax = vmax;
+        g->param = param;
+        if (int e = rule_1d(kind, n1, vmax, param, g->x1, g->w1)) {
+            delete g;
+            return e;
+        }
+        if (int e = rule_1d(kind, n2, vmax, param, g->x2, g->w2)) {
+            delete g;
+            return e;
+        }
+        *out = g;
+        return DVM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DVM_ENOMEM, "out of host memory");
+    }
+}
+
+int dvm_vgrid_info(const dvm_vgrid *g, int32_t *nv)
+{
+    if (!g) return fail(DVM_EINVAL, "null velocity grid");
+    if (nv) *nv = g->n1 * g->n2;
+    return DVM_OK;
+}
+
+int dvm_vgrid_export(const dvm_vgrid *g, double *v, double *w)
+{
+    if (!g) return fail(DVM_EINVAL, "null velocity grid");
+    for (int b = 0; b < g->n2; b++)
+        for (int a = 0; a < g->n1; a++) {
+            const int k = a + g->n1 * b;
+            if (v) {
+                v[2 * k] = g->x1[a];
+                v[2 * k + 1] = g->x2[b];
+            }
+            if (w) w[k] = g->w1[a] * g->w2[b];
+        }
+    return DVM_OK;
+}
+
+void dvm_vgrid_destroy(dvm_vgrid *g) { delete g; }
+
+int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flow, int precision, int want_adjoint,
+                      dvm_solver **out)
+{
+    if (!out || !m || !g || !flow) return fail(DVM_EINVAL, "null argument");
+    *out = nullptr;
+    if (precision != DVM_FP64 && precision != DVM_MIXED) return fail(DVM_EINVAL, "unknown precision %d", precision);
+    try {
+        auto *s = new dvm_solver;
+        s->topo = m->topo;
+        s->nc = m->nc;
+        s->nw = m->nw;
+        s->n1 = g->n1;
+        s->n2 = g->n2;
+        s->nv = g->n1 * g->n2;
+        s->mixed = precision == DVM_MIXED;
+        s->want_adjoint = want_adjoint ? 1 : 0;
+        s->nbr = m->nbr;
+        s->wall_cell = m->wall_cell;
+        s->S = m->S;
+        s->vol = m->vol;
+        s->wA = m->wA;
+        s->wn = m->wn;
+        s->wa = m->wa;
+        s->wb = m->wb;
+        s->x1 = g->x1;
+        s->w1 = g->w1;
+        s->x2 = g->x2;
+        s->w2 = g->w2;
+        if (int e = setup_flow(*s, *flow)) {
+            delete s;
+            return e;
+        }
+        layout(*s);
+        *out = s;
+        return DVM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DVM_ENOMEM, "out of host memory");
+    }
+}
+
+size_t dvm_solver_workspace_bytes(const dvm_solver *s) { return s ? s->off.total : 0; }
+
+int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
+{
+    if (!s || !dev_ptr) return fail(DVM_EINVAL, "null argument");
+    if (s->in_batch) return fail(DVM_ESTATE, "solver is a member of a live batch");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign) return fail(DVM_EINVAL, "device buffer not 256-byte aligned");
+    if (bytes < s->off.total)
+        return fail(DVM_ENOMEM, "device buffer of %zu bytes < workspace %zu bytes", bytes, s->off.total);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(DVM_EINVAL, "buffer is not device memory");
+    }
+    s->base = static_cast<char *>(dev_ptr);
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    s->phase = -1;
+    s->fpar = s->ppar = s->frozen_fpar = 0;
+    s->iters[0] = s->iters[1] = 0;
+    fill_dev(*s);
+    const auto &o = s->off;
+    int e = 0;
+    e = e ? e : upload(*s, o.nbr, s->nbr.data(), s->nbr.size() * sizeof(int32_t));
+    e = e ? e : upload(*s, o.S, s->S.data(), s->S.size() * sizeof(double));
+    e = e ? e : upload(*s, o.vol, s->vol.data(), s->vol.size() * sizeof(double));
+    e = e ? e : upload(*s, o.wall_cell, s->wall_cell.data(), s->wall_cell.size() * sizeof(int32_t));
+    e = e ? e : upload(*s, o.wA, s->wA.data(), s->wA.size() * sizeof(double));
+    e = e ? e : upload(*s, o.wn, s->wn.data(), s->wn.size() * sizeof(double));
+    e = e ? e : upload(*s, o.wa, s->wa.data(), s->wa.size() * sizeof(double));
+    e = e ? e : upload(*s, o.wb, s->wb.data(), s->wb.size() * sizeof(double));
+    e = e ? e : upload(*s, o.D, s->D.data(), s->D.size() * sizeof(double));
+    e = e ? e : upload(*s, o.vx, s->x1.data(), s->x1.size() * sizeof(double));
+    e = e ? e : upload(*s, o.vy, s->x2.data(), s->x2.size() * sizeof(double));
+    e = e ? e : upload(*s, o.wx, s->w1.data(), s->w1.size() * sizeof(double));
+    e = e ? e : upload(*s, o.wy, s->w2.data(), s->w2.size() * sizeof(double));
+    std::vector<float> fdf, gMf;
+    if (s->mixed) {
+        fdf = convert<float>(s->fd);
+        gMf = convert<float>(s->gM);
+        e = e ? e : upload(*s, o.fd, fdf.data(), fdf.size() * sizeof(float));
+        e = e ? e : upload(*s, o.gM, gMf.data(), gMf.size() * sizeof(float));
+    } else {
+        e = e ? e : upload(*s, o.fd, s->fd.data(), s->fd.size() * sizeof(double));
+        e = e ? e : upload(*s, o.gM, s->gM.data(), s->gM.size() * sizeof(double));
+    }
+    if (e) {
+        s->base = nullptr;
+        return e;
+    }
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return DVM_OK;
+}
+
+int dvm_solver_set_stream(dvm_solver *s, void *hip_stream)
+{
+    if (!s) return fail(DVM_EINVAL, "null solver");
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return DVM_OK;
+}
+
+int dvm_primal_init(dvm_solver *s)
+{
+    if (int e = check_bound(s)) return e;
+    HIP_OK(dvm::launch_primal_init(s->dev, s->stream));
+    s->fpar = 0;
+    s->phase = 0;
+    s->iters[0] = s->iters[1] = 0;
+    return DVM_OK;
+}
+
+int dvm_primal_iterate(dvm_solver *s, int max_iter, double tol, int check_every, int *iters, double *resid)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase != 0) return fail(DVM_ESTATE, "no primal phase (call dvm_primal_init)");
+    return iterate(*s, 0, max_iter, tol, check_every, iters, resid);
+}
+
+int dvm_primal_sweeps(dvm_solver *s, int n)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase != 0) return fail(DVM_ESTATE, "no primal phase (call dvm_primal_init)");
+    if (n < 0) return fail(DVM_EINVAL, "n < 0");
+    return sweeps(*s, 0, n);
+}
+
+int dvm_objective(dvm_solver *s, double *J, double *Cd)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase < 0) return fail(DVM_ESTATE, "no primal state");
+    const int par = s->phase == 1 ? s->frozen_fpar : s->fpar;
+    HIP_OK(dvm::launch_objective(s->dev, par, s->stream));
+    double v[2];
+    if (int e = read_back(*s, s->dev.out, v, 2)) return e;
+    if (J) *J = v[0];
+    if (Cd) *Cd = v[1];
+    return DVM_OK;
+}
+
+int dvm_read_moments(dvm_solver *s, double *W)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase < 0) return fail(DVM_ESTATE, "no primal state");
+    if (!W) return fail(DVM_EINVAL, "null output");
+    const int par = s->phase == 1 ? s->frozen_fpar : s->fpar;
+    return read_back(*s, s->dev.W[par], W, (size_t)4 * s->nc);
+}
+
+int dvm_adjoint_init(dvm_solver *s)
+{
+    if (int e = check_bound(s)) return e;
+    if (!s->want_adjoint) return fail(DVM_ESTATE, "solver was created without adjoint buffers");
+    if (s->phase < 0) return fail(DVM_ESTATE, "no primal state to linearise about");
+    if (s->phase == 0) s->frozen_fpar = s->fpar;
+    fill_dev(*s);
+    HIP_OK(dvm::launch_adjoint_init(s->dev, s->frozen_fpar, s->stream));
+    s->ppar = 0;
+    s->phase = 1;
+    s->iters[1] = 0;
+    return DVM_OK;
+}
+
+int dvm_adjoint_iterate(dvm_solver *s, int max_iter, double tol, int check_every, int *iters, double *resid)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint phase (call dvm_adjoint_init)");
+    return iterate(*s, 1, max_iter, tol, check_every, iters, resid);
+}
+
+int dvm_adjoint_sweeps(dvm_solver *s, int n)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint phase (call dvm_adjoint_init)");
+    if (n < 0) return fail(DVM_EINVAL, "n < 0");
+    return sweeps(*s, 1, n);
+}
+
+static int run_sens(dvm_solver *s, int n_params)
+{
+    HIP_OK(dvm::launch_wall_sens(s->dev, s->frozen_fpar, s->ppar, n_params, s->stream));
+    return DVM_OK;
+}
+
+int dvm_wall_sensitivity(dvm_solver *s, double *S_A, double *S_x, double *S_n, double *dJ_dnodes)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+    if (int e = run_sens(s, 0)) return e;
+    std::vector<double> sens(5 * (size_t)s->nw), dn(2 * (size_t)s->nw);
+    if (int e = read_back(*s, s->dev.sens, sens.data(), sens.size())) return e;
+    if (int e = read_back(*s, s->dev.dJdn, dn.data(), dn.size())) return e;
+    for (int l = 0; l < s->nw; l++) {
+        if (S_A) S_A[l] = sens[5 * l];
+        if (S_x) {
+            S_x[2 * l] = sens[5 * l + 1];
+            S_x[2 * l + 1] = sens[5 * l + 2];
+        }
+        if (S_n) {
+            S_n[2 * l] = sens[5 * l + 3];
+            S_n[2 * l + 1] = sens[5 * l + 4];
+        }
+    }
+    if (dJ_dnodes) std::copy(dn.begin(), dn.end(), dJ_dnodes);
+    return DVM_OK;
+}
+
+int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, double *dJ_dalpha)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+    if (n_params < 0 || n_params > dvm::kMaxParams) return fail(DVM_EINVAL, "n_params must be in [0, %d]", dvm::kMaxParams);
+    if (n_params > 0 && (!wall_jac || !dJ_dalpha)) return fail(DVM_EINVAL, "null argument");
+    std::vector<double> jac((size_t)2 * s->nw * dvm::kMaxParams, 0.0);
+    for (int r = 0; r < 2 * s->nw; r++)
+        for (int p = 0; p < n_params; p++) jac[(size_t)r * dvm::kMaxParams + p] = wall_jac[(size_t)r * n_params + p];
+    if (int e = upload(*s, s->off.jac, jac.data(), jac.size() * sizeof(double))) return e;
+    if (int e = run_sens(s, n_params)) return e;
+    if (n_params == 0) {
+        HIP_OK(hipStreamSynchronize(s->stream));   // jac must outlive its upload
+        return DVM_OK;
+    }
+    return read_back(*s, s->dev.dJda, dJ_dalpha, n_params);
+}
+
+size_t dvm_state_bytes(const dvm_solver *s, int which)
+{
+    if (!s) return 0;
+    const size_t row = (size_t)s->nc * s->nv * 2 * elt_bytes(*s);
+    if (which == DVM_STATE_F) return row;
+    if (which == DVM_STATE_PHI && s->want_adjoint)
+        return row + (size_t)8 * s->nc * sizeof(double) + (size_t)s->nw * sizeof(double);
+    return 0;
+}
+
+int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes)
+{
+    if (int e = check_bound(s)) return e;
+    const size_t need = dvm_state_bytes(s, which);
+    if (!need || !host_dst || bytes < need) return fail(DVM_EINVAL, "bad state kind or buffer size");
+    char *dst = static_cast<char *>(host_dst);
+    const size_t row = (size_t)s->nc * s->nv * 2 * elt_bytes(*s);
+    if (which == DVM_STATE_F) {
+        if (s->phase < 0) return fail(DVM_ESTATE, "no primal state");
+        const int par = s->phase == 1 ? s->frozen_fpar : s->fpar;
+        HIP_OK(hipMemcpyAsync(dst, s->dev.f[par], row, hipMemcpyDeviceToHost, s->stream));
+    } else {
+        if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+        HIP_OK(hipMemcpyAsync(dst, s->dev.phi[s->ppar], row, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(hipMemcpyAsync(dst + row, s->dev.aW[s->ppar], (size_t)8 * s->nc * sizeof(double),
+                              hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(hipMemcpyAsync(dst + row + (size_t)8 * s->nc * sizeof(double), s->dev.Phi[s->ppar],
+                              (size_t)s->nw * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    }
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return DVM_OK;
+}
+
+int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
+{
+    if (int e = check_bound(s)) return e;
+    const size_t need = dvm_state_bytes(s, which);
+    if (!need || !host_src || bytes < need) return fail(DVM_EINVAL, "bad state kind or buffer size");
+    const char *src = static_cast<const char *>(host_src);
+    const size_t row = (size_t)s->nc * s->nv * 2 * elt_bytes(*s);
+    if (which == DVM_STATE_F) {
+        s->fpar = 0;
+        HIP_OK(hipMemcpyAsync(s->dev.f[0], src, row, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(dvm::launch_moments(s->dev, 0, s->stream));
+        s->phase = 0;
+        s->iters[0] = s->iters[1] = 0;
+    } else {
+        if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint phase to load into (call dvm_adjoint_init)");
+        HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], src, row, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(hipMemcpyAsync(s->dev.aW[s->ppar], src + row, (size_t)8 * s->nc * sizeof(double),
+                              hipMemcpyHostToDevice, s->stream));
+        HIP_OK(hipMemcpyAsync(s->dev.Phi[s->ppar], src + row + (size_t)8 * s->nc * sizeof(double),
+                              (size_t)s->nw * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    }
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return DVM_OK;
+}
+
+int dvm_solver_iterations(const dvm_solver *s, int phase)
+{
+    if (!s || phase < 0 || phase > 1) return -1;
+    return s->iters[phase];
+}
+
+int dvm_solver_phase(const dvm_solver *s) { return s ? s->phase : -1; }
+
+void dvm_solver_destroy(dvm_solver *s) { delete s; }
+
+// ---- batch ----------------------------------------------------------------
+
+static void batch_layout(int n, int64_t nblocks, dvm_batch *b, size_t *total)
+{
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = cur;
+        cur = align_up(cur + bytes);
+        return o;
+    };
+    const size_t ot = take((size_t)n * sizeof(dvm::DevSolve));
+    const size_t op = take((size_t)n * sizeof(int32_t));
+    const size_t oph = take((size_t)n * sizeof(int32_t));
+    const size_t obs = take((size_t)nblocks * sizeof(int32_t));
+    const size_t obc = take((size_t)nblocks * sizeof(int32_t));
+    const size_t oo = take((size_t)2 * n * sizeof(double));
+    if (b) {
+        b->off_tab = ot;
+        b->off_par = op;
+        b->off_phase = oph;
+        b->off_bs = obs;
+        b->off_bc = obc;
+        b->off_out = oo;
+    }
+    *total = cur;
+}
+
+size_t dvm_batch_work_bytes(int n, int64_t total_cells)
+{
+    if (n <= 0 || total_cells < 0) return 0;
+    size_t t;
+    batch_layout(n, (total_cells + 7) / 8 * 8, nullptr, &t);
+    return t;
+}
+
+int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t work_bytes, void *hip_stream,
+                     dvm_batch **out)
+{
+    if (!out || !solvers || n <= 0 || !work_dev) return fail(DVM_EINVAL, "null argument or empty batch");
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(DVM_EINVAL, "work buffer not 256-byte aligned");
+    int64_t total = 0;
+    int mixed = -1;
+    for (int i = 0; i < n; i++) {
+        const dvm_solver *s = solvers[i];
+        if (int e = check_bound(s)) return e;
+        for (int j = 0; j < i; j++)
+            if (solvers[j] == s) return fail(DVM_EINVAL, "solver listed twice");
+        if (s->phase < 0) return fail(DVM_ESTATE, "member %d has no primal or adjoint phase", i);
+        if (mixed < 0) mixed = s->mixed;
+        if (mixed != s->mixed) return fail(DVM_EINVAL, "batch members must share one precision");
+        total += s->nc;
+    }
+    const int64_t nblocks = (total + 7) / 8 * 8;
+    if (nblocks > INT32_MAX) return fail(DVM_EINVAL, "batch too large");
+    size_t need;
+    try {
+        auto *b = new dvm_batch;
+        batch_layout(n, nblocks, b, &need);
+        if (work_bytes < need) {
+            delete b;
+            return fail(DVM_ENOMEM, "batch work buffer of %zu bytes < %zu bytes", work_bytes, need);
+        }
+        b->members.assign(solvers, solvers + n);
+        b->work = static_cast<char *>(work_dev);
+        b->stream = static_cast<hipStream_t>(hip_stream);
+        b->nblocks = (int)nblocks;
+        b->mixed = mixed;
+        std::vector<dvm::DevSolve> tab(n);
+        std::vector<int32_t> par(n), phase(n);
+        for (int i = 0; i < n; i++) {
+            tab[i] = solvers[i]->dev;
+            phase[i] = solvers[i]->phase;
+            par[i] = phase[i] == 0 ? solvers[i]->fpar : solvers[i]->ppar;
+        }
+        // (solve, cell) list in solve order, then interleaved so that each of
+        // the 8 XCDs gets a contiguous stretch of it
+        std::vector<int32_t> ls, lc;
+        ls.reserve(total);
+        lc.reserve(total);
+        for (int i = 0; i < n; i++)
+            for (int c = 0; c < solvers[i]->nc; c++) {
+                ls.push_back(i);
+                lc.push_back(c);
+            }
+        std::vector<int32_t> bs(nblocks, -1), bc(nblocks, 0);
+        const int64_t per = nblocks / 8;
+        for (int64_t blk = 0; blk < nblocks; blk++) {
+            const int64_t idx = (blk & 7) * per + (blk >> 3);
+            if (idx < total) {
+                bs[blk] = ls[idx];
+                bc[blk] = lc[idx];
+            }
+        }
+        char *w = b->work;
+        hipStream_t st = b->stream;
+        auto up = [&](size_t off, const void *src, size_t bytes) {
+            return hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, st);
+        };
+        hipError_t e = up(b->off_tab, tab.data(), tab.size() * sizeof(dvm::DevSolve));
+        if (!e) e = up(b->off_par, par.data(), par.size() * sizeof(int32_t));
+        if (!e) e = up(b->off_phase, phase.data(), phase.size() * sizeof(int32_t));
+        if (!e) e = up(b->off_bs, bs.data(), bs.size() * sizeof(int32_t));
+        if (!e) e = up(b->off_bc, bc.data(), bc.size() * sizeof(int32_t));
+        if (!e) e = hipStreamSynchronize(st);
+        if (e) {
+            delete b;
+            return fail(DVM_EHIP, "batch table upload: %s", hipGetErrorString(e));
+        }
+        for (int i = 0; i < n; i++) solvers[i]->in_batch = 1;
+        *out = b;
+        return DVM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DVM_ENOMEM, "out of host memory");
+    }
+}
+
+int dvm_batch_run(dvm_batch *b, int iters)
+{
+    if (!b) return fail(DVM_EINVAL, "null batch");
+    if (iters < 0) return fail(DVM_EINVAL, "iters < 0");
+    char *w = b->work;
+    for (int it = 0; it < iters; it++) {
+        HIP_OK(dvm::launch_batch_step(reinterpret_cast<const dvm::DevSolve *>(w + b->off_tab),
+                                      reinterpret_cast<const int32_t *>(w + b->off_bs),
+                                      reinterpret_cast<const int32_t *>(w + b->off_bc),
+                                      reinterpret_cast<const int32_t *>(w + b->off_par),
+                                      reinterpret_cast<const int32_t *>(w + b->off_phase), b->step + it, b->nblocks,
+                                      b->mixed, b->stream));
+    }
+    b->step += iters;
+    for (dvm_solver *s : b->members) {
+        if (s->phase == 0)
+            s->fpar ^= (iters & 1);
+        else
+            s->ppar ^= (iters & 1);
+        s->iters[s->phase] += iters;
+    }
+    return DVM_OK;
+}
+
+int dvm_batch_residual(dvm_batch *b, double *resid)
+{
+    if (!b || !resid) return fail(DVM_EINVAL, "null argument");
+    const int n = (int)b->members.size();
+    double *out = reinterpret_cast<double *>(b->work + b->off_out);
+    HIP_OK(dvm::launch_batch_residual(reinterpret_cast<const dvm::DevSolve *>(b->work + b->off_tab), n, out,
+                                      b->stream));
+    std::vector<double> v(2 * (size_t)n);
+    HIP_OK(hipMemcpyAsync(v.data(), out, v.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_OK(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < n; i++) resid[i] = rel_norm(v[2 * i], v[2 * i + 1]);
+    return DVM_OK;
+}
+
+void dvm_batch_destroy(dvm_batch *b)
+{
+    if (!b) return;
+    for (dvm_solver *s : b->members) s->in_batch = 0;
+    delete b;
+}
+
+}  // extern "C"

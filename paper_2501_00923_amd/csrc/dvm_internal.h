@@ -1,0 +1,76 @@
+// Internal interface between the host side of libdvm and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dvm {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxN1D = 128;       // max velocity nodes per direction
+constexpr int kMaxParams = 64;
+
+// Everything a kernel needs about one solve, passed by value (single solve)
+// or read from a device table (batched).  Pointers are device pointers into
+// the solver's workspace.  Storage type of f / phi / fd / gM is float in
+// mixed mode and double in FP64 mode.
+struct DevSolve {
+    int nc, nw, nv, n1, n2;
+    int topo;
+    int objective;
+    int mixed;
+    // mesh
+    const int32_t *nbr;      // [nc][4]
+    const double *S;         // [nc][4][2]
+    const double *vol;       // [nc]
+    const int32_t *wall_cell;// [nw]
+    const double *wall_A;    // [nw]
+    const double *wall_n;    // [nw][2]
+    const double *wall_a;    // [nw][2]
+    const double *wall_b;    // [nw][2]
+    const double *D;         // [nw] eq. (barg) normaliser
+    // velocity grid (1-D factors)
+    const double *vx, *vy, *wx, *wy;
+    const void *fd;          // [nv][2] far-field values (storage type)
+    const void *gM;          // [nv]    g_M1(1, 0, theta_w) (storage type)
+    // flow
+    double inv_tau_inf, u_inf, theta_w, cd_scale;
+    // primal state (ping-pong)
+    void *f[2];
+    double *W[2];            // [nc][4]
+    double *F[2];            // [nw]
+    double *red;             // [nc][2] per-cell residual partials of the last sweep
+    // adjoint state
+    void *phi[2];
+    double *aW[2];           // [nc][8]: What (4), rho_tau, pad
+    double *Phi[2];          // [nw]
+    const void *fstar;       // frozen primal f (= f[primal parity at adjoint init])
+    double *acoef;           // [nc][16] per-cell adjoint coefficients
+    // sensitivity / objective
+    double *Jl;              // [nw]
+    double *sens;            // [nw][5]: S_A, S_x(2), S_n(2)
+    double *dJdn;            // [nw][2]
+    double *jac;             // [nw][2][kMaxParams]
+    double *dJda;            // [kMaxParams]
+    double *out;             // [16] small scalar outputs
+};
+
+// launches (all on `st`); par = index of the current f / phi buffer
+hipError_t launch_primal_init(const DevSolve &d, hipStream_t st);
+hipError_t launch_primal_sweep(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_moments(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_residual(const DevSolve &d, int adjoint, hipStream_t st);
+hipError_t launch_objective(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st);
+hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
+
+// batched: table of DevSolve on the device, per-block (solve, cell) map,
+// per-solve buffer parity at batch creation and phase (0 primal, 1 adjoint);
+// step = sweeps done since batch creation
+hipError_t launch_batch_step(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_cell,
+                             const int32_t *par0, const int32_t *phase, int step, int nblocks, int mixed,
+                             hipStream_t st);
+hipError_t launch_batch_residual(const DevSolve *tab, int n, double *out, hipStream_t st);
+
+}  // namespace dvm

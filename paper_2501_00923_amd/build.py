@@ -10,8 +10,11 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdvm.so")
 SOURCES = [os.path.join(CSRC, "dvm_kernels.hip"), os.path.join(CSRC, "dvm_host.cpp")]
 
-# -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+# -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
+# -ffp-contract=off: every a*b+c is rounded as written, so a kernel body gives
+# the same bits whichever kernel inlines it (single solve vs batch) and the
+# velocity-face products v.S that decide upwinding round like the oracle's.
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 

@@ -117,7 +117,7 @@ int build_mesh(dvm_mesh &m)
         m.wall_cell[l] = c;
         const P2 a = node(i, 0), b = node(i + 1, 0);
         const double sx = m.S[8 * c], sy = m.S[8 * c + 1];
-        const double A = std::hypot(sx, sy);
+        const double A = std::sqrt(sx * sx + sy * sy);
         m.wA[l] = A;
         m.wn[2 * l] = sx / A;
         m.wn[2 * l + 1] = sy / A;
@@ -154,7 +154,7 @@ int rule_1d(int kind, int n, double vmax, double param, std::vector<double> &x, 
     case DVM_VG_MIDPOINT: {
         const double h = 2.0 * vmax / n;
         for (int a = 0; a < n; a++) {
-            x[a] = (a + 0.5 - 0.5 * n) * h;
+            x[a] = -vmax + (a + 0.5) * h;
             w[a] = h;
         }
         return DVM_OK;
@@ -163,7 +163,7 @@ int rule_1d(int kind, int n, double vmax, double param, std::vector<double> &x, 
         if (n % 4) return fail(DVM_EINVAL, "Newton-Cotes grid needs n divisible by 4 (got %d)", n);
         const int m = n - 1;                  // intervals
         const double h = 2.0 * vmax / m;
-        for (int a = 0; a < n; a++) x[a] = (a - 0.5 * m) * h;
+        for (int a = 0; a < n; a++) x[a] = -vmax + a * h;
         const int left = (m - 3) / 2;         // Simpson intervals left of the 3/8 panel
         auto simpson = [&](int from, int to) {
             for (int p = from; p < to; p += 2) {
@@ -184,8 +184,8 @@ int rule_1d(int kind, int n, double vmax, double param, std::vector<double> &x, 
         const double sp = std::sinh(p);
         auto map = [&](double s) { return vmax * std::sinh(p * s) / sp; };
         for (int a = 0; a < n; a++) {
-            const double s0 = -1.0 + 2.0 * a / n, s1 = -1.0 + 2.0 * (a + 1) / n;
-            x[a] = map(0.5 * (s0 + s1));
+            const double s0 = -1.0 + a * 2.0 / n, s1 = -1.0 + (a + 1) * 2.0 / n;
+            x[a] = map(-1.0 + (a + 0.5) * 2.0 / n);
             w[a] = map(s1) - map(s0);
         }
         return DVM_OK;

@@ -42,6 +42,21 @@ def _rel(a, b):
     return np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0)
 
 
+def _sens_scale(go):
+    """Common scale of the wall sensitivities: an element's S_x can be pure
+    rounding noise next to O(1) S_A (e.g. in free-molecular flow), so each
+    output is compared against the largest of them."""
+    return max(np.max(np.abs(go[k])) for k in ("S_A", "S_x", "S_n", "dJ_dnodes"))
+
+
+def _check_sens(gs, go, tol):
+    sc = _sens_scale(go)
+    for key in ("S_A", "S_x", "S_n", "dJ_dnodes"):
+        err = np.max(np.abs(gs[key] - go[key])) / sc
+        assert err <= tol, (key, err)
+    return max(np.max(np.abs(gs[k] - go[k])) / sc for k in ("S_A", "S_x", "S_n", "dJ_dnodes"))
+
+
 def _case(name):
     if name == "tiny_circle":
         return I.tiny_circle(Kn=1.0, Ma=0.5)
@@ -49,9 +64,9 @@ def _case(name):
         return I.tiny_naca(Kn=0.7, Ma=1.2)
     if name == "o24x12_v20":                       # nv = 400: one full pass + ragged tail
         return I.circle_case(24, 12, 20, 5.0, 0.3, 0.9, r_outer=6.0, stretch=1.15)
-    if name == "c_nc12":                           # nv = 144 < 256 threads
+    if name == "c_nc24":                           # nv = 576: two passes + a 64-velocity tail
         g = I.naca_cgrid(6, 10, 8, t=0.12, m=0.02, r_outer=5.0, h1=0.02)
-        return I.Workload("c_nc12", g, I.VGridSpec(I.VG_NEWTON_COTES, 12, 12, 5.0), I.FlowSpec(0.2, 0.8), 0)
+        return I.Workload("c_nc24", g, I.VGridSpec(I.VG_NEWTON_COTES, 24, 24, 5.0), I.FlowSpec(0.2, 0.8), 0)
     if name == "c_sinh36":                         # nv = 1296: five passes + tail
         g = I.naca_cgrid(4, 8, 6, t=0.10, m=0.0, r_outer=4.0, h1=0.02)
         return I.Workload("c_sinh36", g, I.VGridSpec(I.VG_SINH, 36, 36, 6.0, 2.0), I.FlowSpec(0.05, 2.0), 0)
@@ -61,12 +76,12 @@ def _case(name):
         w = I.tiny_naca(Kn=0.4, Ma=0.6)
         w.flow = I.FlowSpec(0.4, 0.6, Tw=1.6, objective=1)
         return w
-    if name == "one_row":                          # nj = 1: every cell touches wall and far field
+    if name == "one_row":                          # nj = 1, nv = 100 < 256 threads
         return I.circle_case(12, 1, 10, 5.0, 1.0, 0.5, r_outer=2.0, stretch=1.0)
     raise KeyError(name)
 
 
-CASES = ["tiny_circle", "tiny_naca", "o24x12_v20", "c_nc12", "c_sinh36", "freemol", "heat_hotwall", "one_row"]
+CASES = ["tiny_circle", "tiny_naca", "o24x12_v20", "c_nc24", "c_sinh36", "freemol", "heat_hotwall", "one_row"]
 
 
 def _run(wl, precision, n_primal, n_adjoint, n_params_jac=None):
@@ -100,8 +115,7 @@ def test_fp64_primal_adjoint_sensitivity_parity(name):
         assert abs(Cd - Jo / o.cd_scale()) <= 1e-10 * abs(Jo / o.cd_scale()) + 1e-14
     assert _rel(s.state_array(dvm.STATE_PHI), o.phi) <= 1e-11
     gs, go = s.wall_sensitivity(), o.wall_sensitivity()
-    for key in ("S_A", "S_x", "S_n", "dJ_dnodes"):
-        assert _rel(gs[key], go[key]) <= 1e-10, key
+    _check_sens(gs, go, 1e-10)
     jac = wl.grid.wall_jac
     if jac.shape[-1]:
         da = s.param_sensitivity(jac)
@@ -119,7 +133,7 @@ def test_mixed_precision_parity(name):
     Jo = o.objective()
     eJ = abs(J - Jo) / abs(Jo)
     gs, go = s.wall_sensitivity(), o.wall_sensitivity()
-    eS = max(_rel(gs[k], go[k]) for k in ("S_A", "S_x", "S_n", "dJ_dnodes"))
+    eS = _check_sens(gs, go, 1e-3)
     _say(f"[mixed] {name}: f {ef:.2e}  J {eJ:.2e}  sens {eS:.2e}")
     assert ef <= 2e-5 and eJ <= 2e-5 and eS <= 1e-3
 
@@ -160,6 +174,4 @@ def test_c2_naca_full_size_sampled():
     ps = s.state_array(dvm.STATE_PHI)[cells]
     assert _rel(fs, o.f[cells]) <= 1e-11
     assert _rel(ps, o.phi[cells]) <= 1e-11
-    gs, go = s.wall_sensitivity(), o.wall_sensitivity()
-    for key in ("S_A", "S_x", "S_n", "dJ_dnodes"):
-        assert _rel(gs[key], go[key]) <= 1e-10, key
+    _check_sens(s.wall_sensitivity(), o.wall_sensitivity(), 1e-10)

@@ -1,0 +1,144 @@
+"""Differentiable drag: shape parameters -> J with a hand-written adjoint.
+
+``ShapeCase`` describes a family of bodies (a grid generator taking the
+shape parameters alpha), a velocity grid, a flow state and solve options.
+``drag(alpha, case)`` returns J (FP64 scalar tensor); its backward runs the
+adjoint sweep and the wall sensitivity of the paper (Sec. 2.5 eq. sens_shape,
+Sec. 3.2) on the GPU and chains dJ/d(wall nodes) through d(wall nodes)/dalpha.
+
+The fixed-point adjoint needs only the converged primal state, so the
+forward keeps that state on the device; with ``offload=True`` it instead
+snapshots f to host memory and frees the device workspace between forward
+and backward (for memory pressure), and ``checkpoint_every`` keeps host
+snapshots of f during the primal solve (resume / inspection).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+import torch
+
+from . import dvm
+from . import inputs as I
+
+
+@dataclass
+class SolveOptions:
+    max_iter: int = 20000
+    tol: float = 1e-10
+    check_every: int = 50
+    adjoint_max_iter: int = 20000
+    adjoint_tol: float = 1e-10
+    fixed_iters: bool = False        # run exactly max_iter / adjoint_max_iter sweeps
+
+
+@dataclass
+class ShapeCase:
+    make_grid: Callable[[np.ndarray], I.GridInput]
+    vgrid: I.VGridSpec
+    flow: I.FlowSpec
+    precision: int = dvm.FP64
+    options: SolveOptions = field(default_factory=SolveOptions)
+    checkpoint_every: int = 0
+    offload: bool = False
+
+
+@dataclass
+class ForwardRecord:
+    iters: int = 0
+    resid: float = float("nan")
+    Cd: float = float("nan")
+    checkpoints: List[np.ndarray] = field(default_factory=list)
+    adjoint_iters: int = 0
+    adjoint_resid: float = float("nan")
+
+
+def _primal(case: ShapeCase, solver: dvm.Solver, rec: ForwardRecord):
+    o = case.options
+    if case.checkpoint_every > 0:
+        left = o.max_iter
+        while left > 0:
+            m = min(case.checkpoint_every, left)
+            it, r = solver.primal_iterate(m, 0.0 if o.fixed_iters else o.tol, m, raise_notconv=False)
+            rec.iters += it
+            rec.resid = r
+            left -= it
+            rec.checkpoints.append(solver.state_save(dvm.STATE_F))
+            if not o.fixed_iters and r < o.tol:
+                break
+    else:
+        if o.fixed_iters:
+            it, r = solver.primal_iterate(o.max_iter)
+        else:
+            it, r = solver.primal_iterate(o.max_iter, o.tol, o.check_every, raise_notconv=False)
+        rec.iters, rec.resid = it, r
+
+
+class _DragFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, alpha: torch.Tensor, case: ShapeCase, rec: ForwardRecord):
+        a = alpha.detach().cpu().double().numpy()
+        grid = case.make_grid(a)
+        solver = dvm.Solver(dvm.Mesh.from_grid(grid), dvm.VGrid.from_spec(case.vgrid), case.flow.Kn,
+                            case.flow.Ma, case.flow.Tw, case.flow.objective, case.precision, True)
+        solver.primal_init()
+        _primal(case, solver, rec)
+        J, Cd = solver.objective()
+        rec.Cd = Cd
+        ctx.case, ctx.rec, ctx.wall_jac = case, rec, grid.wall_jac
+        if case.offload:
+            ctx.f_host = solver.state_save(dvm.STATE_F)
+            solver.buffer = None          # release the device workspace
+            torch.cuda.empty_cache()
+        ctx.solver = solver
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        case, solver = ctx.case, ctx.solver
+        if case.offload:
+            solver.bind()
+            solver.state_load(dvm.STATE_F, ctx.f_host)
+        solver.adjoint_init()
+        o = case.options
+        if o.fixed_iters:
+            it, r = solver.adjoint_iterate(o.adjoint_max_iter)
+        else:
+            it, r = solver.adjoint_iterate(o.adjoint_max_iter, o.adjoint_tol, o.check_every, raise_notconv=False)
+        ctx.rec.adjoint_iters, ctx.rec.adjoint_resid = it, r
+        dJ = solver.param_sensitivity(ctx.wall_jac)
+        ctx.solver = None
+        return torch.from_numpy(dJ) * gJ.detach().cpu().double(), None, None
+
+
+def drag(alpha: torch.Tensor, case: ShapeCase, record: Optional[ForwardRecord] = None) -> torch.Tensor:
+    """J(alpha) with dJ/dalpha from the adjoint (paper-mode wall sensitivity)."""
+    rec = ForwardRecord() if record is None else record
+    return _DragFn.apply(alpha, case, rec)
+
+
+def naca_bspline_case(seed: int = 0, **kw) -> tuple:
+    """The differentiation workload: seed-drawn NACA thickness / camber,
+    192x96 C-grid, 48x48 Newton-Cotes grid on [-6, 6], Kn 0.5, Ma 2, 24
+    B-spline control-point offsets drawn N(0, 1e-3).  Returns (case, alpha0)."""
+    wl = I.c4_naca_bspline(seed)
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0.08, 0.16)
+    m = rng.uniform(0.0, 0.04)
+
+    def make(alpha):
+        return I.naca_cgrid(24, 72, 96, t=t, m=m, p=0.4,
+                            perturb={"kind": "bspline", "n_ctrl": 14, "amp": np.asarray(alpha)})
+    return ShapeCase(make, wl.vgrid, wl.flow, **kw), wl.grid.params.copy()
+
+
+def circle_fourier_case(ni=64, nj=32, nv=16, vmax=5.0, Kn=1.0, Ma=0.5, r_outer=10.0, stretch=1.1,
+                        **kw) -> tuple:
+    """Circle with 8 radial Fourier modes (a0..a3, b1..b4)."""
+    def make(alpha):
+        alpha = np.asarray(alpha)
+        return I.ogrid(ni, nj, r_outer, stretch, alpha[:4], alpha[4:])
+    return (ShapeCase(make, I.VGridSpec(I.VG_MIDPOINT, nv, nv, vmax), I.FlowSpec(Kn, Ma), **kw),
+            np.zeros(8))

@@ -54,11 +54,28 @@ struct dvm_mesh {
     std::vector<double> S;           // [nc][4][2]
     std::vector<double> vol;         // [nc]
     std::vector<double> wA, wn, wx, wa, wb;
+    std::vector<int32_t> order;      // [nc] sweep order
 };
 
 namespace {
 
 using P2 = std::array<double, 2>;
+
+// Sweep order: strips of kTileI columns, each walked outward in tiles of
+// kTileI x kTileJ cells (about what one XCD keeps in flight), row by row
+// inside a tile.  A cell's j-1 neighbour was then swept ~kTileI cells
+// earlier and its i+-1 neighbours in the same tile row.
+constexpr int kTileI = 16, kTileJ = 16;
+
+void build_order(dvm_mesh &m)
+{
+    m.order.clear();
+    m.order.reserve(m.nc);
+    for (int i0 = 0; i0 < m.ni; i0 += kTileI)
+        for (int j0 = 0; j0 < m.nj; j0 += kTileJ)
+            for (int j = j0; j < std::min(j0 + kTileJ, m.nj); j++)
+                for (int i = i0; i < std::min(i0 + kTileI, m.ni); i++) m.order.push_back(i + m.ni * j);
+}
 
 int build_mesh(dvm_mesh &m)
 {
@@ -128,6 +145,7 @@ int build_mesh(dvm_mesh &m)
         m.wx[2 * l] = 0.5 * (a[0] + b[0]);
         m.wx[2 * l + 1] = 0.5 * (a[1] + b[1]);
     }
+    build_order(m);
     return DVM_OK;
 }
 
@@ -203,7 +221,7 @@ int rule_1d(int kind, int n, double vmax, double param, std::vector<double> &x, 
 struct dvm_solver {
     // problem
     int topo, nc, nw, n1, n2, nv, mixed, want_adjoint, objective;
-    std::vector<int32_t> nbr, wall_cell;
+    std::vector<int32_t> nbr, wall_cell, order;
     std::vector<double> S, vol, wA, wn, wa, wb, D;
     std::vector<double> x1, w1, x2, w2;
     std::vector<double> fd;   // [nv][2]
@@ -211,7 +229,7 @@ struct dvm_solver {
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // workspace
     struct {
-        size_t nbr, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM;
+        size_t nbr, order, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM;
         size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, out, total;
     } off;
     char *base = nullptr;
@@ -239,6 +257,7 @@ void layout(dvm_solver &s)
     const size_t nc = s.nc, nw = s.nw, nv = s.nv, e = elt_bytes(s);
     auto &o = s.off;
     o.nbr = take(4 * nc * sizeof(int32_t));
+    o.order = take(nc * sizeof(int32_t));
     o.S = take(8 * nc * sizeof(double));
     o.vol = take(nc * sizeof(double));
     o.wall_cell = take(nw * sizeof(int32_t));
@@ -297,6 +316,7 @@ void fill_dev(dvm_solver &s)
     d.objective = s.objective;
     d.mixed = s.mixed;
     d.nbr = at<int32_t>(s, s.off.nbr);
+    d.order = at<int32_t>(s, s.off.order);
     d.S = at<double>(s, s.off.S);
     d.vol = at<double>(s, s.off.vol);
     d.wall_cell = at<int32_t>(s, s.off.wall_cell);
@@ -600,6 +620,7 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
         s->mixed = precision == DVM_MIXED;
         s->want_adjoint = want_adjoint ? 1 : 0;
         s->nbr = m->nbr;
+        s->order = m->order;
         s->wall_cell = m->wall_cell;
         s->S = m->S;
         s->vol = m->vol;
@@ -646,6 +667,7 @@ int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream
     const auto &o = s->off;
     int e = 0;
     e = e ? e : upload(*s, o.nbr, s->nbr.data(), s->nbr.size() * sizeof(int32_t));
+    e = e ? e : upload(*s, o.order, s->order.data(), s->order.size() * sizeof(int32_t));
     e = e ? e : upload(*s, o.S, s->S.data(), s->S.size() * sizeof(double));
     e = e ? e : upload(*s, o.vol, s->vol.data(), s->vol.size() * sizeof(double));
     e = e ? e : upload(*s, o.wall_cell, s->wall_cell.data(), s->wall_cell.size() * sizeof(int32_t));
@@ -957,7 +979,7 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         for (int i = 0; i < n; i++)
             for (int c = 0; c < solvers[i]->nc; c++) {
                 ls.push_back(i);
-                lc.push_back(c);
+                lc.push_back(solvers[i]->order[c]);
             }
         std::vector<int32_t> bs(nblocks, -1), bc(nblocks, 0);
         const int64_t per = nblocks / 8;

@@ -21,6 +21,7 @@ struct DevSolve {
     int mixed;
     // mesh
     const int32_t *nbr;      // [nc][4]
+    const int32_t *order;    // [nc] sweep order of the cells (L2-friendly tiles)
     const double *S;         // [nc][4][2]
     const double *vol;       // [nc]
     const int32_t *wall_cell;// [nw]

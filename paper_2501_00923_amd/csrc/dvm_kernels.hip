@@ -27,11 +27,15 @@ template <> struct Vec2<double> { using type = double2; };
 constexpr double kPi = 3.14159265358979323846;
 
 // Workgroups are handed to the 8 XCDs round-robin; give each XCD a
-// contiguous range of cells so that neighbour rows are reused from its L2.
-__device__ __forceinline__ int xcd_cell(int b, int n)
+// contiguous stretch of the sweep order (16x16-cell tiles marching along
+// grid strips) so that the upwind neighbour rows a workgroup reads were
+// fetched moments before by a workgroup of the same XCD and are still in
+// its L2.  Returns -1 for the padding workgroups of the last stretch.
+__device__ __forceinline__ int xcd_cell(const DevSolve &d, int b)
 {
-    const int per = (n + 7) >> 3;
-    return (b & 7) * per + (b >> 3);
+    const int per = (d.nc + 7) >> 3;
+    const int idx = (b & 7) * per + (b >> 3);
+    return idx < d.nc ? d.order[idx] : -1;
 }
 static inline int xcd_grid(int n) { return ((n + 7) >> 3) << 3; }
 
@@ -397,24 +401,24 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_primal_sweep(DevSolve d, int par)
 {
-    const int c = xcd_cell(blockIdx.x, d.nc);
-    if (c >= d.nc) return;
+    const int c = xcd_cell(d, blockIdx.x);
+    if (c < 0) return;
     primal_cell<T>(d, c, par);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_moments(DevSolve d, int par)
 {
-    const int c = xcd_cell(blockIdx.x, d.nc);
-    if (c >= d.nc) return;
+    const int c = xcd_cell(d, blockIdx.x);
+    if (c < 0) return;
     moments_cell<T>(d, c, par);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adjoint_sweep(DevSolve d, int par)
 {
-    const int c = xcd_cell(blockIdx.x, d.nc);
-    if (c >= d.nc) return;
+    const int c = xcd_cell(d, blockIdx.x);
+    if (c < 0) return;
     adjoint_cell<T>(d, c, par);
 }
 
@@ -766,8 +770,13 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
     else
         hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid(n)), dim3(kBlock), 0, st, static_cast<double *>(d.phi[0]), n);
     if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid((size_t)8 * d.nc)), dim3(kBlock), 0, st, d.aW[0], (size_t)8 * d.nc);
-    if (hipError_t e = hipGetLastError()) return e;
+    // both ping-pong buffers: slots 5..7 of each cell are padding that the
+    // sweep never writes, and checkpoints copy them
+    for (int p = 0; p < 2; p++) {
+        hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid((size_t)8 * d.nc)), dim3(kBlock), 0, st, d.aW[p],
+                           (size_t)8 * d.nc);
+        if (hipError_t e = hipGetLastError()) return e;
+    }
     DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_wall_phi0<T>, dim3(d.nw), dim3(kBlock), 0, st, d, 0));
     return hipGetLastError();
 }

@@ -226,10 +226,11 @@ struct dvm_solver {
     std::vector<double> x1, w1, x2, w2;
     std::vector<double> fd;   // [nv][2]
     std::vector<double> gM;   // [nv]
+    std::vector<double> gw2;  // [nv][2]
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // workspace
     struct {
-        size_t nbr, order, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM;
+        size_t nbr, order, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
         size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, out, total;
     } off;
     char *base = nullptr;
@@ -272,6 +273,7 @@ void layout(dvm_solver &s)
     o.wy = take(s.n2 * sizeof(double));
     o.fd = take(2 * nv * e);
     o.gM = take(nv * e);
+    o.gw2 = take(2 * nv * e);
     for (int p = 0; p < 2; p++) {
         o.f[p] = take(2 * nc * nv * e);
         o.W[p] = take(4 * nc * sizeof(double));
@@ -331,6 +333,7 @@ void fill_dev(dvm_solver &s)
     d.wy = at<double>(s, s.off.wy);
     d.fd = at<void>(s, s.off.fd);
     d.gM = at<void>(s, s.off.gM);
+    d.gw2 = at<void>(s, s.off.gw2);
     d.inv_tau_inf = s.inv_tau_inf;
     d.u_inf = s.u_inf;
     d.theta_w = s.theta_w;
@@ -448,6 +451,7 @@ int setup_flow(dvm_solver &s, const dvm_flow &fl)
     s.objective = fl.objective;
     s.fd.resize(2 * s.nv);
     s.gM.resize(s.nv);
+    s.gw2.resize(2 * s.nv);
     for (int b = 0; b < s.n2; b++) {
         for (int a = 0; a < s.n1; a++) {
             const int k = a + s.n1 * b;
@@ -457,6 +461,8 @@ int setup_flow(dvm_solver &s, const dvm_flow &fl)
             s.fd[2 * k + 1] = 0.5 * th_inf * g;
             const double r2 = s.x1[a] * s.x1[a] + s.x2[b] * s.x2[b];
             s.gM[k] = std::exp(-r2 / (2.0 * s.theta_w)) / (2.0 * kPi * s.theta_w);
+            s.gw2[2 * k] = s.gM[k];
+            s.gw2[2 * k + 1] = 0.5 * s.theta_w * s.gM[k];
         }
     }
     // eq. (barg): D_l = -sum_{v.n <= 0} w (v.n) g_M1(1, 0, T_w)
@@ -680,15 +686,18 @@ int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream
     e = e ? e : upload(*s, o.vy, s->x2.data(), s->x2.size() * sizeof(double));
     e = e ? e : upload(*s, o.wx, s->w1.data(), s->w1.size() * sizeof(double));
     e = e ? e : upload(*s, o.wy, s->w2.data(), s->w2.size() * sizeof(double));
-    std::vector<float> fdf, gMf;
+    std::vector<float> fdf, gMf, gw2f;
     if (s->mixed) {
         fdf = convert<float>(s->fd);
         gMf = convert<float>(s->gM);
+        gw2f = convert<float>(s->gw2);
         e = e ? e : upload(*s, o.fd, fdf.data(), fdf.size() * sizeof(float));
         e = e ? e : upload(*s, o.gM, gMf.data(), gMf.size() * sizeof(float));
+        e = e ? e : upload(*s, o.gw2, gw2f.data(), gw2f.size() * sizeof(float));
     } else {
         e = e ? e : upload(*s, o.fd, s->fd.data(), s->fd.size() * sizeof(double));
         e = e ? e : upload(*s, o.gM, s->gM.data(), s->gM.size() * sizeof(double));
+        e = e ? e : upload(*s, o.gw2, s->gw2.data(), s->gw2.size() * sizeof(double));
     }
     if (e) {
         s->base = nullptr;

@@ -34,6 +34,7 @@ struct DevSolve {
     const double *vx, *vy, *wx, *wy;
     const void *fd;          // [nv][2] far-field values (storage type)
     const void *gM;          // [nv]    g_M1(1, 0, theta_w) (storage type)
+    const void *gw2;         // [nv][2] (g_M1, theta_w/2 g_M1)(1, 0, theta_w) (storage type)
     // flow
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // primal state (ping-pong)

@@ -132,9 +132,19 @@ __device__ __forceinline__ void primal_cell(const DevSolve &d, int c, int par)
         S0x = d.S[8 * c];
         S0y = d.S[8 * c + 1];
     }
-    const T *__restrict__ gM = static_cast<const T *>(d.gM);
-    const T2 *__restrict__ fd = static_cast<const T2 *>(d.fd);
-    const T thw2 = (T)(0.5 * d.theta_w), th2 = (T)(0.5 * th);
+    // one source row per face, all of the storage pair type: the upwind
+    // cell's row, the far-field table, or the wall table (g_M1, theta_w/2 g_M1)
+    // scaled by F_l / D_l
+    const T2 *src[4];
+    T sc[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int n = nb[q];
+        src[q] = n >= 0 ? fin + (size_t)n * nv
+                        : static_cast<const T2 *>(n == -1 ? d.fd : d.gw2);
+        sc[q] = n <= -2 ? wcoef : (T)1;
+    }
+    const T th2 = (T)(0.5 * th);
     const T gc = (T)(rho / (2.0 * kPi * th)), VtT = (T)Vt;
     __syncthreads();
 
@@ -145,6 +155,12 @@ __device__ __forceinline__ void primal_cell(const DevSolve &d, int c, int par)
     for (int k = tid; k < nv; k += kBlock) {
         const double v1d = sm.vx[a], v2d = sm.vy[b];
         const T v1 = (T)v1d, v2 = (T)v2d;
+        // The face kind is uniform over the workgroup, only the sign of v.S
+        // differs between lanes: issue every face's source load first (no
+        // wait between them), then pick upwind values with selects.
+        T2 up[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) up[q] = src[q][k];
         T out = 0, in1 = 0, in2 = 0;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
@@ -152,22 +168,8 @@ __device__ __forceinline__ void primal_cell(const DevSolve &d, int c, int par)
             if (s > 0) {
                 out += s;
             } else {
-                T u_1, u_2;
-                const int n = nb[q];
-                if (n >= 0) {
-                    const T2 up = fin[(size_t)n * nv + k];
-                    u_1 = up.x;
-                    u_2 = up.y;
-                } else if (n == -1) {
-                    const T2 up = fd[k];
-                    u_1 = up.x;
-                    u_2 = up.y;
-                } else {
-                    u_1 = wcoef * gM[k];
-                    u_2 = thw2 * u_1;
-                }
-                in1 -= s * u_1;
-                in2 -= s * u_2;
+                in1 -= s * (sc[q] * up[q].x);
+                in2 -= s * (sc[q] * up[q].y);
             }
         }
         const T g1 = gc * sm.ex[a] * sm.ey[b];
@@ -305,6 +307,11 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
         S0y = d.S[8 * c + 1];
     }
     const T *__restrict__ gM = static_cast<const T *>(d.gM);
+    // downstream rows of interior faces; boundary faces read their own row
+    // (a valid address) and ignore it
+    const T2 *dsrc[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) dsrc[q] = pin + (size_t)(nb[q] >= 0 ? nb[q] : c) * nv;
     const int obj = d.objective;
     const T VT = (T)Vv, den0 = (T)(Vv * itau);
     const T Ct0 = (T)C0, Ct1 = (T)C1, Ct2 = (T)C2, Ct3 = (T)C3;
@@ -320,18 +327,23 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
         const double v1d = sm.vx[a], v2d = sm.vy[b];
         const T v1 = (T)v1d, v2 = (T)v2d;
         const T mj = (T)mJ_of(obj, v1d, v2d);
+        // all loads of this velocity first (own phi^n, frozen f, the
+        // downstream rows of interior faces), then the select-based update
+        const T2 old = pin[row + k];
+        const T2 fs = fst[row + k];
+        T2 dwn[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) dwn[q] = dsrc[q][k];
         T out = 0, a1 = 0, a2 = 0;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const T s = v1 * Sx[q] + v2 * Sy[q];
             if (s > 0) {
                 out += s;
-                const int n = nb[q];
-                if (n >= 0) {
-                    const T2 dn2 = pin[(size_t)n * nv + k];
-                    a1 += s * dn2.x;
-                    a2 += s * dn2.y;
-                } else if (n <= -2) {
+                if (nb[q] >= 0) {
+                    a1 += s * dwn[q].x;
+                    a2 += s * dwn[q].y;
+                } else if (nb[q] <= -2) {
                     a1 += s * (Phi_w - mj);
                 }
             }
@@ -342,14 +354,12 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
         T2 r;
         r.x = (a1 + VT * s1) / den;
         r.y = (a2 + VT * Ct3) / den;
-        const T2 old = pin[row + k];
         pout[row + k] = r;
         // epilogue accumulations from phi^{n+1}
         const double w = sm.wx[a] * sm.wy[b];
         const double p1 = (double)r.x, p2 = (double)r.y;
         const double g1 = (double)(gc * sm.ex[a] * sm.ey[b]);
         const double g2 = (double)(th2 * (T)g1);
-        const T2 fs = fst[row + k];
         const double q = p1 + 0.5 * th * p2;
         const double c1 = v1d - u1, c2 = v2d - u2;
         const double wg = w * g1;

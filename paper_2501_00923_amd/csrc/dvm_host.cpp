@@ -62,9 +62,13 @@ namespace {
 using P2 = std::array<double, 2>;
 
 // Sweep order: strips of kTileI columns, each walked outward in tiles of
-// kTileI x kTileJ cells (about what one XCD keeps in flight), row by row
-// inside a tile.  A cell's j-1 neighbour was then swept ~kTileI cells
-// earlier and its i+-1 neighbours in the same tile row.
+// kTileI x kTileJ cells, row by row inside a tile.  Workgroups in flight
+// stream their rows at about the same pace, so a neighbour row is reused
+// from L2 when its reader started shortly after its writer's neighbour
+// fetched it: a cell's j-1 neighbour starts kTileI workgroups earlier, its
+// i+-1 neighbours adjacent.  Measured on the 256x128 C-grid with 2304
+// velocities, 16 x 16 tiles fetch 1.2x the algorithmic bytes of a primal
+// sweep, 64 x 4 tiles 3.1x.
 constexpr int kTileI = 16, kTileJ = 16;
 
 void build_order(dvm_mesh &m)

@@ -178,7 +178,10 @@ __device__ __forceinline__ void primal_cell(const DevSolve &d, int c, int par)
         T2 r;
         r.x = (in1 + VtT * g1) / den;
         r.y = (in2 + VtT * g2) / den;
-        fout[row + k] = r;
+        // streaming stores: the new row is not read again in this sweep, so
+        // keep it from displacing the neighbour rows other workgroups reuse
+        __builtin_nontemporal_store(r.x, &fout[row + k].x);
+        __builtin_nontemporal_store(r.y, &fout[row + k].y);
         const double w = sm.wx[a] * sm.wy[b];
         const double f1 = (double)r.x, f2 = (double)r.y;
         const double wf1 = w * f1;
@@ -354,7 +357,8 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
         T2 r;
         r.x = (a1 + VT * s1) / den;
         r.y = (a2 + VT * Ct3) / den;
-        pout[row + k] = r;
+        __builtin_nontemporal_store(r.x, &pout[row + k].x);
+        __builtin_nontemporal_store(r.y, &pout[row + k].y);
         // epilogue accumulations from phi^{n+1}
         const double w = sm.wx[a] * sm.wy[b];
         const double p1 = (double)r.x, p2 = (double)r.y;

@@ -93,6 +93,112 @@ def run_gpu(wl, precision, sweeps, steps, warmup):
     return out
 
 
+def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every):
+    """Solve server on a seeded request stream (circle / NACA shapes, meshes
+    {64x32, 128x64, 256x128}, velocity grids {16^2, 32^2, 64^2} on [-6, 6],
+    Kn log-uniform in [1e-3, 10], Ma in [0.3, 2], half wanting the adjoint).
+    1) closed loop (all requests at t = 0), continuous batching, mixed
+       precision -> capacity (solves/s);
+    2) Poisson arrivals at 0.8 x capacity: continuous batching, mixed;
+    3) the same arrivals, one solve at a time, FP64.
+    Returns solves/s, p50/p99 latency of 2) and 3) and the drag agreement
+    between them."""
+    import numpy as np
+
+    from paper_2501_00923_amd import dvm
+    from paper_2501_00923_amd import inputs as I
+    from paper_2501_00923_amd import serving as S
+
+    cfg = S.ServeConfig(memory_budget=int(budget_gb * 2 ** 30), sweeps_per_check=check_every, tol=tol,
+                        adjoint_tol=tol, max_iter=cap)
+    reqs = I.poisson_stream(n_requests, 1.0, seed=seed)
+    t0 = time.perf_counter()
+    cap_run = S.serve(reqs, S.GpuBackend(dvm.MIXED), cfg, realtime=False)
+    capacity = cap_run["solves_per_s"]
+    print(f"[bench] serving capacity {capacity:.2f} solves/s ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    rate = 0.8 * capacity
+    stream = I.poisson_stream(n_requests, rate, seed=seed)
+    mix = S.serve(stream, S.GpuBackend(dvm.MIXED), cfg, realtime=True)
+    print(f"[bench] batched mixed: {mix['solves_per_s']:.2f} solves/s p50 {mix['p50_ms']:.0f} ms "
+          f"p99 {mix['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+    one = S.serve_one_at_a_time(stream, S.GpuBackend(dvm.FP64), cfg, realtime=True)
+    print(f"[bench] one-at-a-time fp64: {one['solves_per_s']:.2f} solves/s p50 {one['p50_ms']:.0f} ms "
+          f"p99 {one['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+    rel = []
+    for a, b in zip(mix["results"], one["results"]):
+        if a.status in ("ok", "notconv") and b.status in ("ok", "notconv") and b.J != 0:
+            rel.append(abs(a.J - b.J) / abs(b.J))
+    rel = np.array(rel)
+
+    def summary(o):
+        return {"solves_per_s": o["solves_per_s"], "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
+                "mean_ms": o["mean_ms"], "completed": o["completed"], "failed": o["failed"],
+                "hit_iteration_cap": o["notconv"], "wall_s": o["wall_s"], "peak_resident": o["peak_resident"],
+                "peak_GB": o["peak_bytes"] / 1e9}
+    return {"requests": n_requests, "seed": seed, "arrival_rate_per_s": rate, "capacity_solves_per_s": capacity,
+            "tol": tol, "iteration_cap": cap, "sweeps_per_check": check_every, "memory_budget_GB": budget_gb,
+            "batched_mixed": summary(mix), "one_at_a_time_fp64": summary(one),
+            "drag_rel_diff_mixed_vs_fp64": {"median": float(np.median(rel)) if len(rel) else None,
+                                            "max": float(rel.max()) if len(rel) else None},
+            "speedup_solves_per_s": mix["solves_per_s"] / one["solves_per_s"],
+            "p99_ratio_fp64_over_mixed": one["p99_ms"] / mix["p99_ms"]}
+
+
+def precision_sweep(sweeps, kns, oracle_check_sweeps=2):
+    """Mixed precision (FP32 f/phi, FP64 moments and integrals) against the
+    FP64 path on the NACA0012 256x128 C-grid with the 64x64 sinh velocity
+    grid, Ma 0.5, for each Kn: the same number of primal and adjoint sweeps
+    from the free stream on both; errors of J, C_d, the 16 bump
+    sensitivities and the cell moments.  The FP64 path is itself checked
+    against the oracle at full size after a few sweeps (first Kn)."""
+    import numpy as np
+
+    from paper_2501_00923_amd import dvm
+    from paper_2501_00923_amd import inputs as I
+
+    rows = []
+    for i, Kn in enumerate(kns):
+        wl = I.c3_naca_sinh(Kn)
+        res = {}
+        for prec, name in ((dvm.FP64, "fp64"), (dvm.MIXED, "mixed")):
+            s = dvm.Solver.from_workload(wl, precision=prec)
+            s.primal_init()
+            _, rp = s.primal_iterate(sweeps)
+            J, Cd = s.objective()
+            W = s.moments()
+            s.adjoint_init()
+            _, ra = s.adjoint_iterate(sweeps)
+            g = s.param_sensitivity(wl.grid.wall_jac)
+            res[name] = dict(J=J, Cd=Cd, W=W, g=g, rp=rp, ra=ra)
+            del s
+        a, b = res["mixed"], res["fp64"]
+        row = {"Kn": Kn, "sweeps": sweeps, "J_fp64": b["J"], "Cd_fp64": b["Cd"],
+               "primal_resid_fp64": b["rp"], "primal_resid_mixed": a["rp"],
+               "adjoint_resid_fp64": b["ra"], "adjoint_resid_mixed": a["ra"],
+               "J_rel_err": abs(a["J"] - b["J"]) / abs(b["J"]),
+               "Cd_rel_err": abs(a["Cd"] - b["Cd"]) / abs(b["Cd"]),
+               "dJda_rel_err": float(np.max(np.abs(a["g"] - b["g"])) / np.max(np.abs(b["g"]))),
+               "W_rel_err": float(np.max(np.abs(a["W"] - b["W"])) / np.max(np.abs(b["W"])))}
+        if i == 0 and oracle_check_sweeps > 0:
+            import oracle
+            nthreads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+            o = oracle.Problem.from_workload(wl, nthreads=nthreads)
+            o.primal_init()
+            o.primal_iterate(oracle_check_sweeps)
+            s = dvm.Solver.from_workload(wl, precision=dvm.FP64)
+            s.primal_init()
+            s.primal_iterate(oracle_check_sweeps)
+            row["fp64_vs_oracle_J_rel"] = abs(s.objective()[0] - o.objective()) / abs(o.objective())
+            row["fp64_vs_oracle_W_rel"] = float(np.max(np.abs(s.moments() - o.W)) / np.max(np.abs(o.W)))
+            row["oracle_check_sweeps"] = oracle_check_sweeps
+            del s, o
+        print(f"[precision] Kn {Kn:g}: J err {row['J_rel_err']:.2e}  dJ/da err {row['dJda_rel_err']:.2e}  "
+              f"W err {row['W_rel_err']:.2e}", file=sys.stderr, flush=True)
+        rows.append(row)
+    return rows
+
+
 def cpu_baseline(wl, seconds):
     import oracle
     nthreads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
@@ -134,6 +240,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests in the solve-server leg (0 skips it; 512 is the full stream)")
+    ap.add_argument("--serving-cap", type=int, default=1000, help="sweep cap per phase per request")
+    ap.add_argument("--serving-tol", type=float, default=1e-5)
+    ap.add_argument("--serving-seed", type=int, default=0)
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="print the per-Kn mixed-vs-FP64 error table (256x128 C-grid, 64x64 sinh grid) and exit")
+    ap.add_argument("--precision-sweeps", type=int, default=400)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -160,6 +274,10 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] calibration copy: {n} bytes read + {n} bytes written", file=sys.stderr, flush=True)
         del src, dst
+    if args.precision_sweep:
+        rows = precision_sweep(args.precision_sweeps, [1e-3, 1e-2, 0.1, 1.0, 10.0])
+        print(json.dumps({"precision_sweep": rows}))
+        return
     wl = I.c2_naca(seed=0)
     print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",
           file=sys.stderr, flush=True)
@@ -196,6 +314,11 @@ def main():
             "primal": {"kernel": "k_primal_sweep<double>", "achieved": b_pri / t_pri / 1e9,
                        "frac": b_pri / t_pri / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": r64["primal_sweep_ms"],
                        "algorithmic_bytes_per_launch": b_pri}}
+    serving = None
+    if args.serving_requests > 0:
+        print(f"[bench] serving leg: {args.serving_requests} requests", file=sys.stderr, flush=True)
+        serving = serving_leg(args.serving_requests, args.serving_seed, args.serving_cap, args.serving_tol,
+                              64.0, 20)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
@@ -210,7 +333,7 @@ def main():
                    "sweeps_per_step": {"primal": args.sweeps, "adjoint": args.sweeps},
                    "Kn": wl.flow.Kn, "Ma": wl.flow.Ma, "shape_params": int(wl.grid.wall_jac.shape[-1]),
                    "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed,
+        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "serving": serving,
         "J": r64["J"], "Cd": r64["Cd"],
     }
     print(json.dumps(line))

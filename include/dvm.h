@@ -175,12 +175,16 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
  * A batch groups n bound solvers of one precision.  Each member takes part
  * in the phase it is in when the batch is created: primal (after
  * dvm_primal_init) or adjoint (after dvm_adjoint_init).  dvm_batch_run
- * advances every member by `iters` Jacobi sweeps with one kernel launch
- * per sweep over all member cells, on the batch's stream; a member's sweep
+ * advances every member by `iters` Jacobi sweeps with two kernel launches
+ * per sweep (one over the cells of the primal-phase members, one over those
+ * of the adjoint-phase members), on the batch's stream.  Each launch gives
+ * every one of the 8 XCDs one eighth of every member, so a mix of mesh and
+ * velocity-grid sizes keeps all XCDs equally loaded.  A member's sweep
  * computes exactly what its own dvm_*_sweeps computes alone (same kernels,
  * same reduction order, no floating-point atomics).  work_dev is a
  * caller-owned device buffer of at least dvm_batch_work_bytes(n, total
- * cells) bytes holding the launch tables, written once at create (which
+ * cells of the n members) bytes, 256-byte aligned, holding the launch
+ * tables, written once at create (which
  * synchronises the stream).  While a batch exists its members must not be
  * re-initialised, re-bound, destroyed or swept outside the batch; destroy
  * the batch first.  Admission (which solves share a batch) is the caller's

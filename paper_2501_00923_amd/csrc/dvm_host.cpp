@@ -500,6 +500,7 @@ struct dvm_batch {
     char *work = nullptr;
     hipStream_t stream = nullptr;
     int nblocks = 0, mixed = 0;
+    int nb_primal = 0, nb_adjoint = 0;   // blocks of each phase's group (group 0 first)
     int step = 0;
     size_t off_tab = 0, off_par = 0, off_phase = 0, off_bs = 0, off_bc = 0, off_out = 0;
 };
@@ -940,7 +941,9 @@ size_t dvm_batch_work_bytes(int n, int64_t total_cells)
 {
     if (n <= 0 || total_cells < 0) return 0;
     size_t t;
-    batch_layout(n, (total_cells + 7) / 8 * 8, nullptr, &t);
+    // each member is split into 8 pieces of ceil(nc/8) cells: at most 7
+    // padding workgroups per member
+    batch_layout(n, total_cells + 7 * (int64_t)n, nullptr, &t);
     return t;
 }
 
@@ -950,7 +953,6 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
     if (!out || !solvers || n <= 0 || !work_dev) return fail(DVM_EINVAL, "null argument or empty batch");
     *out = nullptr;
     if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(DVM_EINVAL, "work buffer not 256-byte aligned");
-    int64_t total = 0;
     int mixed = -1;
     for (int i = 0; i < n; i++) {
         const dvm_solver *s = solvers[i];
@@ -960,9 +962,17 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         if (s->phase < 0) return fail(DVM_ESTATE, "member %d has no primal or adjoint phase", i);
         if (mixed < 0) mixed = s->mixed;
         if (mixed != s->mixed) return fail(DVM_EINVAL, "batch members must share one precision");
-        total += s->nc;
     }
-    const int64_t nblocks = (total + 7) / 8 * 8;
+    // two groups of workgroups, primal-phase members then adjoint-phase
+    // members. Workgroup b of a group runs on XCD b % 8, so within a group
+    // XCD x takes the x-th eighth (in the member's tile order) of every
+    // member: each XCD gets the same share of every member's work, whatever
+    // the mix of mesh and velocity-grid sizes, and its L2 sees contiguous
+    // tiles as in a single-solve sweep.
+    int64_t per_phase[2] = {0, 0};
+    for (int i = 0; i < n; i++) per_phase[solvers[i]->phase] += (solvers[i]->nc + 7) / 8;
+    const int64_t nbp = 8 * per_phase[0], nba = 8 * per_phase[1];
+    const int64_t nblocks = nbp + nba;
     if (nblocks > INT32_MAX) return fail(DVM_EINVAL, "batch too large");
     size_t need;
     try {
@@ -976,6 +986,8 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         b->work = static_cast<char *>(work_dev);
         b->stream = static_cast<hipStream_t>(hip_stream);
         b->nblocks = (int)nblocks;
+        b->nb_primal = (int)nbp;
+        b->nb_adjoint = (int)nba;
         b->mixed = mixed;
         std::vector<dvm::DevSolve> tab(n);
         std::vector<int32_t> par(n), phase(n);
@@ -984,24 +996,24 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
             phase[i] = solvers[i]->phase;
             par[i] = phase[i] == 0 ? solvers[i]->fpar : solvers[i]->ppar;
         }
-        // (solve, cell) list in solve order, then interleaved so that each of
-        // the 8 XCDs gets a contiguous stretch of it
-        std::vector<int32_t> ls, lc;
-        ls.reserve(total);
-        lc.reserve(total);
-        for (int i = 0; i < n; i++)
-            for (int c = 0; c < solvers[i]->nc; c++) {
-                ls.push_back(i);
-                lc.push_back(solvers[i]->order[c]);
-            }
         std::vector<int32_t> bs(nblocks, -1), bc(nblocks, 0);
-        const int64_t per = nblocks / 8;
-        for (int64_t blk = 0; blk < nblocks; blk++) {
-            const int64_t idx = (blk & 7) * per + (blk >> 3);
-            if (idx < total) {
-                bs[blk] = ls[idx];
-                bc[blk] = lc[idx];
+        int64_t base = 0;
+        for (int ph = 0; ph < 2; ph++) {
+            std::vector<int64_t> pos(8, 0);   // next slot of each XCD
+            for (int i = 0; i < n; i++) {
+                const dvm_solver *s = solvers[i];
+                if (s->phase != ph) continue;
+                const int64_t per = (s->nc + 7) / 8;
+                for (int x = 0; x < 8; x++) {
+                    const int64_t c0 = x * per, c1 = std::min<int64_t>(s->nc, c0 + per);
+                    for (int64_t c = c0; c < c1; c++, pos[x]++) {
+                        const int64_t blk = base + 8 * pos[x] + x;
+                        bs[blk] = i;
+                        bc[blk] = s->order[c];
+                    }
+                }
             }
+            base += 8 * per_phase[ph];
         }
         char *w = b->work;
         hipStream_t st = b->stream;
@@ -1031,13 +1043,14 @@ int dvm_batch_run(dvm_batch *b, int iters)
     if (!b) return fail(DVM_EINVAL, "null batch");
     if (iters < 0) return fail(DVM_EINVAL, "iters < 0");
     char *w = b->work;
+    const auto *tab = reinterpret_cast<const dvm::DevSolve *>(w + b->off_tab);
+    const auto *bs = reinterpret_cast<const int32_t *>(w + b->off_bs);
+    const auto *bc = reinterpret_cast<const int32_t *>(w + b->off_bc);
+    const auto *par = reinterpret_cast<const int32_t *>(w + b->off_par);
     for (int it = 0; it < iters; it++) {
-        HIP_OK(dvm::launch_batch_step(reinterpret_cast<const dvm::DevSolve *>(w + b->off_tab),
-                                      reinterpret_cast<const int32_t *>(w + b->off_bs),
-                                      reinterpret_cast<const int32_t *>(w + b->off_bc),
-                                      reinterpret_cast<const int32_t *>(w + b->off_par),
-                                      reinterpret_cast<const int32_t *>(w + b->off_phase), b->step + it, b->nblocks,
-                                      b->mixed, b->stream));
+        HIP_OK(dvm::launch_batch(tab, bs, bc, par, b->step + it, b->nb_primal, b->mixed, 0, b->stream));
+        HIP_OK(dvm::launch_batch(tab, bs + b->nb_primal, bc + b->nb_primal, par, b->step + it, b->nb_adjoint,
+                                 b->mixed, 1, b->stream));
     }
     b->step += iters;
     for (dvm_solver *s : b->members) {

@@ -68,11 +68,10 @@ hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
 
 // batched: table of DevSolve on the device, per-block (solve, cell) map,
-// per-solve buffer parity at batch creation and phase (0 primal, 1 adjoint);
-// step = sweeps done since batch creation
-hipError_t launch_batch_step(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_cell,
-                             const int32_t *par0, const int32_t *phase, int step, int nblocks, int mixed,
-                             hipStream_t st);
+// per-solve buffer parity at batch creation; step = sweeps done since batch
+// creation; adjoint selects the kernel of that phase
+hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_cell,
+                        const int32_t *par0, int step, int nblocks, int mixed, int adjoint, hipStream_t st);
 hipError_t launch_batch_residual(const DevSolve *tab, int n, double *out, hipStream_t st);
 
 }  // namespace dvm

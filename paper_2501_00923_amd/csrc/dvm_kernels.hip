@@ -436,21 +436,25 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_sweep(DevSolve d, int par)
     adjoint_cell<T>(d, c, par);
 }
 
-// one sweep of every member of a batch; a block owns one (solve, cell)
+// one sweep of the primal-phase (or adjoint-phase) members of a batch; a
+// block owns one (solve, cell).  The two phases are separate kernels so
+// that each gets the occupancy of its own register footprint.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_batch_step(const DevSolve *tab, const int32_t *blk_solve,
-                                                       const int32_t *blk_cell, const int32_t *par0,
-                                                       const int32_t *phase, int step)
+__global__ __launch_bounds__(kBlock) void k_batch_primal(const DevSolve *tab, const int32_t *blk_solve,
+                                                         const int32_t *blk_cell, const int32_t *par0, int step)
 {
     const int s = blk_solve[blockIdx.x];
     if (s < 0) return;
-    const DevSolve &d = tab[s];
-    const int c = blk_cell[blockIdx.x];
-    const int par = (par0[s] + step) & 1;
-    if (phase[s] == 0)
-        primal_cell<T>(d, c, par);
-    else
-        adjoint_cell<T>(d, c, par);
+    primal_cell<T>(tab[s], blk_cell[blockIdx.x], (par0[s] + step) & 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_batch_adjoint(const DevSolve *tab, const int32_t *blk_solve,
+                                                          const int32_t *blk_cell, const int32_t *par0, int step)
+{
+    const int s = blk_solve[blockIdx.x];
+    if (s < 0) return;
+    adjoint_cell<T>(tab[s], blk_cell[blockIdx.x], (par0[s] + step) & 1);
 }
 
 // f = far-field Maxwellian everywhere (storage type)
@@ -809,12 +813,16 @@ hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_cell,
-                             const int32_t *par0, const int32_t *phase, int step, int nblocks, int mixed,
-                             hipStream_t st)
+hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_cell,
+                        const int32_t *par0, int step, int nblocks, int mixed, int adjoint, hipStream_t st)
 {
-    DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_step<T>, dim3(nblocks), dim3(kBlock), 0, st, tab, blk_solve,
-                                           blk_cell, par0, phase, step));
+    if (nblocks <= 0) return hipSuccess;
+    if (adjoint)
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_adjoint<T>, dim3(nblocks), dim3(kBlock), 0, st, tab,
+                                               blk_solve, blk_cell, par0, step));
+    else
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_primal<T>, dim3(nblocks), dim3(kBlock), 0, st, tab,
+                                               blk_solve, blk_cell, par0, step));
     return hipGetLastError();
 }
 

@@ -54,31 +54,43 @@ struct dvm_mesh {
     std::vector<double> S;           // [nc][4][2]
     std::vector<double> vol;         // [nc]
     std::vector<double> wA, wn, wx, wa, wb;
-    std::vector<int32_t> order;      // [nc] sweep order
+    std::vector<int32_t> perm;       // [nc] device (storage) number of each cell
+    std::vector<int32_t> pstart;     // [np + 1] first device cell of each patch
 };
 
 namespace {
 
 using P2 = std::array<double, 2>;
 
-// Sweep order: strips of kTileI columns, each walked outward in tiles of
-// kTileI x kTileJ cells, row by row inside a tile.  Workgroups in flight
-// stream their rows at about the same pace, so a neighbour row is reused
-// from L2 when its reader started shortly after its writer's neighbour
-// fetched it: a cell's j-1 neighbour starts kTileI workgroups earlier, its
-// i+-1 neighbours adjacent.  Measured on the 256x128 C-grid with 2304
-// velocities, 16 x 16 tiles fetch 1.2x the algorithmic bytes of a primal
-// sweep, 64 x 4 tiles 3.1x.
-constexpr int kTileI = 16, kTileJ = 16;
-
-void build_order(dvm_mesh &m)
+// Sweep and storage order: strips of kTileI columns, each walked outward in
+// tiles of kTileI x kTileJ cells; a tile is cut into patches of kPatchI x
+// kPatchJ cells (one workgroup of a sweep each) taken row by row, and a
+// patch's cells are numbered row by row.  Neighbour rows that a patch reads
+// from outside itself belong to patches processed shortly before or after
+// it on the same XCD (still in its L2), and the rows of the workgroups in
+// flight are contiguous in memory.
+void build_patches(dvm_mesh &m)
 {
-    m.order.clear();
-    m.order.reserve(m.nc);
-    for (int i0 = 0; i0 < m.ni; i0 += kTileI)
-        for (int j0 = 0; j0 < m.nj; j0 += kTileJ)
-            for (int j = j0; j < std::min(j0 + kTileJ, m.nj); j++)
-                for (int i = i0; i < std::min(i0 + kTileI, m.ni); i++) m.order.push_back(i + m.ni * j);
+    using dvm::kPatchI;
+    using dvm::kPatchJ;
+    using dvm::kTileI;
+    using dvm::kTileJ;
+    m.perm.assign(m.nc, -1);
+    m.pstart.clear();
+    int32_t next = 0;
+    for (int i0 = 0; i0 < m.ni; i0 += kTileI) {
+        const int i1 = std::min(i0 + kTileI, m.ni);
+        for (int j0 = 0; j0 < m.nj; j0 += kTileJ) {
+            const int j1 = std::min(j0 + kTileJ, m.nj);
+            for (int pj = j0; pj < j1; pj += kPatchJ)
+                for (int pi = i0; pi < i1; pi += kPatchI) {
+                    m.pstart.push_back(next);
+                    for (int j = pj; j < std::min(pj + kPatchJ, j1); j++)
+                        for (int i = pi; i < std::min(pi + kPatchI, i1); i++) m.perm[i + m.ni * j] = next++;
+                }
+        }
+    }
+    m.pstart.push_back(next);
 }
 
 int build_mesh(dvm_mesh &m)
@@ -149,7 +161,7 @@ int build_mesh(dvm_mesh &m)
         m.wx[2 * l] = 0.5 * (a[0] + b[0]);
         m.wx[2 * l + 1] = 0.5 * (a[1] + b[1]);
     }
-    build_order(m);
+    build_patches(m);
     return DVM_OK;
 }
 
@@ -224,8 +236,9 @@ int rule_1d(int kind, int n, double vmax, double param, std::vector<double> &x, 
 // ---------------------------------------------------------------------------
 struct dvm_solver {
     // problem
-    int topo, nc, nw, n1, n2, nv, mixed, want_adjoint, objective;
-    std::vector<int32_t> nbr, wall_cell, order;
+    int topo, nc, nw, np, n1, n2, nv, mixed, want_adjoint, objective;
+    // mesh in device numbering (cell c of the mesh is device cell perm[c])
+    std::vector<int32_t> nbr, wall_cell, perm, pstart;
     std::vector<double> S, vol, wA, wn, wa, wb, D;
     std::vector<double> x1, w1, x2, w2;
     std::vector<double> fd;   // [nv][2]
@@ -234,7 +247,7 @@ struct dvm_solver {
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // workspace
     struct {
-        size_t nbr, order, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
+        size_t nbr, patch, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
         size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, out, total;
     } off;
     char *base = nullptr;
@@ -262,7 +275,7 @@ void layout(dvm_solver &s)
     const size_t nc = s.nc, nw = s.nw, nv = s.nv, e = elt_bytes(s);
     auto &o = s.off;
     o.nbr = take(4 * nc * sizeof(int32_t));
-    o.order = take(nc * sizeof(int32_t));
+    o.patch = take((s.np + 1) * sizeof(int32_t));
     o.S = take(8 * nc * sizeof(double));
     o.vol = take(nc * sizeof(double));
     o.wall_cell = take(nw * sizeof(int32_t));
@@ -318,11 +331,12 @@ void fill_dev(dvm_solver &s)
     d.nv = s.nv;
     d.n1 = s.n1;
     d.n2 = s.n2;
+    d.np = s.np;
     d.topo = s.topo;
     d.objective = s.objective;
     d.mixed = s.mixed;
     d.nbr = at<int32_t>(s, s.off.nbr);
-    d.order = at<int32_t>(s, s.off.order);
+    d.patch = at<int32_t>(s, s.off.patch);
     d.S = at<double>(s, s.off.S);
     d.vol = at<double>(s, s.off.vol);
     d.wall_cell = at<int32_t>(s, s.off.wall_cell);
@@ -372,6 +386,17 @@ int read_back(dvm_solver &s, const double *dev_src, double *dst, size_t n)
     HIP_OK(hipMemcpyAsync(dst, dev_src, n * sizeof(double), hipMemcpyDeviceToHost, s.stream));
     HIP_OK(hipStreamSynchronize(s.stream));
     return DVM_OK;
+}
+
+// Per-cell rows of `bytes` bytes between device numbering and mesh numbering.
+void rows_to_mesh(const dvm_solver &s, const char *dev_rows, char *mesh_rows, size_t bytes)
+{
+    for (int c = 0; c < s.nc; c++) std::memcpy(mesh_rows + (size_t)c * bytes, dev_rows + (size_t)s.perm[c] * bytes, bytes);
+}
+
+void rows_to_dev(const dvm_solver &s, const char *mesh_rows, char *dev_rows, size_t bytes)
+{
+    for (int c = 0; c < s.nc; c++) std::memcpy(dev_rows + (size_t)s.perm[c] * bytes, mesh_rows + (size_t)c * bytes, bytes);
 }
 
 double rel_norm(double num, double den)
@@ -630,11 +655,23 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
         s->nv = g->n1 * g->n2;
         s->mixed = precision == DVM_MIXED;
         s->want_adjoint = want_adjoint ? 1 : 0;
-        s->nbr = m->nbr;
-        s->order = m->order;
-        s->wall_cell = m->wall_cell;
-        s->S = m->S;
-        s->vol = m->vol;
+        s->np = (int)m->pstart.size() - 1;
+        s->perm = m->perm;
+        s->pstart = m->pstart;
+        s->nbr.resize(m->nbr.size());
+        s->S.resize(m->S.size());
+        s->vol.resize(m->vol.size());
+        for (int c = 0; c < m->nc; c++) {
+            const int32_t dc = m->perm[c];
+            for (int q = 0; q < 4; q++) {
+                const int32_t n = m->nbr[4 * c + q];
+                s->nbr[4 * dc + q] = n >= 0 ? m->perm[n] : n;
+            }
+            for (int e = 0; e < 8; e++) s->S[8 * dc + e] = m->S[8 * c + e];
+            s->vol[dc] = m->vol[c];
+        }
+        s->wall_cell.resize(m->nw);
+        for (int l = 0; l < m->nw; l++) s->wall_cell[l] = m->perm[m->wall_cell[l]];
         s->wA = m->wA;
         s->wn = m->wn;
         s->wa = m->wa;
@@ -678,7 +715,7 @@ int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream
     const auto &o = s->off;
     int e = 0;
     e = e ? e : upload(*s, o.nbr, s->nbr.data(), s->nbr.size() * sizeof(int32_t));
-    e = e ? e : upload(*s, o.order, s->order.data(), s->order.size() * sizeof(int32_t));
+    e = e ? e : upload(*s, o.patch, s->pstart.data(), s->pstart.size() * sizeof(int32_t));
     e = e ? e : upload(*s, o.S, s->S.data(), s->S.size() * sizeof(double));
     e = e ? e : upload(*s, o.vol, s->vol.data(), s->vol.size() * sizeof(double));
     e = e ? e : upload(*s, o.wall_cell, s->wall_cell.data(), s->wall_cell.size() * sizeof(int32_t));
@@ -763,7 +800,14 @@ int dvm_read_moments(dvm_solver *s, double *W)
     if (s->phase < 0) return fail(DVM_ESTATE, "no primal state");
     if (!W) return fail(DVM_EINVAL, "null output");
     const int par = s->phase == 1 ? s->frozen_fpar : s->fpar;
-    return read_back(*s, s->dev.W[par], W, (size_t)4 * s->nc);
+    try {
+        std::vector<double> dev((size_t)4 * s->nc);
+        if (int e = read_back(*s, s->dev.W[par], dev.data(), dev.size())) return e;
+        rows_to_mesh(*s, reinterpret_cast<const char *>(dev.data()), reinterpret_cast<char *>(W), 4 * sizeof(double));
+    } catch (const std::bad_alloc &) {
+        return fail(DVM_ENOMEM, "out of host memory");
+    }
+    return DVM_OK;
 }
 
 int dvm_adjoint_init(dvm_solver *s)
@@ -857,21 +901,27 @@ int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes)
     if (int e = check_bound(s)) return e;
     const size_t need = dvm_state_bytes(s, which);
     if (!need || !host_dst || bytes < need) return fail(DVM_EINVAL, "bad state kind or buffer size");
+    if (which == DVM_STATE_F && s->phase < 0) return fail(DVM_ESTATE, "no primal state");
+    if (which == DVM_STATE_PHI && s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
     char *dst = static_cast<char *>(host_dst);
-    const size_t row = (size_t)s->nc * s->nv * 2 * elt_bytes(*s);
-    if (which == DVM_STATE_F) {
-        if (s->phase < 0) return fail(DVM_ESTATE, "no primal state");
-        const int par = s->phase == 1 ? s->frozen_fpar : s->fpar;
-        HIP_OK(hipMemcpyAsync(dst, s->dev.f[par], row, hipMemcpyDeviceToHost, s->stream));
-    } else {
-        if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
-        HIP_OK(hipMemcpyAsync(dst, s->dev.phi[s->ppar], row, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(hipMemcpyAsync(dst + row, s->dev.aW[s->ppar], (size_t)8 * s->nc * sizeof(double),
-                              hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(hipMemcpyAsync(dst + row + (size_t)8 * s->nc * sizeof(double), s->dev.Phi[s->ppar],
-                              (size_t)s->nw * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    const size_t rowb = (size_t)s->nv * 2 * elt_bytes(*s), all = rowb * s->nc, awb = 8 * sizeof(double);
+    try {
+        std::vector<char> tmp(all + (which == DVM_STATE_PHI ? awb * s->nc : 0));
+        if (which == DVM_STATE_F) {
+            const int par = s->phase == 1 ? s->frozen_fpar : s->fpar;
+            HIP_OK(hipMemcpyAsync(tmp.data(), s->dev.f[par], all, hipMemcpyDeviceToHost, s->stream));
+        } else {
+            HIP_OK(hipMemcpyAsync(tmp.data(), s->dev.phi[s->ppar], all, hipMemcpyDeviceToHost, s->stream));
+            HIP_OK(hipMemcpyAsync(tmp.data() + all, s->dev.aW[s->ppar], awb * s->nc, hipMemcpyDeviceToHost, s->stream));
+            HIP_OK(hipMemcpyAsync(dst + all + awb * s->nc, s->dev.Phi[s->ppar], (size_t)s->nw * sizeof(double),
+                                  hipMemcpyDeviceToHost, s->stream));
+        }
+        HIP_OK(hipStreamSynchronize(s->stream));
+        rows_to_mesh(*s, tmp.data(), dst, rowb);
+        if (which == DVM_STATE_PHI) rows_to_mesh(*s, tmp.data() + all, dst + all, awb);
+    } catch (const std::bad_alloc &) {
+        return fail(DVM_ENOMEM, "out of host memory");
     }
-    HIP_OK(hipStreamSynchronize(s->stream));
     return DVM_OK;
 }
 
@@ -880,23 +930,30 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
     if (int e = check_bound(s)) return e;
     const size_t need = dvm_state_bytes(s, which);
     if (!need || !host_src || bytes < need) return fail(DVM_EINVAL, "bad state kind or buffer size");
+    if (which == DVM_STATE_PHI && s->phase != 1)
+        return fail(DVM_ESTATE, "no adjoint phase to load into (call dvm_adjoint_init)");
     const char *src = static_cast<const char *>(host_src);
-    const size_t row = (size_t)s->nc * s->nv * 2 * elt_bytes(*s);
-    if (which == DVM_STATE_F) {
-        s->fpar = 0;
-        HIP_OK(hipMemcpyAsync(s->dev.f[0], src, row, hipMemcpyHostToDevice, s->stream));
-        HIP_OK(dvm::launch_moments(s->dev, 0, s->stream));
-        s->phase = 0;
-        s->iters[0] = s->iters[1] = 0;
-    } else {
-        if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint phase to load into (call dvm_adjoint_init)");
-        HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], src, row, hipMemcpyHostToDevice, s->stream));
-        HIP_OK(hipMemcpyAsync(s->dev.aW[s->ppar], src + row, (size_t)8 * s->nc * sizeof(double),
-                              hipMemcpyHostToDevice, s->stream));
-        HIP_OK(hipMemcpyAsync(s->dev.Phi[s->ppar], src + row + (size_t)8 * s->nc * sizeof(double),
-                              (size_t)s->nw * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    const size_t rowb = (size_t)s->nv * 2 * elt_bytes(*s), all = rowb * s->nc, awb = 8 * sizeof(double);
+    try {
+        std::vector<char> tmp(all + (which == DVM_STATE_PHI ? awb * s->nc : 0));
+        rows_to_dev(*s, src, tmp.data(), rowb);
+        if (which == DVM_STATE_F) {
+            s->fpar = 0;
+            HIP_OK(hipMemcpyAsync(s->dev.f[0], tmp.data(), all, hipMemcpyHostToDevice, s->stream));
+            HIP_OK(dvm::launch_moments(s->dev, 0, s->stream));
+            s->phase = 0;
+            s->iters[0] = s->iters[1] = 0;
+        } else {
+            rows_to_dev(*s, src + all, tmp.data() + all, awb);
+            HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], tmp.data(), all, hipMemcpyHostToDevice, s->stream));
+            HIP_OK(hipMemcpyAsync(s->dev.aW[s->ppar], tmp.data() + all, awb * s->nc, hipMemcpyHostToDevice, s->stream));
+            HIP_OK(hipMemcpyAsync(s->dev.Phi[s->ppar], src + all + awb * s->nc, (size_t)s->nw * sizeof(double),
+                                  hipMemcpyHostToDevice, s->stream));
+        }
+        HIP_OK(hipStreamSynchronize(s->stream));   // tmp must outlive the copies
+    } catch (const std::bad_alloc &) {
+        return fail(DVM_ENOMEM, "out of host memory");
     }
-    HIP_OK(hipStreamSynchronize(s->stream));
     return DVM_OK;
 }
 
@@ -941,8 +998,8 @@ size_t dvm_batch_work_bytes(int n, int64_t total_cells)
 {
     if (n <= 0 || total_cells < 0) return 0;
     size_t t;
-    // each member is split into 8 pieces of ceil(nc/8) cells: at most 7
-    // padding workgroups per member
+    // one workgroup per patch (at most one per cell), each member split
+    // into 8 pieces of ceil(patches/8): at most 7 padding workgroups per member
     batch_layout(n, total_cells + 7 * (int64_t)n, nullptr, &t);
     return t;
 }
@@ -964,13 +1021,13 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         if (mixed != s->mixed) return fail(DVM_EINVAL, "batch members must share one precision");
     }
     // two groups of workgroups, primal-phase members then adjoint-phase
-    // members. Workgroup b of a group runs on XCD b % 8, so within a group
-    // XCD x takes the x-th eighth (in the member's tile order) of every
-    // member: each XCD gets the same share of every member's work, whatever
-    // the mix of mesh and velocity-grid sizes, and its L2 sees contiguous
-    // tiles as in a single-solve sweep.
+    // members, one workgroup per (member, patch). Workgroup b of a group
+    // runs on XCD b % 8, so within a group XCD x takes the x-th eighth (in
+    // sweep order) of every member's patches: each XCD gets the same share
+    // of every member's work, whatever the mix of mesh and velocity-grid
+    // sizes, and its L2 sees contiguous tiles as in a single-solve sweep.
     int64_t per_phase[2] = {0, 0};
-    for (int i = 0; i < n; i++) per_phase[solvers[i]->phase] += (solvers[i]->nc + 7) / 8;
+    for (int i = 0; i < n; i++) per_phase[solvers[i]->phase] += (solvers[i]->np + 7) / 8;
     const int64_t nbp = 8 * per_phase[0], nba = 8 * per_phase[1];
     const int64_t nblocks = nbp + nba;
     if (nblocks > INT32_MAX) return fail(DVM_EINVAL, "batch too large");
@@ -1003,13 +1060,13 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
             for (int i = 0; i < n; i++) {
                 const dvm_solver *s = solvers[i];
                 if (s->phase != ph) continue;
-                const int64_t per = (s->nc + 7) / 8;
+                const int64_t per = (s->np + 7) / 8;
                 for (int x = 0; x < 8; x++) {
-                    const int64_t c0 = x * per, c1 = std::min<int64_t>(s->nc, c0 + per);
-                    for (int64_t c = c0; c < c1; c++, pos[x]++) {
+                    const int64_t p0 = x * per, p1 = std::min<int64_t>(s->np, p0 + per);
+                    for (int64_t p = p0; p < p1; p++, pos[x]++) {
                         const int64_t blk = base + 8 * pos[x] + x;
                         bs[blk] = i;
-                        bc[blk] = s->order[c];
+                        bc[blk] = (int32_t)p;
                     }
                 }
             }

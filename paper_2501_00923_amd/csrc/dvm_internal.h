@@ -6,9 +6,17 @@
 
 namespace dvm {
 
-constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kBlock = 256;        // threads per workgroup of the per-cell and per-element kernels
+constexpr int kWave = 64;          // wavefront width
 constexpr int kMaxN1D = 128;       // max velocity nodes per direction
 constexpr int kMaxParams = 64;
+
+// The sweeps give each workgroup a patch of kPatchI x kPatchJ cells, one
+// wave per cell; patches tile kTileI x kTileJ tiles, which follow each
+// other along strips of kTileI columns.  Cells are stored (and numbered on
+// the device) in that order, patch after patch.
+constexpr int kPatchI = 2, kPatchJ = 2, kPatchCells = kPatchI * kPatchJ;
+constexpr int kTileI = 16, kTileJ = 16;
 
 // Everything a kernel needs about one solve, passed by value (single solve)
 // or read from a device table (batched).  Pointers are device pointers into
@@ -16,12 +24,13 @@ constexpr int kMaxParams = 64;
 // mixed mode and double in FP64 mode.
 struct DevSolve {
     int nc, nw, nv, n1, n2;
+    int np;                  // patches
     int topo;
     int objective;
     int mixed;
     // mesh
-    const int32_t *nbr;      // [nc][4]
-    const int32_t *order;    // [nc] sweep order of the cells (L2-friendly tiles)
+    const int32_t *nbr;      // [nc][4] (device cell numbering)
+    const int32_t *patch;    // [np + 1] first cell of each patch; patch p = cells [patch[p], patch[p+1])
     const double *S;         // [nc][4][2]
     const double *vol;       // [nc]
     const int32_t *wall_cell;// [nw]
@@ -67,10 +76,10 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st);
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
 
-// batched: table of DevSolve on the device, per-block (solve, cell) map,
+// batched: table of DevSolve on the device, per-block (solve, patch) map,
 // per-solve buffer parity at batch creation; step = sweeps done since batch
 // creation; adjoint selects the kernel of that phase
-hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_cell,
+hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_patch,
                         const int32_t *par0, int step, int nblocks, int mixed, int adjoint, hipStream_t st);
 hipError_t launch_batch_residual(const DevSolve *tab, int n, double *out, hipStream_t st);
 

@@ -3,11 +3,19 @@
 // Layout: f and phi are [cell][velocity][2] (the two reduced distributions
 // of Sec. 2.2 interleaved), so one cell's row of 2*nv values is contiguous
 // and a wave64 reading consecutive velocities streams whole cache lines.
-// One workgroup of 256 threads owns one cell for a sweep: it reads the
-// cell's own row and the upwind rows of its (at most four) neighbours,
-// writes the new row, and reduces the FP64 velocity moments of the new row
-// in its epilogue (wave shuffles, then the 4 wave partials through LDS), so
-// the next sweep finds W^{n+1} ready and f is streamed once per sweep.
+// Cells are numbered on the device in sweep order (see dvm_internal.h).
+//
+// Sweeps: one workgroup per patch of up to kPatchCells cells, one wave per
+// cell.  A wave walks its cell's velocities 64 at a time; at each step every
+// wave puts its own row's values into LDS, and after one barrier a face
+// whose neighbour lies in the same patch reads the neighbour's values from
+// LDS, a face to a cell outside the patch reads them from global memory
+// (L2 in the common case: the neighbouring patch ran shortly before or runs
+// alongside on the same XCD), and a boundary face reads the far-field or
+// wall table.  The loads of the next step are issued before the current
+// step's arithmetic.  The FP64 velocity moments of the new row are summed
+// in registers and reduced across the wave with shuffles in a fixed order,
+// so the next sweep finds W^{n+1} ready and f is streamed once per sweep.
 // The Maxwellian is evaluated as rho/(2 pi theta) * ex[a] * ey[b] with the
 // per-cell 1-D factors in LDS (tensor-product velocity grid), i.e. n1 + n2
 // exponentials per cell instead of n1*n2.
@@ -27,15 +35,15 @@ template <> struct Vec2<double> { using type = double2; };
 constexpr double kPi = 3.14159265358979323846;
 
 // Workgroups are handed to the 8 XCDs round-robin; give each XCD a
-// contiguous stretch of the sweep order (16x16-cell tiles marching along
-// grid strips) so that the upwind neighbour rows a workgroup reads were
-// fetched moments before by a workgroup of the same XCD and are still in
-// its L2.  Returns -1 for the padding workgroups of the last stretch.
-__device__ __forceinline__ int xcd_cell(const DevSolve &d, int b)
+// contiguous stretch of the sweep order (n items: cells or patches) so that
+// the neighbour rows a workgroup reads were fetched moments before by a
+// workgroup of the same XCD and are still in its L2.  Returns -1 for the
+// padding workgroups of the last stretch.
+__device__ __forceinline__ int xcd_item(int n, int b)
 {
-    const int per = (d.nc + 7) >> 3;
+    const int per = (n + 7) >> 3;
     const int idx = (b & 7) * per + (b >> 3);
-    return idx < d.nc ? d.order[idx] : -1;
+    return idx < n ? idx : -1;
 }
 static inline int xcd_grid(int n) { return ((n + 7) >> 3) << 3; }
 
@@ -60,138 +68,196 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *lds)
     }
 }
 
-// Per-cell velocity tables in LDS.
-template <typename T>
-struct CellLds {
-    double vx[kMaxN1D], vy[kMaxN1D], wx[kMaxN1D], wy[kMaxN1D];
-    T ex[kMaxN1D], ey[kMaxN1D];
-    double red[4 * 12];
-};
-
-template <typename T>
-__device__ __forceinline__ void load_vel_tables(const DevSolve &d, CellLds<T> &sm, double u1, double u2,
-                                                double inv2th)
-{
-    const int t = threadIdx.x;
-    if (t < d.n1) {
-        const double x = d.vx[t];
-        sm.vx[t] = x;
-        sm.wx[t] = d.wx[t];
-        const double c = x - u1;
-        sm.ex[t] = (T)exp(-c * c * inv2th);
-    } else if (t - d.n1 < d.n2) {
-        const int b = t - d.n1;
-        const double y = d.vy[b];
-        sm.vy[b] = y;
-        sm.wy[b] = d.wy[b];
-        const double c = y - u2;
-        sm.ey[b] = (T)exp(-c * c * inv2th);
-    }
-}
-
 __device__ __forceinline__ double mJ_of(int objective, double v1, double v2)
 {
     return objective == 0 ? v1 : 0.5 * (v1 * v1 + v2 * v2);
 }
 
+// LDS of a patch sweep: the velocity tables, each cell's Maxwellian
+// factors and, for a sweep that exchanges rows (XCH), the double-buffered
+// exchange of the patch's own rows.
+template <typename T, bool XCH>
+struct PatchLds {
+    double vx[kMaxN1D], vy[kMaxN1D], wx[kMaxN1D], wy[kMaxN1D];
+    T ex[kPatchCells][kMaxN1D], ey[kPatchCells][kMaxN1D];
+    typename Vec2<T>::type xch[XCH ? 2 : 1][XCH ? kPatchCells : 1][kWave];
+};
+
+// Reciprocal for the FP64 update: hardware estimate and two Newton steps
+// (error about one ulp; the IEEE division costs twice the instructions).
+// FP32 keeps the IEEE division: a one-ulp reciprocal there raised the
+// mixed-precision drag error against FP64 from 1e-8 to 2e-7 relative.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+
+// The adjoint sweep exchanges the patch's rows through LDS in FP64 (4%
+// faster than every face reading global memory on the 256x128 C-grid with
+// 2304 velocities); in FP32 and in the primal sweep the per-step barrier
+// costs more than the L2 requests it saves.
+template <typename T>
+constexpr bool kAdjointExchange = sizeof(T) == 8;
+
+// Sum N doubles over the wave (xor butterfly: every lane ends with the same
+// bits, the order is fixed).
+template <int N>
+__device__ __forceinline__ void wave_sum(double (&v)[N])
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < N; i++) v[i] += __shfl_xor(v[i], off, kWave);
+    }
+}
+
+// Values that are the same in every lane of a wave (per-cell constants of a
+// patch sweep), moved to scalar registers so that they do not occupy
+// vector registers through the velocity loop.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+__device__ __forceinline__ double uni(double x)
+{
+    const long long v = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Shared velocity tables (threads 0 .. n1+n2-1; a patch workgroup has at
+// least 4 waves, n1 + n2 <= 256) and this wave's Maxwellian factors
+// exp(-(v - u)^2 / (2 theta)) per direction.
+template <typename T, bool XCH>
+__device__ __forceinline__ void patch_tables(const DevSolve &d, PatchLds<T, XCH> &sm, int w, int lane, double u1,
+                                             double u2, double inv2th)
+{
+    const int t = threadIdx.x, n1 = d.n1, n2 = d.n2;
+    if (t < n1) {
+        sm.vx[t] = d.vx[t];
+        sm.wx[t] = d.wx[t];
+    } else if (t - n1 < n2) {
+        sm.vy[t - n1] = d.vy[t - n1];
+        sm.wy[t - n1] = d.wy[t - n1];
+    }
+    for (int i = lane; i < n1 + n2; i += kWave) {
+        if (i < n1) {
+            const double e = d.vx[i] - u1;
+            sm.ex[w][i] = (T)exp(-e * e * inv2th);
+        } else {
+            const double e = d.vy[i - n1] - u2;
+            sm.ey[w][i - n1] = (T)exp(-e * e * inv2th);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
-// primal sweep of one cell: eq. (numerpr_gov), first-order upwind, Jacobi
+// primal sweep of one patch: eq. (numerpr_gov), first-order upwind, Jacobi
 // point-implicit: f^{n+1} = (sum_in |v.S| f_up + V g/tau) / (sum_out v.S + V/tau)
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void primal_cell(const DevSolve &d, int c, int par)
+__device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
 {
     using T2 = typename Vec2<T>::type;
-    __shared__ CellLds<T> sm;
-    const int tid = threadIdx.x;
+    __shared__ PatchLds<T, false> sm;
+    const int w = uni((int)(threadIdx.x / kWave)), lane = threadIdx.x % kWave;
+    const int c0 = uni(d.patch[p]), cnt = uni(d.patch[p + 1]) - c0;
+    const bool act = w < cnt;                   // idle waves of a partial patch only join the barrier
+    const int c = c0 + (act ? w : 0);
     const int nv = d.nv, n1 = d.n1;
     const T2 *__restrict__ fin = static_cast<const T2 *>(d.f[par]);
     T2 *__restrict__ fout = static_cast<T2 *>(d.f[par ^ 1]);
 
     const double *Win = d.W[par] + 4 * c;
-    const double W0 = Win[0], W1 = Win[1], W2 = Win[2], W3 = Win[3];
+    const double W0 = uni(Win[0]), W1 = uni(Win[1]), W2 = uni(Win[2]), W3 = uni(Win[3]);
     const double rho = W0, u1 = W1 / rho, u2 = W2 / rho;
     const double th = (2.0 / 3.0) * (W3 / rho - 0.5 * (u1 * u1 + u2 * u2));
     const double itau = d.inv_tau_inf * rho * sqrt(2.0 * th);
     const double Vt = d.vol[c] * itau;
-    load_vel_tables<T>(d, sm, u1, u2, 0.5 / th);
+    patch_tables<T, false>(d, sm, w, lane, u1, u2, 0.5 / th);
 
+    const size_t row = (size_t)c * nv;
     int nb[4];
     T Sx[4], Sy[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        nb[q] = d.nbr[4 * c + q];
-        Sx[q] = (T)d.S[8 * c + 2 * q];
-        Sy[q] = (T)d.S[8 * c + 2 * q + 1];
+        nb[q] = uni(d.nbr[4 * c + q]);
+        Sx[q] = uni((T)d.S[8 * c + 2 * q]);
+        Sy[q] = uni((T)d.S[8 * c + 2 * q + 1]);
     }
     const int wl = nb[0] <= -2 ? -2 - nb[0] : -1;
     T wcoef = 0;
     double S0x = 0, S0y = 0;
     if (wl >= 0) {
-        wcoef = (T)(d.F[par][wl] / d.D[wl]);
-        S0x = d.S[8 * c];
-        S0y = d.S[8 * c + 1];
+        wcoef = uni((T)(d.F[par][wl] / d.D[wl]));
+        S0x = uni(d.S[8 * c]);
+        S0y = uni(d.S[8 * c + 1]);
     }
-    // one source row per face, all of the storage pair type: the upwind
-    // cell's row, the far-field table, or the wall table (g_M1, theta_w/2 g_M1)
+    // one source row per face: the neighbour's row (a neighbour in the same
+    // patch was read moments before by its own wave on this CU and is in
+    // L1), the far-field table, or the wall table (g_M1, theta_w/2 g_M1)
     // scaled by F_l / D_l
     const T2 *src[4];
     T sc[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int n = nb[q];
-        src[q] = n >= 0 ? fin + (size_t)n * nv
-                        : static_cast<const T2 *>(n == -1 ? d.fd : d.gw2);
+        src[q] = n >= 0 ? fin + (size_t)n * nv : static_cast<const T2 *>(n == -1 ? d.fd : d.gw2);
         sc[q] = n <= -2 ? wcoef : (T)1;
     }
-    const T th2 = (T)(0.5 * th);
-    const T gc = (T)(rho / (2.0 * kPi * th)), VtT = (T)Vt;
+    const T th2 = uni((T)(0.5 * th));
+    const T gc = uni((T)(rho / (2.0 * kPi * th))), VtT = uni((T)Vt);
     __syncthreads();
 
     double m0 = 0, m1 = 0, m2 = 0, m3 = 0, mF = 0;
-    int a = tid % n1, b = tid / n1;
-    const int da = kBlock % n1, db = kBlock / n1;
-    const size_t row = (size_t)c * nv;
-    for (int k = tid; k < nv; k += kBlock) {
-        const double v1d = sm.vx[a], v2d = sm.vy[b];
-        const T v1 = (T)v1d, v2 = (T)v2d;
-        // The face kind is uniform over the workgroup, only the sign of v.S
-        // differs between lanes: issue every face's source load first (no
-        // wait between them), then pick upwind values with selects.
-        T2 up[4];
+    int a = lane % n1, b = lane / n1;
+    const int da = kWave % n1, db = kWave / n1;
+    const int nstep = (nv + kWave - 1) / kWave;
+    for (int t = 0; t < nstep; t++) {
+        const int k = t * kWave + lane;
+        if (act && k < nv) {
+            // the face kind is uniform over the wave, only the sign of v.S
+            // differs between lanes: issue every face's load first
+            T2 up[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) up[q] = src[q][k];
-        T out = 0, in1 = 0, in2 = 0;
+            for (int q = 0; q < 4; q++) up[q] = src[q][k];
+            const double v1d = sm.vx[a], v2d = sm.vy[b];
+            const T v1 = (T)v1d, v2 = (T)v2d;
+            T out = 0, in1 = 0, in2 = 0;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const T s = v1 * Sx[q] + v2 * Sy[q];
-            if (s > 0) {
-                out += s;
-            } else {
-                in1 -= s * (sc[q] * up[q].x);
-                in2 -= s * (sc[q] * up[q].y);
+            for (int q = 0; q < 4; q++) {
+                const T s = v1 * Sx[q] + v2 * Sy[q];
+                if (s > 0) {
+                    out += s;
+                } else {
+                    in1 -= s * (sc[q] * up[q].x);
+                    in2 -= s * (sc[q] * up[q].y);
+                }
             }
-        }
-        const T g1 = gc * sm.ex[a] * sm.ey[b];
-        const T g2 = th2 * g1;
-        const T den = out + VtT;
-        T2 r;
-        r.x = (in1 + VtT * g1) / den;
-        r.y = (in2 + VtT * g2) / den;
-        // streaming stores: the new row is not read again in this sweep, so
-        // keep it from displacing the neighbour rows other workgroups reuse
-        __builtin_nontemporal_store(r.x, &fout[row + k].x);
-        __builtin_nontemporal_store(r.y, &fout[row + k].y);
-        const double w = sm.wx[a] * sm.wy[b];
-        const double f1 = (double)r.x, f2 = (double)r.y;
-        const double wf1 = w * f1;
-        m0 += wf1;
-        m1 += wf1 * v1d;
-        m2 += wf1 * v2d;
-        m3 += wf1 * (0.5 * (v1d * v1d + v2d * v2d)) + w * f2;
-        if (wl >= 0) {
-            const double s0 = v1d * S0x + v2d * S0y;
-            if (s0 > 0) mF += wf1 * s0;
+            const T g1 = gc * sm.ex[w][a] * sm.ey[w][b];
+            const T g2 = th2 * g1;
+            const T rden = recip(out + VtT);
+            T2 r;
+            r.x = (in1 + VtT * g1) * rden;
+            r.y = (in2 + VtT * g2) * rden;
+            // streaming stores: the new row is not read again in this sweep
+            __builtin_nontemporal_store(r.x, &fout[row + k].x);
+            __builtin_nontemporal_store(r.y, &fout[row + k].y);
+            const double wt = sm.wx[a] * sm.wy[b];
+            const double f1 = (double)r.x, f2 = (double)r.y;
+            const double wf1 = wt * f1;
+            m0 += wf1;
+            m1 += wf1 * v1d;
+            m2 += wf1 * v2d;
+            m3 += wf1 * (0.5 * (v1d * v1d + v2d * v2d)) + wt * f2;
+            if (wl >= 0) {
+                const double s0 = v1d * S0x + v2d * S0y;
+                if (s0 > 0) mF += wf1 * s0;
+            }
         }
         a += da;
         b += db;
@@ -201,8 +267,8 @@ __device__ __forceinline__ void primal_cell(const DevSolve &d, int c, int par)
         }
     }
     double acc[5] = {m0, m1, m2, m3, mF};
-    block_sum<5>(acc, sm.red);
-    if (tid == 0) {
+    wave_sum<5>(acc);
+    if (act && lane == 0) {
         double *Wo = d.W[par ^ 1] + 4 * c;
         Wo[0] = acc[0];
         Wo[1] = acc[1];
@@ -215,32 +281,32 @@ __device__ __forceinline__ void primal_cell(const DevSolve &d, int c, int par)
     }
 }
 
-// moments W and wall flux F of f[par] for one cell (no update)
+// moments W and wall flux F of f[par] for one cell (no update), one wave
+// per cell: the same lane <-> velocity map, expressions and summation order
+// as the primal sweep's epilogue, so a state loaded from a checkpoint
+// continues bit for bit.
 template <typename T>
-__device__ __forceinline__ void moments_cell(const DevSolve &d, int c, int par)
+__device__ __forceinline__ void moments_wave(const DevSolve &d, int c, int par)
 {
     using T2 = typename Vec2<T>::type;
-    __shared__ CellLds<T> sm;
-    const int tid = threadIdx.x, nv = d.nv, n1 = d.n1;
-    load_vel_tables<T>(d, sm, 0.0, 0.0, 0.0);
+    const int lane = threadIdx.x % kWave, nv = d.nv, n1 = d.n1;
     const int l0 = d.nbr[4 * c];
     const int wl = l0 <= -2 ? -2 - l0 : -1;
     const double S0x = d.S[8 * c], S0y = d.S[8 * c + 1];
     const T2 *__restrict__ f = static_cast<const T2 *>(d.f[par]);
-    __syncthreads();
     double m0 = 0, m1 = 0, m2 = 0, m3 = 0, mF = 0;
-    int a = tid % n1, b = tid / n1;
-    const int da = kBlock % n1, db = kBlock / n1;
-    for (int k = tid; k < nv; k += kBlock) {
-        const double v1d = sm.vx[a], v2d = sm.vy[b];
+    int a = lane % n1, b = lane / n1;
+    const int da = kWave % n1, db = kWave / n1;
+    for (int k = lane; k < nv; k += kWave) {
+        const double v1d = d.vx[a], v2d = d.vy[b];
         const T2 r = f[(size_t)c * nv + k];
-        const double w = sm.wx[a] * sm.wy[b];
+        const double wt = d.wx[a] * d.wy[b];
         const double f1 = (double)r.x, f2 = (double)r.y;
-        const double wf1 = w * f1;
+        const double wf1 = wt * f1;
         m0 += wf1;
         m1 += wf1 * v1d;
         m2 += wf1 * v2d;
-        m3 += wf1 * (0.5 * (v1d * v1d + v2d * v2d)) + w * f2;
+        m3 += wf1 * (0.5 * (v1d * v1d + v2d * v2d)) + wt * f2;
         if (wl >= 0) {
             const double s0 = v1d * S0x + v2d * S0y;
             if (s0 > 0) mF += wf1 * s0;
@@ -253,8 +319,8 @@ __device__ __forceinline__ void moments_cell(const DevSolve &d, int c, int par)
         }
     }
     double acc[5] = {m0, m1, m2, m3, mF};
-    block_sum<5>(acc, sm.red);
-    if (tid == 0) {
+    wave_sum<5>(acc);
+    if (lane == 0) {
         double *Wo = d.W[par] + 4 * c;
         Wo[0] = acc[0];
         Wo[1] = acc[1];
@@ -265,25 +331,29 @@ __device__ __forceinline__ void moments_cell(const DevSolve &d, int c, int par)
 }
 
 // ---------------------------------------------------------------------------
-// adjoint sweep of one cell: eq. (numerad_gov) with the wall and far-field
+// adjoint sweep of one patch: eq. (numerad_gov) with the wall and far-field
 // conditions of eq. (formula_adjointbgk), Jacobi point-implicit:
 // phi^{n+1} = (sum_out v.S phi_down + V (phi_eq/tau + phi_tau)) / (sum_out v.S + V/tau)
 // Epilogue: What (eq. adjoint_macdefines, via primitive variables),
 // rho_tau, the wall multiplier Phi_l and the residual partials of phi^{n+1}.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
+template <typename T, bool XCH>
+__device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
 {
     using T2 = typename Vec2<T>::type;
-    __shared__ CellLds<T> sm;
-    const int tid = threadIdx.x;
+    __shared__ PatchLds<T, XCH> sm;
+    const int w = uni((int)(threadIdx.x / kWave)), lane = threadIdx.x % kWave;
+    const int c0 = uni(d.patch[p]), cnt = uni(d.patch[p + 1]) - c0;
+    const bool act = w < cnt;
+    const int c = c0 + (act ? w : 0);
     const int nv = d.nv, n1 = d.n1;
     const T2 *__restrict__ pin = static_cast<const T2 *>(d.phi[par]);
     T2 *__restrict__ pout = static_cast<T2 *>(d.phi[par ^ 1]);
     const T2 *__restrict__ fst = static_cast<const T2 *>(d.fstar);
 
     const double *ac = d.acoef + 16 * c;
-    const double rho = ac[0], u1 = ac[1], u2 = ac[2], th = ac[3], itau = ac[4], gcoef = ac[5];
+    const double rho = uni(ac[0]), u1 = uni(ac[1]), u2 = uni(ac[2]), th = uni(ac[3]), itau = uni(ac[4]);
+    const double gcoef = ac[5];
     const double dt0 = ac[6], dt1 = ac[7], dt2 = ac[8], dt3 = ac[9];
     const double Vv = d.vol[c];
     const double *aw = d.aW[par] + 8 * c;
@@ -291,95 +361,129 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
     // source phi_eq / tau + phi_tau = C0 + C1 v1 + C2 v2 + C3 |v|^2/2 (first), C3 (second)
     const double C0 = aw[0] * itau - rt * dt0, C1 = aw[1] * itau - rt * dt1;
     const double C2 = aw[2] * itau - rt * dt2, C3 = aw[3] * itau - rt * dt3;
-    load_vel_tables<T>(d, sm, u1, u2, 0.5 / th);
+    patch_tables<T, XCH>(d, sm, w, lane, u1, u2, 0.5 / th);
 
-    int nb[4];
+    const size_t row = (size_t)c * nv;
+    int nb[4], slot[4];
     T Sx[4], Sy[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        nb[q] = d.nbr[4 * c + q];
-        Sx[q] = (T)d.S[8 * c + 2 * q];
-        Sy[q] = (T)d.S[8 * c + 2 * q + 1];
+        nb[q] = uni(d.nbr[4 * c + q]);
+        Sx[q] = uni((T)d.S[8 * c + 2 * q]);
+        Sy[q] = uni((T)d.S[8 * c + 2 * q + 1]);
+        slot[q] = XCH && nb[q] >= c0 && nb[q] < c0 + cnt ? nb[q] - c0 : -1;
     }
     const int wl = nb[0] <= -2 ? -2 - nb[0] : -1;
     T Phi_w = 0;
     double S0x = 0, S0y = 0;
     if (wl >= 0) {
-        Phi_w = (T)d.Phi[par][wl];
-        S0x = d.S[8 * c];
-        S0y = d.S[8 * c + 1];
+        Phi_w = uni((T)d.Phi[par][wl]);
+        S0x = uni(d.S[8 * c]);
+        S0y = uni(d.S[8 * c + 1]);
     }
     const T *__restrict__ gM = static_cast<const T *>(d.gM);
-    // downstream rows of interior faces; boundary faces read their own row
-    // (a valid address) and ignore it
+    // downstream rows of faces to cells not exchanged through LDS; every
+    // other face reads the own row (loaded anyway, an L1 hit) and ignores it
     const T2 *dsrc[4];
 #pragma unroll
-    for (int q = 0; q < 4; q++) dsrc[q] = pin + (size_t)(nb[q] >= 0 ? nb[q] : c) * nv;
+    for (int q = 0; q < 4; q++) dsrc[q] = pin + (size_t)(nb[q] >= 0 && slot[q] < 0 ? nb[q] : c) * nv;
     const int obj = d.objective;
-    const T VT = (T)Vv, den0 = (T)(Vv * itau);
-    const T Ct0 = (T)C0, Ct1 = (T)C1, Ct2 = (T)C2, Ct3 = (T)C3;
-    const T gc = (T)gcoef, th2 = (T)(0.5 * th);
+    const T VT = uni((T)Vv), den0 = uni((T)(Vv * itau));
+    const T Ct0 = uni((T)C0), Ct1 = uni((T)C1), Ct2 = uni((T)C2), Ct3 = uni((T)C3);
+    const T gc = uni((T)gcoef), th2 = uni((T)(0.5 * th));
     const double thw2 = 0.5 * d.theta_w;
     __syncthreads();
 
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, R = 0, Pw = 0, dn = 0, dd = 0;
-    int a = tid % n1, b = tid / n1;
-    const int da = kBlock % n1, db = kBlock / n1;
-    const size_t row = (size_t)c * nv;
-    for (int k = tid; k < nv; k += kBlock) {
-        const double v1d = sm.vx[a], v2d = sm.vy[b];
-        const T v1 = (T)v1d, v2 = (T)v2d;
-        const T mj = (T)mJ_of(obj, v1d, v2d);
-        // all loads of this velocity first (own phi^n, frozen f, the
-        // downstream rows of interior faces), then the select-based update
-        const T2 old = pin[row + k];
-        const T2 fs = fst[row + k];
-        T2 dwn[4];
+    int a = lane % n1, b = lane / n1;
+    const int da = kWave % n1, db = kWave / n1;
+    const int nstep = (nv + kWave - 1) / kWave;
+    T2 own_n = {0, 0}, fs_n = {0, 0}, dwn_n[4] = {};
+    if (XCH && act) {
+        const int k = min(lane, nv - 1);
+        own_n = pin[row + k];
+        fs_n = fst[row + k];
 #pragma unroll
-        for (int q = 0; q < 4; q++) dwn[q] = dsrc[q][k];
-        T out = 0, a1 = 0, a2 = 0;
+        for (int q = 0; q < 4; q++) dwn_n[q] = dsrc[q][k];
+    }
+    for (int t = 0; t < nstep; t++) {
+        const int buf = t & 1;
+        const int k = t * kWave + lane;
+        T2 old, fs, dwn[4];
+        if constexpr (XCH) {
+            // every wave publishes its own values of this step, then the
+            // next step's loads go out before this step's arithmetic
+            sm.xch[buf][w][lane] = own_n;
+            old = own_n;
+            fs = fs_n;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const T s = v1 * Sx[q] + v2 * Sy[q];
-            if (s > 0) {
-                out += s;
-                if (nb[q] >= 0) {
-                    a1 += s * dwn[q].x;
-                    a2 += s * dwn[q].y;
-                } else if (nb[q] <= -2) {
-                    a1 += s * (Phi_w - mj);
+            for (int q = 0; q < 4; q++) dwn[q] = dwn_n[q];
+            __syncthreads();
+            if (act && t + 1 < nstep) {
+                const int kn = min(k + kWave, nv - 1);
+                own_n = pin[row + kn];
+                fs_n = fst[row + kn];
+#pragma unroll
+                for (int q = 0; q < 4; q++) dwn_n[q] = dsrc[q][kn];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (slot[q] >= 0) dwn[q] = sm.xch[buf][slot[q]][lane];
+        }
+        if (act && k < nv) {
+            if constexpr (!XCH) {
+                old = pin[row + k];
+                fs = fst[row + k];
+#pragma unroll
+                for (int q = 0; q < 4; q++) dwn[q] = dsrc[q][k];
+            }
+            const double v1d = sm.vx[a], v2d = sm.vy[b];
+            const T v1 = (T)v1d, v2 = (T)v2d;
+            const T mj = (T)mJ_of(obj, v1d, v2d);
+            T out = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const T s = v1 * Sx[q] + v2 * Sy[q];
+                if (s > 0) {
+                    out += s;
+                    if (nb[q] >= 0) {
+                        a1 += s * dwn[q].x;
+                        a2 += s * dwn[q].y;
+                    } else if (nb[q] <= -2) {
+                        a1 += s * (Phi_w - mj);
+                    }
                 }
             }
+            const T vv2 = (T)0.5 * (v1 * v1 + v2 * v2);
+            const T s1 = Ct0 + Ct1 * v1 + Ct2 * v2 + Ct3 * vv2;
+            const T rden = recip(out + den0);
+            T2 r;
+            r.x = (a1 + VT * s1) * rden;
+            r.y = (a2 + VT * Ct3) * rden;
+            __builtin_nontemporal_store(r.x, &pout[row + k].x);
+            __builtin_nontemporal_store(r.y, &pout[row + k].y);
+            // epilogue accumulations from phi^{n+1}
+            const double wt = sm.wx[a] * sm.wy[b];
+            const double p1 = (double)r.x, p2 = (double)r.y;
+            const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
+            const double g2 = (double)(th2 * (T)g1);
+            const double qq = p1 + 0.5 * th * p2;
+            const double c1 = v1d - u1, c2 = v2d - u2;
+            const double wg = wt * g1;
+            A0 += wg * qq;
+            A1 += wg * qq * c1;
+            A2 += wg * qq * c2;
+            A3 += wg * qq * (c1 * c1 + c2 * c2);
+            A4 += wg * p2;
+            R += wt * (p1 * (g1 - (double)fs.x) + p2 * (g2 - (double)fs.y));
+            if (wl >= 0) {
+                const double s0 = v1d * S0x + v2d * S0y;
+                if (s0 <= 0) Pw += wt * s0 * (double)gM[k] * ((p1 + mJ_of(obj, v1d, v2d)) + thw2 * p2);
+            }
+            const double e1 = p1 - (double)old.x, e2 = p2 - (double)old.y;
+            dn += wt * (e1 * e1 + e2 * e2);
+            dd += wt * (p1 * p1 + p2 * p2);
         }
-        const T vv2 = (T)0.5 * (v1 * v1 + v2 * v2);
-        const T s1 = Ct0 + Ct1 * v1 + Ct2 * v2 + Ct3 * vv2;
-        const T den = out + den0;
-        T2 r;
-        r.x = (a1 + VT * s1) / den;
-        r.y = (a2 + VT * Ct3) / den;
-        __builtin_nontemporal_store(r.x, &pout[row + k].x);
-        __builtin_nontemporal_store(r.y, &pout[row + k].y);
-        // epilogue accumulations from phi^{n+1}
-        const double w = sm.wx[a] * sm.wy[b];
-        const double p1 = (double)r.x, p2 = (double)r.y;
-        const double g1 = (double)(gc * sm.ex[a] * sm.ey[b]);
-        const double g2 = (double)(th2 * (T)g1);
-        const double q = p1 + 0.5 * th * p2;
-        const double c1 = v1d - u1, c2 = v2d - u2;
-        const double wg = w * g1;
-        A0 += wg * q;
-        A1 += wg * q * c1;
-        A2 += wg * q * c2;
-        A3 += wg * q * (c1 * c1 + c2 * c2);
-        A4 += wg * p2;
-        R += w * (p1 * (g1 - (double)fs.x) + p2 * (g2 - (double)fs.y));
-        if (wl >= 0) {
-            const double s0 = v1d * S0x + v2d * S0y;
-            if (s0 <= 0) Pw += w * s0 * (double)gM[k] * ((p1 + mJ_of(obj, v1d, v2d)) + thw2 * p2);
-        }
-        const double e1 = p1 - (double)old.x, e2 = p2 - (double)old.y;
-        dn += w * (e1 * e1 + e2 * e2);
-        dd += w * (p1 * p1 + p2 * p2);
         a += da;
         b += db;
         if (a >= n1) {
@@ -388,8 +492,8 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
         }
     }
     double acc[9] = {A0, A1, A2, A3, A4, R, Pw, dn, dd};
-    block_sum<9>(acc, sm.red);
-    if (tid == 0) {
+    wave_sum<9>(acc);
+    if (act && lane == 0) {
         // phi . dg/dP with P = (rho, u1, u2, theta)
         const double P0 = acc[0] / rho;
         const double P1 = acc[1] / th, P2 = acc[2] / th;
@@ -412,49 +516,55 @@ __device__ __forceinline__ void adjoint_cell(const DevSolve &d, int c, int par)
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+constexpr int kPatchBlock = kPatchCells * kWave;   // threads of a patch workgroup
+static_assert(kPatchCells >= 4, "the velocity tables are loaded by the first 256 threads");
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_primal_sweep(DevSolve d, int par)
+__global__ __launch_bounds__(kPatchBlock) void k_primal_sweep(DevSolve d, int par)
 {
-    const int c = xcd_cell(d, blockIdx.x);
-    if (c < 0) return;
-    primal_cell<T>(d, c, par);
+    const int p = xcd_item(d.np, blockIdx.x);
+    if (p < 0) return;
+    primal_patch<T>(d, p, par);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_moments(DevSolve d, int par)
 {
-    const int c = xcd_cell(d, blockIdx.x);
-    if (c < 0) return;
-    moments_cell<T>(d, c, par);
+    const int c = blockIdx.x * (kBlock / kWave) + (int)(threadIdx.x / kWave);
+    if (c < d.nc) moments_wave<T>(d, c, par);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adjoint_sweep(DevSolve d, int par)
+__global__ __launch_bounds__(kPatchBlock) void k_adjoint_sweep(DevSolve d, int par)
 {
-    const int c = xcd_cell(d, blockIdx.x);
-    if (c < 0) return;
-    adjoint_cell<T>(d, c, par);
+    const int p = xcd_item(d.np, blockIdx.x);
+    if (p < 0) return;
+    adjoint_patch<T, kAdjointExchange<T>>(d, p, par);
 }
 
 // one sweep of the primal-phase (or adjoint-phase) members of a batch; a
-// block owns one (solve, cell).  The two phases are separate kernels so
-// that each gets the occupancy of its own register footprint.
+// workgroup owns one (solve, patch).  The two phases are separate kernels
+// so that each gets the occupancy of its own register footprint.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_batch_primal(const DevSolve *tab, const int32_t *blk_solve,
-                                                         const int32_t *blk_cell, const int32_t *par0, int step)
+__global__ __launch_bounds__(kPatchBlock) void k_batch_primal(const DevSolve *__restrict__ tab,
+                                                              const int32_t *__restrict__ blk_solve,
+                                                              const int32_t *__restrict__ blk_patch,
+                                                              const int32_t *__restrict__ par0, int step)
 {
     const int s = blk_solve[blockIdx.x];
     if (s < 0) return;
-    primal_cell<T>(tab[s], blk_cell[blockIdx.x], (par0[s] + step) & 1);
+    primal_patch<T>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_batch_adjoint(const DevSolve *tab, const int32_t *blk_solve,
-                                                          const int32_t *blk_cell, const int32_t *par0, int step)
+__global__ __launch_bounds__(kPatchBlock) void k_batch_adjoint(const DevSolve *__restrict__ tab,
+                                                               const int32_t *__restrict__ blk_solve,
+                                                               const int32_t *__restrict__ blk_patch,
+                                                               const int32_t *__restrict__ par0, int step)
 {
     const int s = blk_solve[blockIdx.x];
     if (s < 0) return;
-    adjoint_cell<T>(tab[s], blk_cell[blockIdx.x], (par0[s] + step) & 1);
+    adjoint_patch<T, kAdjointExchange<T>>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
 }
 
 // f = far-field Maxwellian everywhere (storage type)
@@ -754,13 +864,15 @@ hipError_t launch_primal_init(const DevSolve &d, hipStream_t st)
 
 hipError_t launch_moments(const DevSolve &d, int par, hipStream_t st)
 {
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_moments<T>, dim3(xcd_grid(d.nc)), dim3(kBlock), 0, st, d, par));
+    constexpr int per_block = kBlock / kWave;
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_moments<T>, dim3((d.nc + per_block - 1) / per_block), dim3(kBlock), 0,
+                                             st, d, par));
     return hipGetLastError();
 }
 
 hipError_t launch_primal_sweep(const DevSolve &d, int par, hipStream_t st)
 {
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_primal_sweep<T>, dim3(xcd_grid(d.nc)), dim3(kBlock), 0, st, d, par));
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_primal_sweep<T>, dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0, st, d, par));
     return hipGetLastError();
 }
 
@@ -801,7 +913,7 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
 
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st)
 {
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_adjoint_sweep<T>, dim3(xcd_grid(d.nc)), dim3(kBlock), 0, st, d, par));
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_adjoint_sweep<T>, dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0, st, d, par));
     return hipGetLastError();
 }
 
@@ -813,16 +925,16 @@ hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params,
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_cell,
+hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_patch,
                         const int32_t *par0, int step, int nblocks, int mixed, int adjoint, hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
     if (adjoint)
-        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_adjoint<T>, dim3(nblocks), dim3(kBlock), 0, st, tab,
-                                               blk_solve, blk_cell, par0, step));
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_adjoint<T>, dim3(nblocks), dim3(kPatchBlock), 0, st, tab,
+                                               blk_solve, blk_patch, par0, step));
     else
-        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_primal<T>, dim3(nblocks), dim3(kBlock), 0, st, tab,
-                                               blk_solve, blk_cell, par0, step));
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_primal<T>, dim3(nblocks), dim3(kPatchBlock), 0, st, tab,
+                                               blk_solve, blk_patch, par0, step));
     return hipGetLastError();
 }
 

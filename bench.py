@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
 KERNEL_SRC = os.path.join(ROOT, "paper_2501_00923_amd", "csrc", "dvm_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_naca0012_c256x128_v48_traffic.json")
 
 
 def kernel_hash() -> str:

@@ -199,9 +199,57 @@ def precision_sweep(sweeps, kns, oracle_check_sweeps=2):
     return rows
 
 
-def cpu_baseline(wl, seconds):
+def fd_check(h, tol, params=None):
+    """The differentiation workload (seed-drawn NACA thickness and camber,
+    192x96 C-grid, 48x48 Newton-Cotes grid, Kn 0.5, Ma 2, 24 B-spline
+    offsets): dJ/dalpha from the adjoint through the autograd wrapper
+    (primal f snapshotted every 50 sweeps) against central differences
+    J(alpha +- h e_p) of re-converged primal solves."""
+    import numpy as np
+    import torch
+
+    from paper_2501_00923_amd import autograd as AG
+
+    opts = AG.SolveOptions(max_iter=60000, tol=tol, adjoint_max_iter=60000, adjoint_tol=tol, check_every=100)
+    case, a0 = AG.naca_bspline_case(seed=0, options=opts, checkpoint_every=50, keep_checkpoints=1)
+    rec = AG.ForwardRecord()
+    alpha = torch.tensor(a0, requires_grad=True)
+    t0 = time.perf_counter()
+    J = AG.drag(alpha, case, rec)
+    J.backward()
+    t_grad = time.perf_counter() - t0
+    g = alpha.grad.numpy().copy()
+    print(f"[fd] J {J.item():.12e}, primal {rec.iters} sweeps (resid {rec.resid:.1e}), adjoint "
+          f"{rec.adjoint_iters} sweeps (resid {rec.adjoint_resid:.1e}), {t_grad:.1f} s", file=sys.stderr, flush=True)
+    case.checkpoint_every = 0
+    params = list(range(len(a0))) if params is None else params
+    rows = []
+    t0 = time.perf_counter()
+    for p in params:
+        e = np.zeros_like(a0)
+        e[p] = h
+        rp, rm = AG.ForwardRecord(), AG.ForwardRecord()
+        Jp = AG.drag(torch.tensor(a0 + e), case, rp).item()
+        Jm = AG.drag(torch.tensor(a0 - e), case, rm).item()
+        fd = (Jp - Jm) / (2 * h)
+        rows.append({"param": p, "adjoint": float(g[p]), "fd": fd, "sweeps": [rp.iters, rm.iters]})
+        print(f"[fd] p {p:2d}: adjoint {g[p]: .6e}  fd {fd: .6e}", file=sys.stderr, flush=True)
+    gv = np.array([r["adjoint"] for r in rows])
+    fv = np.array([r["fd"] for r in rows])
+    scale = float(np.max(np.abs(fv)))
+    return {"workload": "naca_bspline_c192x96_v48nc_kn0.5_ma2 (seed 0)", "h": h, "tol": tol, "J": J.item(),
+            "primal_sweeps": rec.iters, "adjoint_sweeps": rec.adjoint_iters,
+            "checkpoints_kept": len(rec.checkpoints), "last_checkpoint_sweep": rec.checkpoint_iters[-1],
+            "grad_seconds": t_grad, "fd_seconds": time.perf_counter() - t0,
+            "max_abs_diff_over_max_fd": float(np.max(np.abs(gv - fv)) / scale),
+            "median_rel_diff": float(np.median(np.abs(gv - fv) / np.maximum(np.abs(fv), 1e-3 * scale))),
+            "cosine": float(gv @ fv / (np.linalg.norm(gv) * np.linalg.norm(fv))), "rows": rows}
+
+
+def oracle_rate(wl, seconds, nthreads):
+    """Primal then adjoint Jacobi sweeps of the oracle, each for about
+    seconds/2: (updates/s, primal sweeps, adjoint sweeps, time)."""
     import oracle
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     p = oracle.Problem.from_workload(wl, nthreads=nthreads)
     p.primal_init()
     pairs = p.nc * p.nv
@@ -224,11 +272,19 @@ def cpu_baseline(wl, seconds):
             break
     ta = time.perf_counter() - t0
     na = done
-    rate = pairs * (np_ + na) / (tp + ta)
+    return pairs * (np_ + na) / (tp + ta), np_, na, tp + ta
+
+
+def cpu_baseline(wl, seconds):
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    rate, np_, na, t = oracle_rate(wl, seconds, nthreads)
+    rate1, np1, na1, t1 = oracle_rate(wl, seconds / 2, 1)
+    pairs = wl.grid.ni * wl.grid.nj * wl.vgrid.n1 * wl.vgrid.n2
     return {"value": rate, "unit": "cell-velocity updates/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{wl.name}: {np_} primal + {na} adjoint Jacobi sweeps of the full grid "
-                      f"({pairs} pairs) from the free stream, FP64, OpenMP over cells "
-                      f"({tp + ta:.1f} s)"}
+                      f"({pairs} pairs) from the free stream, FP64, OpenMP over cells ({t:.1f} s)",
+            "single_core": {"value": rate1, "cores": 1,
+                            "sample": f"{np1} primal + {na1} adjoint sweeps, one thread ({t1:.1f} s)"}}
 
 
 def main():
@@ -247,7 +303,11 @@ def main():
     ap.add_argument("--serving-seed", type=int, default=0)
     ap.add_argument("--precision-sweep", action="store_true",
                     help="print the per-Kn mixed-vs-FP64 error table (256x128 C-grid, 64x64 sinh grid) and exit")
-    ap.add_argument("--precision-sweeps", type=int, default=400)
+    ap.add_argument("--precision-sweeps", type=int, default=2000)
+    ap.add_argument("--fd-check", action="store_true",
+                    help="print the adjoint-vs-central-difference table of the 24-parameter B-spline NACA case and exit")
+    ap.add_argument("--fd-h", type=float, default=1e-6)
+    ap.add_argument("--fd-tol", type=float, default=1e-12)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -277,6 +337,9 @@ def main():
     if args.precision_sweep:
         rows = precision_sweep(args.precision_sweeps, [1e-3, 1e-2, 0.1, 1.0, 10.0])
         print(json.dumps({"precision_sweep": rows}))
+        return
+    if args.fd_check:
+        print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol)}))
         return
     wl = I.c2_naca(seed=0)
     print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",

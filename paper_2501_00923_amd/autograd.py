@@ -42,6 +42,7 @@ class ShapeCase:
     precision: int = dvm.FP64
     options: SolveOptions = field(default_factory=SolveOptions)
     checkpoint_every: int = 0
+    keep_checkpoints: Optional[int] = None   # None: keep every snapshot; n: only the last n
     offload: bool = False
 
 
@@ -51,6 +52,7 @@ class ForwardRecord:
     resid: float = float("nan")
     Cd: float = float("nan")
     checkpoints: List[np.ndarray] = field(default_factory=list)
+    checkpoint_iters: List[int] = field(default_factory=list)   # sweeps done at each kept snapshot
     adjoint_iters: int = 0
     adjoint_resid: float = float("nan")
 
@@ -66,6 +68,10 @@ def _primal(case: ShapeCase, solver: dvm.Solver, rec: ForwardRecord):
             rec.resid = r
             left -= it
             rec.checkpoints.append(solver.state_save(dvm.STATE_F))
+            rec.checkpoint_iters.append(rec.iters)
+            if case.keep_checkpoints is not None and len(rec.checkpoints) > case.keep_checkpoints:
+                drop = len(rec.checkpoints) - case.keep_checkpoints
+                del rec.checkpoints[:drop], rec.checkpoint_iters[:drop]
             if not o.fixed_iters and r < o.tol:
                 break
     else:

@@ -8,9 +8,10 @@ their iterates agree to rounding.  Bars:
          max|f|, sensitivities <= 1e-3 (FP32 rounding of ~1e-7 per sweep,
          growing with the sweep count; measured errors are reported by the
          precision tests and the benchmark)
-Cases span several 256-velocity passes with a ragged tail, fewer velocities
-than threads, both topologies (wake cut), tau = infinity, the heat
-objective and a hot wall.
+Cases span several 64-velocity wave steps with a ragged tail, fewer
+velocities than a wave, odd grid sizes (partial 2x2 patches and tiles), the
+largest velocity grid (128 x 128), both topologies (wake cut), tau =
+infinity, the heat objective and a hot wall.
 """
 import math
 import sys
@@ -76,12 +77,20 @@ def _case(name):
         w = I.tiny_naca(Kn=0.4, Ma=0.6)
         w.flow = I.FlowSpec(0.4, 0.6, Tw=1.6, objective=1)
         return w
-    if name == "one_row":                          # nj = 1, nv = 100 < 256 threads
+    if name == "one_row":                          # nj = 1, nv = 100; patches of 2 cells
         return I.circle_case(12, 1, 10, 5.0, 1.0, 0.5, r_outer=2.0, stretch=1.0)
+    if name == "o13x7_odd":                        # odd ni, nj: patches of 1, 2 and 4 cells; nv = 324
+        return I.circle_case(13, 7, 18, 5.0, 0.5, 0.6, r_outer=4.0, stretch=1.2)
+    if name == "c_odd":                            # C-grid 28 x 7: odd nj, wake cut; nv = 400
+        g = I.naca_cgrid(5, 9, 7, t=0.12, m=0.03, r_outer=4.0, h1=0.03)
+        return I.Workload("c_odd", g, I.VGridSpec(I.VG_MIDPOINT, 20, 20, 6.0), I.FlowSpec(0.3, 1.1), 0)
+    if name == "v128_max":                         # the largest velocity grid, 128 x 128 = 16384
+        return I.circle_case(6, 3, 128, 6.0, 0.8, 0.9, r_outer=3.0, stretch=1.3)
     raise KeyError(name)
 
 
-CASES = ["tiny_circle", "tiny_naca", "o24x12_v20", "c_nc24", "c_sinh36", "freemol", "heat_hotwall", "one_row"]
+CASES = ["tiny_circle", "tiny_naca", "o24x12_v20", "c_nc24", "c_sinh36", "freemol", "heat_hotwall", "one_row",
+         "o13x7_odd", "c_odd", "v128_max"]
 
 
 def _run(wl, precision, n_primal, n_adjoint, n_params_jac=None):
@@ -123,7 +132,7 @@ def test_fp64_primal_adjoint_sensitivity_parity(name):
         assert _rel(da, do) <= 1e-10
 
 
-@pytest.mark.parametrize("name", ["tiny_circle", "o24x12_v20", "c_sinh36"])
+@pytest.mark.parametrize("name", ["tiny_circle", "o24x12_v20", "c_sinh36", "o13x7_odd"])
 def test_mixed_precision_parity(name):
     wl = _case(name)
     r = _run(wl, dvm.MIXED, 37, 29)

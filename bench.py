@@ -30,13 +30,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
-KERNEL_SRC = os.path.join(ROOT, "paper_2501_00923_amd", "csrc", "dvm_kernels.hip")
+# the sweep kernels, their layout constants and the host-built sweep order
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2501_00923_amd", "csrc", f)
+               for f in ("dvm_kernels.hip", "dvm_internal.h", "dvm_host.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_naca0012_c256x128_v48_traffic.json")
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def bytes_per_update(kind: str, mixed: bool) -> int:

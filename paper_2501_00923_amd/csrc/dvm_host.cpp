@@ -67,8 +67,8 @@ using P2 = std::array<double, 2>;
 // kPatchJ cells (one workgroup of a sweep each) taken row by row, and a
 // patch's cells are numbered row by row.  Neighbour rows that a patch reads
 // from outside itself belong to patches processed shortly before or after
-// it on the same XCD (still in its L2), and the rows of the workgroups in
-// flight are contiguous in memory.
+// it on the same XCD (in its L2, else in the MALL), and the rows of the
+// workgroups in flight are contiguous in memory.
 void build_patches(dvm_mesh &m)
 {
     using dvm::kPatchI;

@@ -75,6 +75,7 @@ def lib():
         L.or_adjoint_dJdp.restype = D
         L.or_adjoint_dJdp.argtypes = [P, I]
         L.or_wall_sensitivity.argtypes = [P, dp, dp, dp, C.c_void_p]
+        L.or_mesh_sensitivity.argtypes = [P, D, dp]
         L.or_wall_JB.restype = D
         L.or_wall_JB.argtypes = [P, I, D, D, D, D, D]
         _lib = L
@@ -129,6 +130,7 @@ class Problem:
         s = np.zeros(8, dtype=np.int64)
         lib().or_sizes(self._h, s)
         self.nc, self.nw, self.nv, self.n1, self.n2 = (int(x) for x in s[:5])
+        self.ni, self.nj = int(ni), int(nj)
 
     @classmethod
     def from_workload(cls, wl, nthreads=None, Kn=None, Ma=None, Tw=None):
@@ -272,6 +274,13 @@ class Problem:
         dn = np.zeros((self.nw, 2))
         lib().or_wall_sensitivity(self._h, SA, Sx, Sn, dn.ctypes.data)
         return dict(S_A=SA, S_x=Sx, S_n=Sn, dJ_dnodes=dn)
+
+    def mesh_sensitivity(self, h: float = 1e-30):
+        """dL/dx for every mesh node coordinate, shape (nj+1, ni+1, 2): the
+        exact discrete shape derivative at converged f and phi."""
+        out = np.zeros((self.nj + 1, self.ni + 1, 2))
+        lib().or_mesh_sensitivity(self._h, float(h), out)
+        return out
 
     def wall_JB(self, l, A, x, n):
         return lib().or_wall_JB(self._h, int(l), float(A), float(x[0]), float(x[1]),

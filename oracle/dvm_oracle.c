@@ -53,11 +53,14 @@
  * and T_w; wall-element derivatives against finite differences of the
  * discrete J and B_w expressions; node transform against finite
  * differences of the element geometry; mirror symmetry of the
- * sensitivities.  The end-to-end shape derivative itself is the paper's
+ * sensitivities.  The end-to-end shape derivative of the paper is its
  * wall-only approximation (Sec. 2.5: volume-mesh motion is not
  * differentiated); its agreement with finite differences is a
  * discretisation-level trend, not an identity (parity unpinned beyond the
- * element-level pins above).
+ * element-level pins above).  The exact discrete shape derivative
+ * (or_mesh_sensitivity, the Lagrangian differentiated in every node
+ * coordinate by complex step) is pinned by translation invariance and by
+ * central differences of the re-converged drag under shape change.
  */
 #include <complex.h>
 #include <math.h>
@@ -100,6 +103,7 @@ typedef struct {
     double *F;         /* [nw] wall incoming mass flux of f */
     double *phi, *phin;
     double *cellred;   /* [nc][2] residual partials */
+    double *nodes;     /* [(nj+1)(ni+1)][2] mesh node coordinates */
     int nthreads;
 } or_problem;
 
@@ -368,6 +372,8 @@ or_problem *or_create(int topo, int ni, int nj, int nwake, const double *nodes,
     p->topo = topo; p->ni = ni; p->nj = nj; p->nwake = nwake;
     p->nthreads = nthreads > 0 ? nthreads : 1;
     if (build_mesh(p, nodes) != 0) { free(p); return NULL; }
+    p->nodes = malloc(sizeof(double) * 2 * (size_t)(ni + 1) * (nj + 1));
+    memcpy(p->nodes, nodes, sizeof(double) * 2 * (size_t)(ni + 1) * (nj + 1));
     p->n1 = n1; p->n2 = n2; p->nv = n1 * n2;
     double *x1 = malloc(sizeof(double) * n1), *w1 = malloc(sizeof(double) * n1);
     double *x2 = malloc(sizeof(double) * n2), *w2 = malloc(sizeof(double) * n2);
@@ -408,6 +414,7 @@ void or_destroy(or_problem *p)
     free(p->wA); free(p->wn); free(p->wx); free(p->wa); free(p->wb);
     free(p->v); free(p->w); free(p->fd); free(p->gM); free(p->D); free(p->mJ);
     free(p->f); free(p->fn); free(p->W); free(p->F); free(p->phi); free(p->phin); free(p->cellred);
+    free(p->nodes);
     free(p);
 }
 
@@ -892,6 +899,109 @@ double or_adjoint_dJdp(or_problem *p, int which)
         }
     free(dR);
     return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* exact discrete shape derivative: complex step in the node coordinates */
+/* ------------------------------------------------------------------ */
+
+/* Face vectors (dy, -dx) of the edges corner q -> q+1 and the shoelace area
+ * of cell c, with coordinate d of node m shifted by i h. */
+static void cell_geometry_z(const or_problem *p, int c, int m, int d, double h, double complex S[4][2],
+                            double complex *V)
+{
+    int i = c % p->ni, j = c / p->ni;
+    int cid[4] = { node_id(p, i, j), node_id(p, i + 1, j), node_id(p, i + 1, j + 1), node_id(p, i, j + 1) };
+    double complex X[4], Y[4];
+    for (int q = 0; q < 4; q++) {
+        X[q] = p->nodes[2 * cid[q]] + ((cid[q] == m && d == 0) ? I * h : 0);
+        Y[q] = p->nodes[2 * cid[q] + 1] + ((cid[q] == m && d == 1) ? I * h : 0);
+    }
+    double complex A2 = 0;
+    for (int q = 0; q < 4; q++) {
+        int r = (q + 1) % 4;
+        A2 += (X[q] - X[0]) * (Y[r] - Y[0]) - (X[r] - X[0]) * (Y[q] - Y[0]);
+        S[q][0] = Y[r] - Y[q];
+        S[q][1] = -(X[r] - X[q]);
+    }
+    *V = 0.5 * A2;
+}
+
+/* d/dx of the discrete Lagrangian L = J + sum_{c,k} w_k phi_{c,k} . R_{c,k}
+ * (as in or_adjoint_dJdp) for every node coordinate x, with f and phi held
+ * fixed.  When f solves the primal equations and phi the adjoint equations
+ * this is dJ/dx of the discrete problem under mesh motion (the volume-mesh
+ * terms that the paper's wall-only derivative of Sec. 2.5 leaves out
+ * included).  Each coordinate in turn is shifted by i h; only the residuals
+ * of the cells with that node as a corner change (face vectors, volume and,
+ * for a wall cell, the element's normal and length through F_l, D_l and the
+ * diffuse wall value), and J only through those elements.  out has
+ * [(nj+1)(ni+1)][2] entries in the node numbering of the mesh. */
+void or_mesh_sensitivity(or_problem *p, double h, double *out)
+{
+    const int ni = p->ni, nj = p->nj, nv = p->nv, nn = (ni + 1) * (nj + 1);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(p->nthreads)
+    for (int m = 0; m < nn; m++) {
+        const int im = m % (ni + 1), jm = m / (ni + 1);
+        for (int d = 0; d < 2; d++) {
+            double complex L = 0;
+            for (int jc = jm - 1; jc <= jm; jc++) {
+                for (int ic = im - 1; ic <= im; ic++) {
+                    if (ic < 0 || ic >= ni || jc < 0 || jc >= nj) continue;
+                    const int c = ic + ni * jc;
+                    double complex S[4][2], V;
+                    cell_geometry_z(p, c, m, d, h, S, &V);
+                    const double *fc = p->f + (size_t)c * nv * 2;
+                    const double *pc = p->phi + (size_t)c * nv * 2;
+                    /* diffuse wall of this cell's j- face */
+                    const int nb0 = p->nbr[4 * c];
+                    const int l = nb0 <= -2 ? -2 - nb0 : -1;
+                    double complex A = 0, n1 = 0, n2 = 0, Fz = 0, Dz = 0;
+                    if (l >= 0) {
+                        A = csqrt(S[0][0] * S[0][0] + S[0][1] * S[0][1]);
+                        n1 = S[0][0] / A;
+                        n2 = S[0][1] / A;
+                        for (int k = 0; k < nv; k++) {
+                            double complex vn = p->v[2 * k] * n1 + p->v[2 * k + 1] * n2;
+                            if (creal(vn) > 0) Fz += p->w[k] * vn * fc[2 * k];
+                            else Dz -= p->w[k] * vn * p->gM[k];
+                        }
+                        /* J_l, eq. (numer_J) */
+                        for (int k = 0; k < nv; k++) {
+                            double complex vn = p->v[2 * k] * n1 + p->v[2 * k + 1] * n2;
+                            double complex f1 = creal(vn) > 0 ? fc[2 * k] : Fz * p->gM[k] / Dz;
+                            L += A * p->w[k] * p->mJ[k] * vn * f1;
+                        }
+                    }
+                    double rho, u1, u2, th;
+                    prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+                    const double itau = inv_tau_of(p, rho, th);
+                    for (int k = 0; k < nv; k++) {
+                        const double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+                        double complex r1 = 0, r2 = 0;
+                        for (int q = 0; q < 4; q++) {
+                            double complex sq = v1 * S[q][0] + v2 * S[q][1];
+                            double complex a1, a2;
+                            if (creal(sq) > 0) { a1 = fc[2 * k]; a2 = fc[2 * k + 1]; }
+                            else {
+                                int nb = p->nbr[4 * c + q];
+                                if (nb >= 0) { a1 = p->f[((size_t)nb * nv + k) * 2]; a2 = p->f[((size_t)nb * nv + k) * 2 + 1]; }
+                                else if (nb == -1) { a1 = p->fd[2 * k]; a2 = p->fd[2 * k + 1]; }
+                                else { a1 = Fz * p->gM[k] / Dz; a2 = 0.5 * p->theta_w * a1; }
+                            }
+                            r1 += sq * a1;
+                            r2 += sq * a2;
+                        }
+                        const double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+                        r1 += V * itau * (fc[2 * k] - g1);
+                        r2 += V * itau * (fc[2 * k + 1] - 0.5 * th * g1);
+                        L += p->w[k] * (pc[2 * k] * r1 + pc[2 * k + 1] * r2);
+                    }
+                }
+            }
+            out[2 * m + d] = cimag(L) / h;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------ */

@@ -160,6 +160,19 @@ int dvm_wall_sensitivity(dvm_solver *s, double *S_A, double *S_x, double *S_n, d
  * wall_jac[nw][2][n_params] (host, FP64), n_params <= DVM_MAX_PARAMS.  Runs
  * the sensitivity kernels first.  Synchronises. */
 int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, double *dJ_dalpha);
+/* Exact discrete shape derivative: dJ_dx[(nj+1)(ni+1)][2] (mesh node order,
+ * node (i, j) at index j*(ni+1)+i as in dvm_mesh_create) receives dL/dx for
+ * every node coordinate, L = J + sum_{c,k} w_k phi_c,k . R_c,k the discrete
+ * Lagrangian of Sec. 2.5 (R the residual of eq. numerpr_gov, J of eq.
+ * numer_J) with the current f and phi held fixed: face vectors, volumes,
+ * and the wall element normals and lengths (through F_l, D_l and J_l) all
+ * move with the nodes.  With converged primal and adjoint states this is
+ * the derivative of the discrete drag under mesh motion, including the
+ * volume-mesh terms that the wall-only form (dvm_wall_sensitivity) leaves
+ * out; chain it through the caller's d(nodes)/d(alpha).  The two copies of
+ * a periodic O-grid column (i = 0 and i = ni) are separate entries.
+ * Requires the adjoint phase (DVM_ESTATE otherwise).  Synchronises. */
+int dvm_mesh_sensitivity(dvm_solver *s, double *dJ_dx);
 
 /* Checkpoint / restore as raw bytes.  DVM_STATE_F: f in the storage
  * precision ([nc][nv][2]); loading it recomputes its moments and wall

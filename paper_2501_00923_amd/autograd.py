@@ -4,7 +4,9 @@
 shape parameters alpha), a velocity grid, a flow state and solve options.
 ``drag(alpha, case)`` returns J (FP64 scalar tensor); its backward runs the
 adjoint sweep and the wall sensitivity of the paper (Sec. 2.5 eq. sens_shape,
-Sec. 3.2) on the GPU and chains dJ/d(wall nodes) through d(wall nodes)/dalpha.
+Sec. 3.2) on the GPU and chains dJ/d(wall nodes) through d(wall nodes)/dalpha,
+or, with ``exact=True``, the exact discrete derivative in every mesh node
+chained through d(nodes)/dalpha.
 
 The fixed-point adjoint needs only the converged primal state, so the
 forward keeps that state on the device; with ``offload=True`` it instead
@@ -44,6 +46,7 @@ class ShapeCase:
     checkpoint_every: int = 0
     keep_checkpoints: Optional[int] = None   # None: keep every snapshot; n: only the last n
     offload: bool = False
+    exact: bool = False      # exact discrete derivative (every mesh node moves) instead of the wall-only form
 
 
 @dataclass
@@ -93,7 +96,7 @@ class _DragFn(torch.autograd.Function):
         _primal(case, solver, rec)
         J, Cd = solver.objective()
         rec.Cd = Cd
-        ctx.case, ctx.rec, ctx.wall_jac = case, rec, grid.wall_jac
+        ctx.case, ctx.rec, ctx.wall_jac, ctx.node_jac = case, rec, grid.wall_jac, grid.node_jac
         if case.offload:
             ctx.f_host = solver.state_save(dvm.STATE_F)
             solver.buffer = None          # release the device workspace
@@ -114,7 +117,10 @@ class _DragFn(torch.autograd.Function):
         else:
             it, r = solver.adjoint_iterate(o.adjoint_max_iter, o.adjoint_tol, o.check_every, raise_notconv=False)
         ctx.rec.adjoint_iters, ctx.rec.adjoint_resid = it, r
-        dJ = solver.param_sensitivity(ctx.wall_jac)
+        if case.exact:
+            dJ = np.einsum("jid,jidp->p", solver.mesh_sensitivity(), ctx.node_jac)
+        else:
+            dJ = solver.param_sensitivity(ctx.wall_jac)
         ctx.solver = None
         return torch.from_numpy(dJ) * gJ.detach().cpu().double(), None, None
 

@@ -236,9 +236,10 @@ int rule_1d(int kind, int n, double vmax, double param, std::vector<double> &x, 
 // ---------------------------------------------------------------------------
 struct dvm_solver {
     // problem
-    int topo, nc, nw, np, n1, n2, nv, mixed, want_adjoint, objective;
-    // mesh in device numbering (cell c of the mesh is device cell perm[c])
-    std::vector<int32_t> nbr, wall_cell, perm, pstart;
+    int topo, ni, nj, nc, nw, np, n1, n2, nv, mixed, want_adjoint, objective;
+    // mesh in device numbering (cell c of the mesh is device cell perm[c],
+    // device cell d is mesh cell cell_of[d])
+    std::vector<int32_t> nbr, wall_cell, perm, cell_of, pstart;
     std::vector<double> S, vol, wA, wn, wa, wb, D;
     std::vector<double> x1, w1, x2, w2;
     std::vector<double> fd;   // [nv][2]
@@ -247,8 +248,9 @@ struct dvm_solver {
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // workspace
     struct {
-        size_t nbr, patch, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
-        size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, out, total;
+        size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
+        size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, msens, dJdx, out,
+            total;
     } off;
     char *base = nullptr;
     hipStream_t stream = nullptr;
@@ -276,6 +278,7 @@ void layout(dvm_solver &s)
     auto &o = s.off;
     o.nbr = take(4 * nc * sizeof(int32_t));
     o.patch = take((s.np + 1) * sizeof(int32_t));
+    o.cell_of = take(nc * sizeof(int32_t));
     o.S = take(8 * nc * sizeof(double));
     o.vol = take(nc * sizeof(double));
     o.wall_cell = take(nw * sizeof(int32_t));
@@ -308,9 +311,11 @@ void layout(dvm_solver &s)
         o.dJdn = take(2 * nw * sizeof(double));
         o.jac = take(2 * nw * dvm::kMaxParams * sizeof(double));
         o.dJda = take(dvm::kMaxParams * sizeof(double));
+        o.msens = take(8 * nc * sizeof(double));
+        o.dJdx = take(2 * (size_t)(s.ni + 1) * (s.nj + 1) * sizeof(double));
     } else {
         o.phi[0] = o.phi[1] = o.aW[0] = o.aW[1] = o.Phi[0] = o.Phi[1] = o.acoef = o.sens = o.dJdn = o.jac =
-            o.dJda = (size_t)-1;
+            o.dJda = o.msens = o.dJdx = (size_t)-1;
     }
     o.Jl = take(nw * sizeof(double));
     o.out = take(16 * sizeof(double));
@@ -332,11 +337,14 @@ void fill_dev(dvm_solver &s)
     d.n1 = s.n1;
     d.n2 = s.n2;
     d.np = s.np;
+    d.ni = s.ni;
+    d.nj = s.nj;
     d.topo = s.topo;
     d.objective = s.objective;
     d.mixed = s.mixed;
     d.nbr = at<int32_t>(s, s.off.nbr);
     d.patch = at<int32_t>(s, s.off.patch);
+    d.cell_of = at<int32_t>(s, s.off.cell_of);
     d.S = at<double>(s, s.off.S);
     d.vol = at<double>(s, s.off.vol);
     d.wall_cell = at<int32_t>(s, s.off.wall_cell);
@@ -372,6 +380,8 @@ void fill_dev(dvm_solver &s)
     d.dJdn = at<double>(s, s.off.dJdn);
     d.jac = at<double>(s, s.off.jac);
     d.dJda = at<double>(s, s.off.dJda);
+    d.msens = at<double>(s, s.off.msens);
+    d.dJdx = at<double>(s, s.off.dJdx);
     d.out = at<double>(s, s.off.out);
 }
 
@@ -656,7 +666,11 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
         s->mixed = precision == DVM_MIXED;
         s->want_adjoint = want_adjoint ? 1 : 0;
         s->np = (int)m->pstart.size() - 1;
+        s->ni = m->ni;
+        s->nj = m->nj;
         s->perm = m->perm;
+        s->cell_of.resize(m->nc);
+        for (int c = 0; c < m->nc; c++) s->cell_of[m->perm[c]] = c;
         s->pstart = m->pstart;
         s->nbr.resize(m->nbr.size());
         s->S.resize(m->S.size());
@@ -716,6 +730,7 @@ int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream
     int e = 0;
     e = e ? e : upload(*s, o.nbr, s->nbr.data(), s->nbr.size() * sizeof(int32_t));
     e = e ? e : upload(*s, o.patch, s->pstart.data(), s->pstart.size() * sizeof(int32_t));
+    e = e ? e : upload(*s, o.cell_of, s->cell_of.data(), s->cell_of.size() * sizeof(int32_t));
     e = e ? e : upload(*s, o.S, s->S.data(), s->S.size() * sizeof(double));
     e = e ? e : upload(*s, o.vol, s->vol.data(), s->vol.size() * sizeof(double));
     e = e ? e : upload(*s, o.wall_cell, s->wall_cell.data(), s->wall_cell.size() * sizeof(int32_t));
@@ -884,6 +899,15 @@ int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, d
         return DVM_OK;
     }
     return read_back(*s, s->dev.dJda, dJ_dalpha, n_params);
+}
+
+int dvm_mesh_sensitivity(dvm_solver *s, double *dJ_dx)
+{
+    if (int e = check_bound(s)) return e;
+    if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+    if (!dJ_dx) return fail(DVM_EINVAL, "null output");
+    HIP_OK(dvm::launch_mesh_sens(s->dev, s->frozen_fpar, s->ppar, s->stream));
+    return read_back(*s, s->dev.dJdx, dJ_dx, 2 * (size_t)(s->ni + 1) * (s->nj + 1));
 }
 
 size_t dvm_state_bytes(const dvm_solver *s, int which)

@@ -27,12 +27,14 @@ constexpr int kTileI = 32, kTileJ = 16;
 struct DevSolve {
     int nc, nw, nv, n1, n2;
     int np;                  // patches
+    int ni, nj;              // structured grid size (cells along the wall, cells outward)
     int topo;
     int objective;
     int mixed;
     // mesh
     const int32_t *nbr;      // [nc][4] (device cell numbering)
     const int32_t *patch;    // [np + 1] first cell of each patch; patch p = cells [patch[p], patch[p+1])
+    const int32_t *cell_of;  // [nc] mesh cell number (i + ni*j) of each device cell
     const double *S;         // [nc][4][2]
     const double *vol;       // [nc]
     const int32_t *wall_cell;// [nw]
@@ -65,6 +67,8 @@ struct DevSolve {
     double *dJdn;            // [nw][2]
     double *jac;             // [nw][2][kMaxParams]
     double *dJda;            // [kMaxParams]
+    double *msens;           // [nc][4][2] per mesh cell: dL/d(corner coordinates)
+    double *dJdx;            // [(nj+1)(ni+1)][2] dL/d(node coordinates), mesh node numbering
     double *out;             // [16] small scalar outputs
 };
 
@@ -77,6 +81,7 @@ hipError_t launch_objective(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st);
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
+hipError_t launch_mesh_sens(const DevSolve &d, int fpar, int ppar, hipStream_t st);
 
 // batched: table of DevSolve on the device, per-block (solve, patch) map,
 // per-solve buffer parity at batch creation; step = sweeps done since batch

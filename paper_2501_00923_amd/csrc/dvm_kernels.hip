@@ -24,15 +24,9 @@
 
 #include <algorithm>
 
-#include "dvm_internal.h"
+#include "dvm_device.h"
 
 namespace dvm {
-
-template <typename T> struct Vec2;
-template <> struct Vec2<float> { using type = float2; };
-template <> struct Vec2<double> { using type = double2; };
-
-constexpr double kPi = 3.14159265358979323846;
 
 // Workgroups are handed to the 8 XCDs round-robin; give each XCD a
 // contiguous stretch of the sweep order (n items: cells or patches) so that
@@ -46,32 +40,6 @@ __device__ __forceinline__ int xcd_item(int n, int b)
     return idx < n ? idx : -1;
 }
 static inline int xcd_grid(int n) { return ((n + 7) >> 3) << 3; }
-
-// Sum N doubles over the workgroup; result valid in thread 0.  Fixed order.
-template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N], double *lds)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < N; i++) v[i] += __shfl_xor(v[i], off, 64);
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < N; i++) lds[wv * N + i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < N; i++) v[i] = ((lds[i] + lds[N + i]) + lds[2 * N + i]) + lds[3 * N + i];
-    }
-}
-
-__device__ __forceinline__ double mJ_of(int objective, double v1, double v2)
-{
-    return objective == 0 ? v1 : 0.5 * (v1 * v1 + v2 * v2);
-}
 
 // LDS of a patch sweep: the velocity tables, each cell's Maxwellian
 // factors and, for a sweep that exchanges rows (XCH), the double-buffered
@@ -103,31 +71,6 @@ __device__ __forceinline__ float recip(float x) { return 1.0f / x; }
 // costs more than the L2 requests it saves.
 template <typename T>
 constexpr bool kAdjointExchange = sizeof(T) == 8;
-
-// Sum N doubles over the wave (xor butterfly: every lane ends with the same
-// bits, the order is fixed).
-template <int N>
-__device__ __forceinline__ void wave_sum(double (&v)[N])
-{
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < N; i++) v[i] += __shfl_xor(v[i], off, kWave);
-    }
-}
-
-// Values that are the same in every lane of a wave (per-cell constants of a
-// patch sweep), moved to scalar registers so that they do not occupy
-// vector registers through the velocity loop.
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
-__device__ __forceinline__ double uni(double x)
-{
-    const long long v = __double_as_longlong(x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // Shared velocity tables (threads 0 .. n1+n2-1; a patch workgroup has at
 // least 4 waves, n1 + n2 <= 256) and this wave's Maxwellian factors
@@ -706,153 +649,8 @@ __global__ __launch_bounds__(kBlock) void k_objective_sum(DevSolve d)
 }
 
 // ---------------------------------------------------------------------------
-// wall sensitivity, eqs. (sens_J_itf), (gaussgrad), (sens_B_itf): one block
-// per wall element
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_wall_sens(DevSolve d, int fpar, int ppar)
-{
-    using T2 = typename Vec2<T>::type;
-    __shared__ double red[4 * 12];
-    const int l = blockIdx.x;
-    const int c = d.wall_cell[l];
-    const T2 *f = static_cast<const T2 *>(d.f[fpar]);
-    const T2 *ph = static_cast<const T2 *>(d.phi[ppar]);
-    const T2 *fd = static_cast<const T2 *>(d.fd);
-    const T *gM = static_cast<const T *>(d.gM);
-    const double n1 = d.wall_n[2 * l], n2 = d.wall_n[2 * l + 1], A = d.wall_A[l];
-    const double iD = 1.0 / d.D[l], F = d.F[fpar][l], thw2 = 0.5 * d.theta_w;
-    const double iV = 1.0 / d.vol[c];
-    int nb[4];
-    double Sx[4], Sy[4];
-    for (int q = 0; q < 4; q++) {
-        nb[q] = d.nbr[4 * c + q];
-        Sx[q] = d.S[8 * c + 2 * q];
-        Sy[q] = d.S[8 * c + 2 * q + 1];
-    }
-    double sa = 0, jx0 = 0, jx1 = 0, jn0 = 0, jn1 = 0, M0 = 0, M1 = 0, G0 = 0, G1 = 0, bx0 = 0, bx1 = 0, Pw = 0;
-    const size_t row = (size_t)c * d.nv;
-    for (int k = threadIdx.x; k < d.nv; k += kBlock) {
-        const int a = k % d.n1, b = k / d.n1;
-        const double v1 = d.vx[a], v2 = d.vy[b], w = d.wx[a] * d.wy[b];
-        const double vn = v1 * n1 + v2 * n2;
-        const double mj = mJ_of(d.objective, v1, v2);
-        const T2 fc = f[row + k];
-        const double gw1 = F * (double)gM[k] * iD;
-        const double f1l = vn > 0 ? (double)fc.x : gw1;
-        // Green-Gauss gradient with the scheme's upwind face values
-        double g10 = 0, g11 = 0, g20 = 0, g21 = 0;
-        for (int q = 0; q < 4; q++) {
-            const double s = v1 * Sx[q] + v2 * Sy[q];
-            double a1, a2;
-            if (s > 0) {
-                a1 = (double)fc.x;
-                a2 = (double)fc.y;
-            } else if (nb[q] >= 0) {
-                const T2 u = f[(size_t)nb[q] * d.nv + k];
-                a1 = (double)u.x;
-                a2 = (double)u.y;
-            } else if (nb[q] == -1) {
-                const T2 u = fd[k];
-                a1 = (double)u.x;
-                a2 = (double)u.y;
-            } else {
-                a1 = gw1;
-                a2 = thw2 * gw1;
-            }
-            g10 += a1 * Sx[q];
-            g11 += a1 * Sy[q];
-            g20 += a2 * Sx[q];
-            g21 += a2 * Sy[q];
-        }
-        g10 *= iV;
-        g11 *= iV;
-        g20 *= iV;
-        g21 *= iV;
-        sa += w * mj * vn * f1l;
-        jx0 += w * mj * vn * g10;
-        jx1 += w * mj * vn * g11;
-        jn0 += w * mj * v1 * f1l;
-        jn1 += w * mj * v2 * f1l;
-        M0 += w * v1 * f1l;
-        M1 += w * v2 * f1l;
-        if (vn > 0) {
-            G0 += w * vn * g10;
-            G1 += w * vn * g11;
-        } else {
-            const T2 pc = ph[row + k];
-            const double pw1 = -vn * ((double)pc.x + mj), pw2 = -vn * (double)pc.y;
-            bx0 += w * (pw1 * g10 + pw2 * g20);
-            bx1 += w * (pw1 * g11 + pw2 * g21);
-            const double gb1 = (double)gM[k] * iD;
-            Pw += w * (pw1 * gb1 + pw2 * thw2 * gb1);
-        }
-    }
-    double acc[12] = {sa, jx0, jx1, jn0, jn1, M0, M1, G0, G1, bx0, bx1, Pw};
-    block_sum<12>(acc, red);
-    if (threadIdx.x == 0) {
-        double *o = d.sens + 5 * l;
-        const double Phi = acc[11];
-        o[0] = acc[0];
-        o[1] = A * (acc[1] + acc[9] - Phi * acc[7]);
-        o[2] = A * (acc[2] + acc[10] - Phi * acc[8]);
-        o[3] = A * (acc[3] - Phi * acc[5]);
-        o[4] = A * (acc[4] - Phi * acc[6]);
-    }
-}
-
-// element -> node transform, eq. (sens_nod), then dJ/dalpha = dJ/dx . dx/dalpha
-__global__ __launch_bounds__(kBlock) void k_nodes_params(DevSolve d, int n_params)
-{
-    __shared__ double red[4];
-    const int nw = d.nw;
-    for (int m = threadIdx.x; m < nw; m += kBlock) {
-        double g[2] = {0, 0};
-        for (int side = 0; side < 2; side++) {
-            const int l = side == 0 ? m : (m + nw - 1) % nw;   // m is x_{l,1} of l = m, x_{l,2} of l = m-1
-            const double *o = d.sens + 5 * l;
-            const double ax = d.wall_a[2 * l], ay = d.wall_a[2 * l + 1];
-            const double bx = d.wall_b[2 * l], by = d.wall_b[2 * l + 1];
-            const double A = d.wall_A[l], n1 = d.wall_n[2 * l], n2 = d.wall_n[2 * l + 1];
-            const double sg = ((ax - bx) * n2 - (ay - by) * n1) > 0 ? 1.0 : -1.0;
-            const double sgn = side == 0 ? 1.0 : -1.0;     // d/db = -d/da for A and n
-            const double dA0 = (ax - bx) / A, dA1 = (ay - by) / A;
-            // (dn/da)^T S_n, dn/da = sg/A [[-n1 n2, -n2^2], [n1^2, n1 n2]]
-            const double t0 = sg / A * (-n1 * n2 * o[3] + n1 * n1 * o[4]);
-            const double t1 = sg / A * (-n2 * n2 * o[3] + n1 * n2 * o[4]);
-            g[0] += sgn * (o[0] * dA0 + t0) + 0.5 * o[1];
-            g[1] += sgn * (o[0] * dA1 + t1) + 0.5 * o[2];
-        }
-        d.dJdn[2 * m] = g[0];
-        d.dJdn[2 * m + 1] = g[1];
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (int p = 0; p < n_params; p++) {
-        double s = 0;
-        for (int m = threadIdx.x; m < nw; m += kBlock)
-            s += d.dJdn[2 * m] * d.jac[(2 * m) * kMaxParams + p] + d.dJdn[2 * m + 1] * d.jac[(2 * m + 1) * kMaxParams + p];
-        double acc[1] = {s};
-        block_sum<1>(acc, red);
-        if (threadIdx.x == 0) d.dJda[p] = acc[0];
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define DVM_DISPATCH(mixed, ...) \
-    do {                          \
-        if (mixed) {              \
-            using T = float;      \
-            __VA_ARGS__;          \
-        } else {                  \
-            using T = double;     \
-            __VA_ARGS__;          \
-        }                         \
-    } while (0)
-
 static inline int ew_grid(size_t n) { return (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192); }
 
 hipError_t launch_primal_init(const DevSolve &d, hipStream_t st)
@@ -914,14 +712,6 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st)
 {
     DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_adjoint_sweep<T>, dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0, st, d, par));
-    return hipGetLastError();
-}
-
-hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st)
-{
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_wall_sens<T>, dim3(d.nw), dim3(kBlock), 0, st, d, fpar, ppar));
-    if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_nodes_params, dim3(1), dim3(kBlock), 0, st, d, n_params);
     return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "dvm_solver_create", "dvm_solver_workspace_bytes", "dvm_solver_bind", "dvm_solver_set_stream",
     "dvm_primal_init", "dvm_primal_iterate", "dvm_primal_sweeps", "dvm_objective", "dvm_read_moments",
     "dvm_adjoint_init", "dvm_adjoint_iterate", "dvm_adjoint_sweeps",
-    "dvm_wall_sensitivity", "dvm_param_sensitivity",
+    "dvm_wall_sensitivity", "dvm_param_sensitivity", "dvm_mesh_sensitivity",
     "dvm_state_bytes", "dvm_state_save", "dvm_state_load",
     "dvm_batch_work_bytes", "dvm_batch_create", "dvm_batch_run", "dvm_batch_residual", "dvm_batch_destroy",
     "dvm_solver_iterations", "dvm_solver_phase", "dvm_last_error", "dvm_solver_destroy",
@@ -86,6 +86,7 @@ def lib():
         "dvm_adjoint_sweeps": (i32, [vp, i32]),
         "dvm_wall_sensitivity": (i32, [vp, vp, vp, vp, vp]),
         "dvm_param_sensitivity": (i32, [vp, i32, vp, vp]),
+        "dvm_mesh_sensitivity": (i32, [vp, vp]),
         "dvm_state_bytes": (sz, [vp, i32]),
         "dvm_state_save": (i32, [vp, i32, vp, sz]),
         "dvm_state_load": (i32, [vp, i32, vp, sz]),
@@ -211,6 +212,7 @@ class Solver:
                                        C.byref(h)))
         self._h = h
         self.nc, self.nw, self.nv = mesh.nc, mesh.nw, vgrid.nv
+        self.ni, self.nj = mesh.ni, mesh.nj
         self.precision = precision
         self.workspace_bytes = int(lib().dvm_solver_workspace_bytes(h))
         self.buffer = None
@@ -277,6 +279,12 @@ class Solver:
         dn = np.zeros((self.nw, 2))
         _check(lib().dvm_wall_sensitivity(self._h, _ptr(SA), _ptr(Sx), _ptr(Sn), _ptr(dn)))
         return dict(S_A=SA, S_x=Sx, S_n=Sn, dJ_dnodes=dn)
+
+    def mesh_sensitivity(self) -> np.ndarray:
+        """Exact discrete dJ/d(node coordinates), shape (nj+1, ni+1, 2)."""
+        out = np.zeros((self.nj + 1, self.ni + 1, 2))
+        _check(lib().dvm_mesh_sensitivity(self._h, _ptr(out)))
+        return out
 
     def param_sensitivity(self, wall_jac: np.ndarray) -> np.ndarray:
         wall_jac = np.ascontiguousarray(wall_jac, dtype=np.float64)

@@ -61,7 +61,8 @@ def test_autograd_matches_oracle_adjoint_and_offload_is_identical():
 def test_autograd_fd_agreement_paper_mode():
     """Central differences (h = 1e-6) of fully converged J against the
     adjoint gradient: sine modes vanish on both sides; the a0 and a2 modes
-    agree to the discretisation level of the wall-only shape derivative."""
+    agree to the discretisation level of the wall-only shape derivative, and
+    to the differences' own error with the exact discrete derivative."""
     case, a0 = AG.circle_fourier_case(32, 16, 8, 5.0, Kn=1.0, Ma=0.5, r_outer=5.0, stretch=1.2 ** 0.5,
                                       options=AG.SolveOptions(max_iter=30000, tol=1e-13, adjoint_tol=1e-13,
                                                               check_every=100))
@@ -81,6 +82,15 @@ def test_autograd_fd_agreement_paper_mode():
     assert abs(fd[5]) < 1e-6 and abs(g[5]) < 1e-10
     assert abs(g[0] - fd[0]) < 0.1 * abs(fd[0])
     assert abs(g[2] - fd[2]) < 0.05 * abs(fd[2])
+    # the exact discrete derivative (every mesh node moves with alpha) equals
+    # the differences to their own error
+    case.exact = True
+    alpha = torch.tensor(a0, requires_grad=True)
+    AG.drag(alpha, case).backward()
+    ge = alpha.grad.numpy()
+    _say(f"[gpu] exact {ge[[0, 2, 5]]}")
+    for p in (0, 2, 5):
+        assert abs(ge[p] - fd[p]) <= 1e-4 * max(abs(fd[0]), abs(fd[2]))
 
 
 def test_differentiation_workload_matches_oracle():

@@ -130,6 +130,9 @@ def test_fp64_primal_adjoint_sensitivity_parity(name):
         da = s.param_sensitivity(jac)
         do = np.einsum("md,mdp->p", go["dJ_dnodes"], jac)
         assert _rel(da, do) <= 1e-10
+    # exact discrete derivative in every node coordinate
+    ms, mo = s.mesh_sensitivity(), o.mesh_sensitivity()
+    assert _rel(ms, mo) <= 1e-10
 
 
 @pytest.mark.parametrize("name", ["tiny_circle", "o24x12_v20", "c_sinh36", "o13x7_odd"])
@@ -143,8 +146,9 @@ def test_mixed_precision_parity(name):
     eJ = abs(J - Jo) / abs(Jo)
     gs, go = s.wall_sensitivity(), o.wall_sensitivity()
     eS = _check_sens(gs, go, 1e-3)
-    _say(f"[mixed] {name}: f {ef:.2e}  J {eJ:.2e}  sens {eS:.2e}")
-    assert ef <= 2e-5 and eJ <= 2e-5 and eS <= 1e-3
+    eM = _rel(s.mesh_sensitivity(), o.mesh_sensitivity())
+    _say(f"[mixed] {name}: f {ef:.2e}  J {eJ:.2e}  sens {eS:.2e}  mesh sens {eM:.2e}")
+    assert ef <= 2e-5 and eJ <= 2e-5 and eS <= 1e-3 and eM <= 1e-3
 
 
 def test_c1_circle_full_size():

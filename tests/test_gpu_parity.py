@@ -84,13 +84,15 @@ def _case(name):
     if name == "c_odd":                            # C-grid 28 x 7: odd nj, wake cut; nv = 400
         g = I.naca_cgrid(5, 9, 7, t=0.12, m=0.03, r_outer=4.0, h1=0.03)
         return I.Workload("c_odd", g, I.VGridSpec(I.VG_MIDPOINT, 20, 20, 6.0), I.FlowSpec(0.3, 1.1), 0)
+    if name == "o12x6_v17":                        # odd n1: one velocity per lane in FP32 as well
+        return I.circle_case(12, 6, 17, 5.0, 0.7, 0.8, r_outer=4.0, stretch=1.2)
     if name == "v128_max":                         # the largest velocity grid, 128 x 128 = 16384
         return I.circle_case(6, 3, 128, 6.0, 0.8, 0.9, r_outer=3.0, stretch=1.3)
     raise KeyError(name)
 
 
 CASES = ["tiny_circle", "tiny_naca", "o24x12_v20", "c_nc24", "c_sinh36", "freemol", "heat_hotwall", "one_row",
-         "o13x7_odd", "c_odd", "v128_max"]
+         "o13x7_odd", "c_odd", "o12x6_v17", "v128_max"]
 
 
 def _run(wl, precision, n_primal, n_adjoint, n_params_jac=None):
@@ -135,7 +137,7 @@ def test_fp64_primal_adjoint_sensitivity_parity(name):
     assert _rel(ms, mo) <= 1e-10
 
 
-@pytest.mark.parametrize("name", ["tiny_circle", "o24x12_v20", "c_sinh36", "o13x7_odd"])
+@pytest.mark.parametrize("name", ["tiny_circle", "o24x12_v20", "c_sinh36", "o13x7_odd", "o12x6_v17"])
 def test_mixed_precision_parity(name):
     wl = _case(name)
     r = _run(wl, dvm.MIXED, 37, 29)

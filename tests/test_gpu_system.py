@@ -28,8 +28,11 @@ def _solver(wl, precision):
     return s
 
 
+# velocity grids 8^2, 8^2, 20^2 and 17^2: the last one (odd n1) takes the
+# one-velocity-per-lane path in FP32, the others the paired path
 MIX = [I.tiny_circle(Kn=1.0, Ma=0.5), I.tiny_naca(Kn=0.3, Ma=1.5),
-       I.circle_case(24, 12, 20, 5.0, 0.3, 0.9, r_outer=6.0, stretch=1.15)]
+       I.circle_case(24, 12, 20, 5.0, 0.3, 0.9, r_outer=6.0, stretch=1.15),
+       I.circle_case(10, 5, 17, 5.0, 0.6, 0.7, r_outer=4.0, stretch=1.2)]
 
 
 @pytest.mark.parametrize("precision", [dvm.FP64, dvm.MIXED])
@@ -79,10 +82,11 @@ def test_batch_residuals_match_single():
     assert r1 == r2
 
 
+@pytest.mark.parametrize("case", [2, 3])
 @pytest.mark.parametrize("precision", [dvm.FP64, dvm.MIXED])
-def test_checkpoint_resume_bitwise(precision):
-    _say(f"[gpu] checkpoint precision={precision}")
-    wl = MIX[2]
+def test_checkpoint_resume_bitwise(precision, case):
+    _say(f"[gpu] checkpoint precision={precision} case={case}")
+    wl = MIX[case]
     s = _solver(wl, precision)
     s.primal_sweeps(50)
     snap = s.state_save(dvm.STATE_F)

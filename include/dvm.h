@@ -139,7 +139,8 @@ int dvm_primal_sweeps(dvm_solver *s, int n);
 /* J of eq. (numer_J) for the current f, FP64; C_d = J / (u_inf^2 L / 2) with
  * L = 2 (O-grid: circle diameter) or 1 (C-grid: chord).  Synchronises. */
 int dvm_objective(dvm_solver *s, double *J, double *Cd);
-/* Conservative moments W[nc][4] of the current f (FP64). Synchronises. */
+/* Conservative moments W[nc][4] of the current f (FP64), cells in mesh
+ * order (c = i + ni*j).  Synchronises. */
 int dvm_read_moments(dvm_solver *s, double *W);
 
 /* Freeze the current f as the primal solution and set phi = 0. */
@@ -174,12 +175,13 @@ int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, d
  * Requires the adjoint phase (DVM_ESTATE otherwise).  Synchronises. */
 int dvm_mesh_sensitivity(dvm_solver *s, double *dJ_dx);
 
-/* Checkpoint / restore as raw bytes.  DVM_STATE_F: f in the storage
- * precision ([nc][nv][2]); loading it recomputes its moments and wall
- * fluxes (bitwise as the sweep computes them) and starts a primal phase.
- * DVM_STATE_PHI: phi followed by its FP64 adjoint moments ([nc][8]) and wall
- * multipliers ([nw]); needs an adjoint phase.  Resuming from a snapshot
- * reproduces the iterates bitwise.  save synchronises. */
+/* Checkpoint / restore as raw bytes, cells in mesh order (c = i + ni*j)
+ * whatever the library's internal cell numbering.  DVM_STATE_F: f in the
+ * storage precision ([nc][nv][2]); loading it recomputes its moments and
+ * wall fluxes (bitwise as the sweep computes them) and starts a primal
+ * phase.  DVM_STATE_PHI: phi followed by its FP64 adjoint moments ([nc][8])
+ * and wall multipliers ([nw]); needs an adjoint phase.  Resuming from a
+ * snapshot reproduces the iterates bitwise.  Both synchronise. */
 size_t dvm_state_bytes(const dvm_solver *s, int which);
 int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes);
 int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes);

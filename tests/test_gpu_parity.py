@@ -86,13 +86,15 @@ def _case(name):
         return I.Workload("c_odd", g, I.VGridSpec(I.VG_MIDPOINT, 20, 20, 6.0), I.FlowSpec(0.3, 1.1), 0)
     if name == "o12x6_v17":                        # odd n1: one velocity per lane in FP32 as well
         return I.circle_case(12, 6, 17, 5.0, 0.7, 0.8, r_outer=4.0, stretch=1.2)
+    if name == "o70x20_tiles":                     # 3 x 2 sweep tiles of 32 x 16 with ragged last ones
+        return I.circle_case(70, 20, 12, 5.0, 0.5, 0.9, r_outer=6.0, stretch=1.12)
     if name == "v128_max":                         # the largest velocity grid, 128 x 128 = 16384
         return I.circle_case(6, 3, 128, 6.0, 0.8, 0.9, r_outer=3.0, stretch=1.3)
     raise KeyError(name)
 
 
 CASES = ["tiny_circle", "tiny_naca", "o24x12_v20", "c_nc24", "c_sinh36", "freemol", "heat_hotwall", "one_row",
-         "o13x7_odd", "c_odd", "o12x6_v17", "v128_max"]
+         "o13x7_odd", "c_odd", "o12x6_v17", "o70x20_tiles", "v128_max"]
 
 
 def _run(wl, precision, n_primal, n_adjoint, n_params_jac=None):

@@ -4,8 +4,10 @@ Requests (a shape, mesh and velocity-grid size, Kn, Ma, and whether the
 adjoint sensitivities are wanted) arrive over time.  The server admits a
 pending request as soon as its exact device footprint fits the memory
 budget, keeps every admitted solve's state resident, and advances all
-resident solves together: one kernel launch per sweep covers every cell of
-every resident solve (primal-phase and adjoint-phase members alike).  Every
+resident solves together: each sweep is two kernel launches, one over the
+cells of every primal-phase solve and one over every adjoint-phase solve.
+Requests are admitted in arrival order, except that a request that does not
+fit yet lets later, smaller ones pass (it waits for memory to free).  Every
 ``q`` sweeps it reads the residuals; a converged (or capped) primal either
 switches to its adjoint phase or finishes, a finished solve reads out J
 (and dJ/dalpha), frees its memory, and the freed memory admits waiting

@@ -380,12 +380,13 @@ def main():
     b_adj = bytes_per_update("adjoint", False) * pairs
     b_pri = bytes_per_update("primal", False) * pairs
     achieved = b_adj / t_adj / 1e9
-    traffic = None
+    traffic, tr = None, {}
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_sha") == kernel_hash():
-            traffic = tr.get("adjoint_fp64_bytes_per_launch")
+        if tr.get("kernel_sha") != kernel_hash():
+            tr = {}            # counters taken on other kernel code: not this code's traffic
+        traffic = tr.get("adjoint_fp64_bytes_per_launch")
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_adjoint_sweep<double>",
@@ -393,7 +394,16 @@ def main():
             "avg_launch_ms": r64["adjoint_sweep_ms"],
             "primal": {"kernel": "k_primal_sweep<double>", "achieved": b_pri / t_pri / 1e9,
                        "frac": b_pri / t_pri / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": r64["primal_sweep_ms"],
-                       "algorithmic_bytes_per_launch": b_pri}}
+                       "algorithmic_bytes_per_launch": b_pri,
+                       "traffic": tr.get("primal_fp64_bytes_per_launch")}}
+    if mixed is not None:
+        for kind, key in (("adjoint", "adjoint_sweep_ms"), ("primal", "primal_sweep_ms")):
+            b = bytes_per_update(kind, True) * pairs
+            t = mixed[key] * 1e-3
+            roof[f"{kind}_mixed"] = {"kernel": f"k_{kind}_sweep<float>", "achieved": b / t / 1e9,
+                                     "frac": b / t / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": mixed[key],
+                                     "algorithmic_bytes_per_launch": b,
+                                     "traffic": tr.get(f"{kind}_mixed_bytes_per_launch")}
     serving = None
     if args.serving_requests > 0:
         print(f"[bench] serving leg: {args.serving_requests} requests", file=sys.stderr, flush=True)

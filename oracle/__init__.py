@@ -78,6 +78,10 @@ def lib():
         L.or_mesh_sensitivity.argtypes = [P, D, dp]
         L.or_wall_JB.restype = D
         L.or_wall_JB.argtypes = [P, I, D, D, D, D, D]
+        L.or_set_scheme.restype = I
+        L.or_set_scheme.argtypes = [P, I, I, I]
+        L.or_so_slopes.argtypes = [P, dp, dp, dp]
+        L.or_so_faces.argtypes = [P, dp, dp]
         _lib = L
     return _lib
 
@@ -131,6 +135,31 @@ class Problem:
         lib().or_sizes(self._h, s)
         self.nc, self.nw, self.nv, self.n1, self.n2 = (int(x) for x in s[:5])
         self.ni, self.nj = int(ni), int(nj)
+        self.order = 1
+
+    def set_scheme(self, order: int = 2, limiter: bool = True, correction_every: int = 5):
+        """Spatial order 1 (first-order upwind) or 2 (Green-Gauss slopes with an
+        optional Barth-Jespersen limiter, iterated by defect correction with the
+        correction re-evaluated every `correction_every` sweeps)."""
+        if lib().or_set_scheme(self._h, int(order), 1 if limiter else 0, int(correction_every)) != 0:
+            raise ValueError("oracle: invalid scheme")
+        self.order = int(order)
+
+    def so_slopes(self, f=None):
+        """Limited slopes G[c, k, component, direction] and limiter factors
+        psi[c, k, component] of f (default: the current f)."""
+        f = self.f if f is None else np.ascontiguousarray(f, dtype=np.float64)
+        G = np.zeros((self.nc, self.nv, 2, 2))
+        psi = np.zeros((self.nc, self.nv, 2))
+        lib().or_so_slopes(self._h, f, G, psi)
+        return G, psi
+
+    def so_faces(self, f=None):
+        """Second-order face values [c, q, k, component] on each face's upwind side."""
+        f = self.f if f is None else np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros((self.nc, 4, self.nv, 2))
+        lib().or_so_faces(self._h, f, out)
+        return out
 
     @classmethod
     def from_workload(cls, wl, nthreads=None, Kn=None, Ma=None, Tw=None):
@@ -268,6 +297,8 @@ class Problem:
         return lib().or_adjoint_dJdp(self._h, which)
 
     def wall_sensitivity(self):
+        if self.order != 1:
+            raise ValueError("oracle: the wall sensitivity is implemented for the first-order scheme")
         SA = np.zeros(self.nw)
         Sx = np.zeros((self.nw, 2))
         Sn = np.zeros((self.nw, 2))
@@ -278,6 +309,8 @@ class Problem:
     def mesh_sensitivity(self, h: float = 1e-30):
         """dL/dx for every mesh node coordinate, shape (nj+1, ni+1, 2): the
         exact discrete shape derivative at converged f and phi."""
+        if self.order != 1:
+            raise ValueError("oracle: the mesh sensitivity is implemented for the first-order scheme")
         out = np.zeros((self.nj + 1, self.ni + 1, 2))
         lib().or_mesh_sensitivity(self._h, float(h), out)
         return out

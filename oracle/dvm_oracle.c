@@ -22,6 +22,7 @@
  *                                                     Sec. 3.1, eq. (numerad_gov)
  *   wall-element derivatives of J and B_w             Sec. 3.2, eqs. (sens_J_itf), (gaussgrad), (sens_B_itf)
  *   element -> node transform                         Sec. 3.2, eq. (sens_nod)
+ *   second-order spatial reconstruction               Sec. 3.1 (readings in its section below)
  *
  * Readings where the paper is silent (the paper omits its solver scheme,
  * Sec. 3.1):
@@ -61,6 +62,14 @@
  * (or_mesh_sensitivity, the Lagrangian differentiated in every node
  * coordinate by complex step) is pinned by translation invariance and by
  * central differences of the re-converged drag under shape change.
+ * Second-order scheme (tests/test_oracle_second_order.py): exact slopes and
+ * face values for linear fields on equal parallelograms; Barth-Jespersen
+ * bounds; the defect-correction fixed point solves R2 = 0 independently of
+ * the correction interval; drag converges at second order under O-grid
+ * refinement (first order for the first-order scheme); dot-product identity
+ * of the frozen-limiter adjoint against the complex twin of R2 and J;
+ * unlimited adjoint dJ/dp against central differences.  The wall and mesh
+ * sensitivities are first-order only.
  */
 #include <complex.h>
 #include <math.h>
@@ -105,6 +114,16 @@ typedef struct {
     double *cellred;   /* [nc][2] residual partials */
     double *nodes;     /* [(nj+1)(ni+1)][2] mesh node coordinates */
     int nthreads;
+
+    /* second-order scheme (order 2; see "second-order reconstruction") */
+    int order, limiter, kcorr;
+    double *fm;        /* [nc][4][2] face midpoints */
+    double *corr;      /* [nc][nv][2] held second-order flux correction */
+    double *dF;        /* [nw] held wall-flux correction */
+    int corr_ok, since;
+    double *psi;       /* [nc][nv][2] limiter of the frozen f (adjoint) */
+    double *acorr;     /* [nc][nv][2] held adjoint reconstruction term */
+    int acorr_ok, asince;
 } or_problem;
 
 /* ------------------------------------------------------------------ */
@@ -257,6 +276,7 @@ static int build_mesh(or_problem *p, const double *nodes)
     p->S = malloc(sizeof(double) * 8 * p->nc);
     p->vol = malloc(sizeof(double) * p->nc);
     p->cen = malloc(sizeof(double) * 2 * p->nc);
+    p->fm = malloc(sizeof(double) * 8 * p->nc);
     p->wall_cell = malloc(sizeof(int) * p->nw);
     p->wall_face = malloc(sizeof(int) * p->nw);
     p->wA = malloc(sizeof(double) * p->nw);
@@ -294,6 +314,8 @@ static int build_mesh(or_problem *p, const double *nodes)
                 int r = (q + 1) % 4;
                 p->S[8 * c + 2 * q] = Y[r] - Y[q];
                 p->S[8 * c + 2 * q + 1] = -(X[r] - X[q]);
+                p->fm[8 * c + 2 * q] = 0.5 * (X[q] + X[r]);
+                p->fm[8 * c + 2 * q + 1] = 0.5 * (Y[q] + Y[r]);
             }
             /* neighbours */
             int *nb = p->nbr + 4 * c;
@@ -403,6 +425,7 @@ or_problem *or_create(int topo, int ni, int nj, int nwake, const double *nodes,
     p->W = malloc(sizeof(double) * 4 * p->nc);
     p->F = malloc(sizeof(double) * p->nw);
     p->cellred = malloc(sizeof(double) * 2 * p->nc);
+    p->order = 1; p->limiter = 1; p->kcorr = 5;
     if (!p->f || !p->fn || !p->phi || !p->phin) return NULL;
     return p;
 }
@@ -415,6 +438,7 @@ void or_destroy(or_problem *p)
     free(p->v); free(p->w); free(p->fd); free(p->gM); free(p->D); free(p->mJ);
     free(p->f); free(p->fn); free(p->W); free(p->F); free(p->phi); free(p->phin); free(p->cellred);
     free(p->nodes);
+    free(p->fm); free(p->corr); free(p->dF); free(p->psi); free(p->acorr);
     free(p);
 }
 
@@ -483,10 +507,13 @@ void or_primal_init(or_problem *p)
     for (int c = 0; c < p->nc; c++)
         memcpy(p->f + (size_t)c * nv * 2, p->fd, sizeof(double) * 2 * nv);
     update_W_F(p, p->f);
+    p->corr_ok = 0;
 }
 
-/* value of f carried into cell c through face q at velocity k (s <= 0) */
-static void inflow_value(const or_problem *p, const double *f, int c, int q, int k, double *o1, double *o2)
+/* value of f carried into cell c through face q at velocity k (s <= 0);
+ * Fw: the wall fluxes F_l of the diffuse wall value */
+static void inflow_value(const or_problem *p, const double *f, const double *Fw, int c, int q, int k,
+                         double *o1, double *o2)
 {
     int nb = p->nbr[4 * c + q];
     if (nb >= 0) {
@@ -497,9 +524,207 @@ static void inflow_value(const or_problem *p, const double *f, int c, int q, int
     } else {
         int l = -2 - nb;
         double gb1 = p->gM[k] / p->D[l];           /* eq. (barg) */
-        *o1 = p->F[l] * gb1;
-        *o2 = p->F[l] * 0.5 * p->theta_w * gb1;
+        *o1 = Fw[l] * gb1;
+        *o2 = Fw[l] * 0.5 * p->theta_w * gb1;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* second-order reconstruction                                         */
+/* ------------------------------------------------------------------ */
+/* Sec. 3.1 states second-order accuracy in physical space for both the
+ * primal and the adjoint balance and leaves the scheme to its references.
+ * Readings taken here (order 2):
+ *   - a cell value sits at the cell's area centroid x_c; the gradient is
+ *     Green-Gauss, grad f_c = (1/V_c) sum_q fbar_q S_cq, with fbar the mean
+ *     of the two cell values on an interior face and f_c on a boundary face;
+ *   - Barth-Jespersen limiter, per cell, velocity and component: psi is the
+ *     largest factor in [0, 1] for which f_c + psi grad f_c . (m_q - x_c)
+ *     stays between the minimum and maximum of f over the cell and its
+ *     interior neighbours at every face midpoint m_q;
+ *   - the value of a face is reconstructed on its upwind side,
+ *     f_u + psi_u grad f_u . (m_q - x_u); inflow from the far field stays
+ *     f_d, inflow from the wall stays F_l gbar, with F_l summed over the
+ *     reconstructed outgoing wall values; the drag uses the same wall values;
+ *   - iteration by defect correction: every K sweeps the difference c
+ *     between the second- and first-order face fluxes of each cell, and the
+ *     difference dF of the wall fluxes, are evaluated from the current f
+ *     and held; each sweep is the first-order Jacobi sweep with -c in its
+ *     numerator and F + dF as wall flux.  A fixed point solves the
+ *     second-order balance R2(f) = 0.  (Applying the correction in every
+ *     sweep, K = 1, is a forward-Euler pseudo-time step of the second-order
+ *     operator and diverges where transport dominates.)
+ *   - adjoint: the limiter factors psi of the converged f are frozen; the
+ *     adjoint is the exact transpose of the frozen-limiter linearisation of
+ *     R2 and J, iterated the same way: its reconstruction term E is
+ *     re-evaluated every K sweeps. */
+
+/* Green-Gauss gradient g[component][direction] of f at cell c, velocity k */
+static void so_grad(const or_problem *p, const double *f, int c, int k, double g[2][2])
+{
+    const int nv = p->nv;
+    const double *fc = f + ((size_t)c * nv + k) * 2;
+    g[0][0] = g[0][1] = g[1][0] = g[1][1] = 0;
+    for (int q = 0; q < 4; q++) {
+        int nb = p->nbr[4 * c + q];
+        double b1 = fc[0], b2 = fc[1];
+        if (nb >= 0) {
+            const double *fj = f + ((size_t)nb * nv + k) * 2;
+            b1 = 0.5 * (fc[0] + fj[0]);
+            b2 = 0.5 * (fc[1] + fj[1]);
+        }
+        double Sx = p->S[8 * c + 2 * q], Sy = p->S[8 * c + 2 * q + 1];
+        g[0][0] += b1 * Sx; g[0][1] += b1 * Sy;
+        g[1][0] += b2 * Sx; g[1][1] += b2 * Sy;
+    }
+    for (int m = 0; m < 2; m++) { g[m][0] /= p->vol[c]; g[m][1] /= p->vol[c]; }
+}
+
+/* Barth-Jespersen factor of each component for the gradient g */
+static void so_limit(const or_problem *p, const double *f, int c, int k, const double g[2][2], double psi[2])
+{
+    const int nv = p->nv;
+    psi[0] = psi[1] = 1.0;
+    if (!p->limiter) return;
+    const double *fc = f + ((size_t)c * nv + k) * 2;
+    for (int m = 0; m < 2; m++) {
+        double lo = fc[m], hi = fc[m];
+        for (int q = 0; q < 4; q++) {
+            int nb = p->nbr[4 * c + q];
+            if (nb < 0) continue;
+            double v = f[((size_t)nb * nv + k) * 2 + m];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        for (int q = 0; q < 4; q++) {
+            double rx = p->fm[8 * c + 2 * q] - p->cen[2 * c], ry = p->fm[8 * c + 2 * q + 1] - p->cen[2 * c + 1];
+            double d = g[m][0] * rx + g[m][1] * ry;
+            double r = 1.0;
+            if (d > 0) r = (hi - fc[m]) / d;
+            else if (d < 0) r = (lo - fc[m]) / d;
+            if (r < psi[m]) psi[m] = r;
+        }
+    }
+}
+
+/* limited slopes G = psi grad f, [nc][nv][2 components][2 directions], and
+ * optionally the factors psi [nc][nv][2] */
+static void so_slopes(const or_problem *p, const double *f, double *G, double *psi)
+{
+    const int nv = p->nv;
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+    for (int c = 0; c < p->nc; c++)
+        for (int k = 0; k < nv; k++) {
+            double g[2][2], ps[2];
+            so_grad(p, f, c, k, g);
+            so_limit(p, f, c, k, g, ps);
+            double *o = G + ((size_t)c * nv + k) * 4;
+            o[0] = ps[0] * g[0][0]; o[1] = ps[0] * g[0][1];
+            o[2] = ps[1] * g[1][0]; o[3] = ps[1] * g[1][1];
+            if (psi) { psi[((size_t)c * nv + k) * 2] = ps[0]; psi[((size_t)c * nv + k) * 2 + 1] = ps[1]; }
+        }
+}
+
+/* reconstruction increment of face q of cell c at velocity k, component m,
+ * from the face's upwind side (s = v.S_cq): the cell itself (s > 0), the
+ * interior neighbour (s <= 0), none for inflow through a boundary */
+static double so_delta(const or_problem *p, const double *G, int c, int q, int k, int m, double s)
+{
+    int u = c;
+    if (!(s > 0)) {
+        u = p->nbr[4 * c + q];
+        if (u < 0) return 0.0;
+    }
+    const double *g = G + ((size_t)u * p->nv + k) * 4 + 2 * m;
+    double rx = p->fm[8 * c + 2 * q] - p->cen[2 * u], ry = p->fm[8 * c + 2 * q + 1] - p->cen[2 * u + 1];
+    return g[0] * rx + g[1] * ry;
+}
+
+/* dF_l = sum_{v.n > 0} w (v.n) (reconstructed - cell value of f1) at the wall */
+static void so_wall_dF(const or_problem *p, const double *G, double *dF)
+{
+    for (int l = 0; l < p->nw; l++) {
+        int c = p->wall_cell[l];
+        double n1 = p->wn[2 * l], n2 = p->wn[2 * l + 1], acc = 0;
+        for (int k = 0; k < p->nv; k++) {
+            double vn = p->v[2 * k] * n1 + p->v[2 * k + 1] * n2;
+            if (vn > 0) acc += p->w[k] * vn * so_delta(p, G, c, p->wall_face[l], k, 0, 1.0);
+        }
+        dF[l] = acc;
+    }
+}
+
+/* c = sum_q (v.S_q)(second-order - first-order face value) and dF of f */
+static void so_correction(or_problem *p, const double *f)
+{
+    const int nv = p->nv;
+    double *G = malloc(sizeof(double) * 4 * (size_t)p->nc * nv);
+    so_slopes(p, f, G, NULL);
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+    for (int c = 0; c < p->nc; c++)
+        for (int k = 0; k < nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], c1 = 0, c2 = 0;
+            for (int q = 0; q < 4; q++) {
+                double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                c1 += s * so_delta(p, G, c, q, k, 0, s);
+                c2 += s * so_delta(p, G, c, q, k, 1, s);
+            }
+            p->corr[((size_t)c * nv + k) * 2] = c1;
+            p->corr[((size_t)c * nv + k) * 2 + 1] = c2;
+        }
+    so_wall_dF(p, G, p->dF);
+    free(G);
+}
+
+static void so_alloc(or_problem *p)
+{
+    size_t n = (size_t)p->nc * p->nv * 2;
+    if (!p->corr) p->corr = calloc(n, sizeof(double));
+    if (!p->dF) p->dF = calloc(p->nw, sizeof(double));
+    if (!p->psi) p->psi = calloc(n, sizeof(double));
+    if (!p->acorr) p->acorr = calloc(n, sizeof(double));
+}
+
+/* order 1 or 2; limiter 0 (none) or 1 (Barth-Jespersen); K >= 1 sweeps
+ * between evaluations of the held correction.  Returns 0, or -1 for an
+ * invalid setting. */
+int or_set_scheme(or_problem *p, int order, int limiter, int kcorr)
+{
+    if ((order != 1 && order != 2) || (limiter != 0 && limiter != 1) || kcorr < 1) return -1;
+    p->order = order; p->limiter = limiter; p->kcorr = kcorr;
+    if (order == 2) so_alloc(p);
+    p->corr_ok = p->acorr_ok = 0;
+    return 0;
+}
+
+/* limited slopes and limiter factors of f (pins) */
+void or_so_slopes(or_problem *p, const double *f, double *G, double *psi) { so_slopes(p, f, G, psi); }
+
+/* the face values R2 uses: for every cell c, face q and velocity k the
+ * value on the face's upwind side, out [nc][4][nv][2] */
+void or_so_faces(or_problem *p, const double *f, double *out)
+{
+    const int nv = p->nv;
+    double *G = malloc(sizeof(double) * 4 * (size_t)p->nc * nv), *F2 = malloc(sizeof(double) * p->nw);
+    double *Ws = malloc(sizeof(double) * 4 * p->nc), *Fs = malloc(sizeof(double) * p->nw);
+    memcpy(Ws, p->W, sizeof(double) * 4 * p->nc); memcpy(Fs, p->F, sizeof(double) * p->nw);
+    update_W_F(p, f);
+    so_slopes(p, f, G, NULL);
+    so_wall_dF(p, G, F2);
+    for (int l = 0; l < p->nw; l++) F2[l] += p->F[l];
+    for (int c = 0; c < p->nc; c++)
+        for (int q = 0; q < 4; q++)
+            for (int k = 0; k < nv; k++) {
+                double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+                double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1], a1, a2;
+                if (s > 0) { a1 = f[((size_t)c * nv + k) * 2]; a2 = f[((size_t)c * nv + k) * 2 + 1]; }
+                else inflow_value(p, f, F2, c, q, k, &a1, &a2);
+                double *o = out + (((size_t)c * 4 + q) * nv + k) * 2;
+                o[0] = a1 + so_delta(p, G, c, q, k, 0, s);
+                o[1] = a2 + so_delta(p, G, c, q, k, 1, s);
+            }
+    memcpy(p->W, Ws, sizeof(double) * 4 * p->nc); memcpy(p->F, Fs, sizeof(double) * p->nw);
+    free(G); free(F2); free(Ws); free(Fs);
 }
 
 /* One Jacobi sweep of eq. (numerpr_gov), every cell from f^n.  Returns the
@@ -508,7 +733,15 @@ double or_primal_iterate(or_problem *p, int niter)
 {
     const int nv = p->nv;
     double r = 0;
+    double *Fw = malloc(sizeof(double) * (p->nw > 0 ? p->nw : 1));
     for (int it = 0; it < niter; it++) {
+        const int so = p->order == 2;
+        if (so && (!p->corr_ok || p->since == p->kcorr)) {
+            so_correction(p, p->f);
+            p->corr_ok = 1;
+            p->since = 0;
+        }
+        for (int l = 0; l < p->nw; l++) Fw[l] = p->F[l] + (so ? p->dF[l] : 0.0);
 #pragma omp parallel for schedule(static) num_threads(p->nthreads)
         for (int c = 0; c < p->nc; c++) {
             double rho, u1, u2, th;
@@ -523,9 +756,13 @@ double or_primal_iterate(or_problem *p, int niter)
                     if (s > 0) out += s;
                     else {
                         double a1, a2;
-                        inflow_value(p, p->f, c, q, k, &a1, &a2);
+                        inflow_value(p, p->f, Fw, c, q, k, &a1, &a2);
                         in1 -= s * a1; in2 -= s * a2;
                     }
+                }
+                if (so) {
+                    in1 -= p->corr[((size_t)c * nv + k) * 2];
+                    in2 -= p->corr[((size_t)c * nv + k) * 2 + 1];
                 }
                 double g1 = maxwell1(rho, u1, u2, th, v1, v2), g2 = 0.5 * th * g1;
                 double den = out + V * itau;
@@ -534,6 +771,7 @@ double or_primal_iterate(or_problem *p, int niter)
                 fo[1] = (in2 + V * itau * g2) / den;
             }
         }
+        if (so) p->since++;
         /* residual on W */
         double *Wold = malloc(sizeof(double) * 4 * p->nc);
         memcpy(Wold, p->W, sizeof(double) * 4 * p->nc);
@@ -548,14 +786,15 @@ double or_primal_iterate(or_problem *p, int niter)
         free(Wold);
         r = sqrt(num / den);
     }
+    free(Fw);
     return r;
 }
 
 void or_get_f(const or_problem *p, double *out) { memcpy(out, p->f, sizeof(double) * (size_t)p->nc * p->nv * 2); }
-void or_set_f(or_problem *p, const double *in) { memcpy(p->f, in, sizeof(double) * (size_t)p->nc * p->nv * 2); update_W_F(p, p->f); }
+void or_set_f(or_problem *p, const double *in) { memcpy(p->f, in, sizeof(double) * (size_t)p->nc * p->nv * 2); update_W_F(p, p->f); p->corr_ok = 0; }
 void or_get_W(const or_problem *p, double *out) { memcpy(out, p->W, sizeof(double) * 4 * p->nc); }
 void or_get_phi(const or_problem *p, double *out) { memcpy(out, p->phi, sizeof(double) * (size_t)p->nc * p->nv * 2); }
-void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); }
+void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); p->acorr_ok = 0; }
 
 /* wall value f1_{l,k}: cell value on Xi^+, F_l gbar1 on Xi^- (Sec. 3.2) */
 static double wall_f1(const or_problem *p, const double *f, int l, int k)
@@ -565,19 +804,36 @@ static double wall_f1(const or_problem *p, const double *f, int l, int k)
     return p->F[l] * p->gM[k] / p->D[l];
 }
 
-/* J = sum_l A_l sum_k w m_J (v.n) f1_{l,k}, eq. (numer_J); per element into Jl */
+/* J = sum_l A_l sum_k w m_J (v.n) f1_{l,k}, eq. (numer_J); per element into Jl.
+ * Order 2: the outgoing wall values are reconstructed from the current f and
+ * the incoming ones use the matching F_l + dF_l. */
 double or_objective(const or_problem *p, double *Jl)
 {
     double J = 0;
+    double *G = NULL;
+    if (p->order == 2) {
+        G = malloc(sizeof(double) * 4 * (size_t)p->nc * p->nv);
+        so_slopes(p, p->f, G, NULL);
+    }
     for (int l = 0; l < p->nw; l++) {
-        double s = 0;
+        double s = 0, F2 = p->F[l];
+        int c = p->wall_cell[l], q0 = p->wall_face[l];
+        if (G) {
+            for (int k = 0; k < p->nv; k++) {
+                double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
+                if (vn > 0) F2 += p->w[k] * vn * so_delta(p, G, c, q0, k, 0, 1.0);
+            }
+        }
         for (int k = 0; k < p->nv; k++) {
             double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
-            s += p->w[k] * p->mJ[k] * vn * wall_f1(p, p->f, l, k);
+            double f1 = wall_f1(p, p->f, l, k);
+            if (G) f1 = vn > 0 ? f1 + so_delta(p, G, c, q0, k, 0, 1.0) : F2 * p->gM[k] / p->D[l];
+            s += p->w[k] * p->mJ[k] * vn * f1;
         }
         if (Jl) Jl[l] = p->wA[l] * s;
         J += p->wA[l] * s;
     }
+    free(G);
     return J;
 }
 
@@ -594,6 +850,34 @@ double or_cd_scale(const or_problem *p)
 void or_primal_residual(or_problem *p, const double *f, double *out)
 {
     const int nv = p->nv;
+    if (p->order == 2) {
+        /* R2 = sum_q (v.S_q) f_q (second-order face values) + V (f - g) / tau */
+        double *fq = malloc(sizeof(double) * 8 * (size_t)p->nc * nv);
+        or_so_faces(p, f, fq);
+        double *Wsave = malloc(sizeof(double) * 4 * p->nc);
+        memcpy(Wsave, p->W, sizeof(double) * 4 * p->nc);
+        for (int c = 0; c < p->nc; c++) or_moments(nv, p->v, p->w, f + (size_t)c * nv * 2, p->W + 4 * c);
+        for (int c = 0; c < p->nc; c++) {
+            double rho, u1, u2, th;
+            prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+            double itau = inv_tau_of(p, rho, th), V = p->vol[c];
+            for (int k = 0; k < nv; k++) {
+                double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], r1 = 0, r2 = 0;
+                for (int q = 0; q < 4; q++) {
+                    double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                    const double *a = fq + (((size_t)c * 4 + q) * nv + k) * 2;
+                    r1 += s * a[0]; r2 += s * a[1];
+                }
+                const double *fc = f + ((size_t)c * nv + k) * 2;
+                double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+                out[((size_t)c * nv + k) * 2] = r1 + V * itau * (fc[0] - g1);
+                out[((size_t)c * nv + k) * 2 + 1] = r2 + V * itau * (fc[1] - 0.5 * th * g1);
+            }
+        }
+        memcpy(p->W, Wsave, sizeof(double) * 4 * p->nc);
+        free(Wsave); free(fq);
+        return;
+    }
     double *Wsave = malloc(sizeof(double) * 4 * p->nc), *Fsave = malloc(sizeof(double) * p->nw);
     memcpy(Wsave, p->W, sizeof(double) * 4 * p->nc);
     memcpy(Fsave, p->F, sizeof(double) * p->nw);
@@ -609,7 +893,7 @@ void or_primal_residual(or_problem *p, const double *f, double *out)
             for (int q = 0; q < 4; q++) {
                 double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
                 if (s > 0) { r1 += s * fc[0]; r2 += s * fc[1]; }
-                else { double a1, a2; inflow_value(p, f, c, q, k, &a1, &a2); r1 += s * a1; r2 += s * a2; }
+                else { double a1, a2; inflow_value(p, f, p->F, c, q, k, &a1, &a2); r1 += s * a1; r2 += s * a2; }
             }
             double g1 = maxwell1(rho, u1, u2, th, v1, v2);
             out[((size_t)c * nv + k) * 2] = r1 + V * itau * (fc[0] - g1);
@@ -647,13 +931,48 @@ void or_complex_step(or_problem *p, const double *u, double h, int which, double
         fdz[2 * k] = g; fdz[2 * k + 1] = 0.5 * thinf * g;
         gMz[k] = 1.0 / (2 * OR_PI * thw) * cexp(-(v1 * v1 + v2 * v2) / (2 * thw));
     }
+    /* order 2: slopes of the perturbed f with the limiter factors of the
+     * real f held (the frozen-limiter linearisation) */
+    double complex *Gz = NULL;
+    if (p->order == 2) {
+        double *Gr = malloc(sizeof(double) * 4 * (size_t)nc * nv), *ps = malloc(sizeof(double) * 2 * (size_t)nc * nv);
+        so_slopes(p, p->f, Gr, ps);
+        free(Gr);
+        Gz = malloc(sizeof(double complex) * 4 * (size_t)nc * nv);
+        for (int c = 0; c < nc; c++)
+            for (int k = 0; k < nv; k++) {
+                const double complex *fc = fz + ((size_t)c * nv + k) * 2;
+                double complex g[2][2] = { { 0, 0 }, { 0, 0 } };
+                for (int q = 0; q < 4; q++) {
+                    int nb = p->nbr[4 * c + q];
+                    double complex b1 = fc[0], b2 = fc[1];
+                    if (nb >= 0) {
+                        const double complex *fj = fz + ((size_t)nb * nv + k) * 2;
+                        b1 = 0.5 * (fc[0] + fj[0]); b2 = 0.5 * (fc[1] + fj[1]);
+                    }
+                    g[0][0] += b1 * p->S[8 * c + 2 * q]; g[0][1] += b1 * p->S[8 * c + 2 * q + 1];
+                    g[1][0] += b2 * p->S[8 * c + 2 * q]; g[1][1] += b2 * p->S[8 * c + 2 * q + 1];
+                }
+                double complex *o = Gz + ((size_t)c * nv + k) * 4;
+                const double *pk = ps + ((size_t)c * nv + k) * 2;
+                o[0] = pk[0] * g[0][0] / p->vol[c]; o[1] = pk[0] * g[0][1] / p->vol[c];
+                o[2] = pk[1] * g[1][0] / p->vol[c]; o[3] = pk[1] * g[1][1] / p->vol[c];
+            }
+        free(ps);
+    }
+    /* reconstruction increment of face q of cell c, component m, upwind side */
+#define ZDELTA(c_, q_, k_, m_, up_)                                                                   \
+    (Gz == NULL || (up_) < 0 ? (double complex)0                                                     \
+     : Gz[((size_t)(up_) * nv + (k_)) * 4 + 2 * (m_)] * (p->fm[8 * (c_) + 2 * (q_)] - p->cen[2 * (up_)]) + \
+       Gz[((size_t)(up_) * nv + (k_)) * 4 + 2 * (m_) + 1] * (p->fm[8 * (c_) + 2 * (q_) + 1] - p->cen[2 * (up_) + 1]))
     double complex *Dz = malloc(sizeof(double complex) * nw), *Fz = malloc(sizeof(double complex) * nw);
     for (int l = 0; l < nw; l++) {
-        const double complex *fc = fz + (size_t)p->wall_cell[l] * nv * 2;
+        const int cw = p->wall_cell[l], qw = p->wall_face[l];
+        const double complex *fc = fz + (size_t)cw * nv * 2;
         double complex d = 0, F = 0;
         for (int k = 0; k < nv; k++) {
             double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
-            if (vn > 0) F += p->w[k] * vn * fc[2 * k];
+            if (vn > 0) F += p->w[k] * vn * (fc[2 * k] + ZDELTA(cw, qw, k, 0, cw));
             else d -= p->w[k] * vn * gMz[k];
         }
         Dz[l] = d; Fz[l] = F;
@@ -661,11 +980,12 @@ void or_complex_step(or_problem *p, const double *u, double h, int which, double
     /* J */
     double complex J = 0;
     for (int l = 0; l < nw; l++) {
-        const double complex *fc = fz + (size_t)p->wall_cell[l] * nv * 2;
+        const int cw = p->wall_cell[l], qw = p->wall_face[l];
+        const double complex *fc = fz + (size_t)cw * nv * 2;
         for (int k = 0; k < nv; k++) {
             double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
             double vn = v1 * p->wn[2 * l] + v2 * p->wn[2 * l + 1];
-            double complex f1 = vn > 0 ? fc[2 * k] : Fz[l] * gMz[k] / Dz[l];
+            double complex f1 = vn > 0 ? fc[2 * k] + ZDELTA(cw, qw, k, 0, cw) : Fz[l] * gMz[k] / Dz[l];
             double mj = p->objective == 0 ? v1 : 0.5 * (v1 * v1 + v2 * v2);
             J += p->wA[l] * p->w[k] * mj * vn * f1;
         }
@@ -692,10 +1012,15 @@ void or_complex_step(or_problem *p, const double *u, double h, int which, double
                 for (int q = 0; q < 4; q++) {
                     double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
                     double complex a1, a2;
-                    if (s > 0) { a1 = fc[2 * k]; a2 = fc[2 * k + 1]; }
-                    else {
+                    if (s > 0) {
+                        a1 = fc[2 * k] + ZDELTA(c, q, k, 0, c);
+                        a2 = fc[2 * k + 1] + ZDELTA(c, q, k, 1, c);
+                    } else {
                         int nb = p->nbr[4 * c + q];
-                        if (nb >= 0) { a1 = fz[((size_t)nb * nv + k) * 2]; a2 = fz[((size_t)nb * nv + k) * 2 + 1]; }
+                        if (nb >= 0) {
+                            a1 = fz[((size_t)nb * nv + k) * 2] + ZDELTA(c, q, k, 0, nb);
+                            a2 = fz[((size_t)nb * nv + k) * 2 + 1] + ZDELTA(c, q, k, 1, nb);
+                        }
                         else if (nb == -1) { a1 = fdz[2 * k]; a2 = fdz[2 * k + 1]; }
                         else { int l = -2 - nb; a1 = Fz[l] * gMz[k] / Dz[l]; a2 = 0.5 * thw * a1; }
                     }
@@ -710,7 +1035,8 @@ void or_complex_step(or_problem *p, const double *u, double h, int which, double
             }
         }
     }
-    free(fz); free(fdz); free(gMz); free(Dz); free(Fz);
+#undef ZDELTA
+    free(fz); free(fdz); free(gMz); free(Dz); free(Fz); free(Gz);
 }
 
 /* ------------------------------------------------------------------ */
@@ -794,9 +1120,64 @@ static void outflow_adjoint(const or_problem *p, const double *phi, const double
     else { int l = -2 - nb; *o1 = Phi[l] - (with_source ? p->mJ[k] : 0.0); *o2 = 0; }
 }
 
+/* Reconstruction term of the order-2 adjoint: E = (d r2 / d f)^T a, where
+ * r2 collects psi_u grad f_u . (m_q - x_u) over the faces q an upwind cell u
+ * feeds (psi frozen) and a_q = s (phi_u - phi_down) is the weight of face
+ * q's value in the Lagrangian J + sum_k w phi . R (phi_down of the
+ * first-order adjoint: neighbour, 0 at the far field, (Phi_l - m_J, 0) at the
+ * wall).  Written as the transpose of the Green-Gauss sum: B_u = psi_u sum_q
+ * a_q (m_q - x_u) is scattered back to f_u and to its interior neighbours
+ * with the weights fbar_q = (f_u + f_nb)/2 or f_u gives them.  Phi holds the
+ * wall multipliers of phi; the objective's m_J enters through p->mJ. */
+static void so_adjoint_term(const or_problem *p, const double *phi, const double *Phi, double *E)
+{
+    const int nv = p->nv;
+    memset(E, 0, sizeof(double) * 2 * (size_t)p->nc * nv);
+    for (int u = 0; u < p->nc; u++) {
+        const double V = p->vol[u];
+        for (int k = 0; k < nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+            const double *pu = phi + ((size_t)u * nv + k) * 2;
+            double B[2][2] = { { 0, 0 }, { 0, 0 } };
+            for (int q = 0; q < 4; q++) {
+                double s = v1 * p->S[8 * u + 2 * q] + v2 * p->S[8 * u + 2 * q + 1];
+                if (!(s > 0)) continue;
+                double d1, d2;
+                outflow_adjoint(p, phi, Phi, u, q, k, 1, &d1, &d2);
+                double rx = p->fm[8 * u + 2 * q] - p->cen[2 * u], ry = p->fm[8 * u + 2 * q + 1] - p->cen[2 * u + 1];
+                double a1 = s * (pu[0] - d1), a2 = s * (pu[1] - d2);
+                B[0][0] += a1 * rx; B[0][1] += a1 * ry;
+                B[1][0] += a2 * rx; B[1][1] += a2 * ry;
+            }
+            const double *ps = p->psi + ((size_t)u * nv + k) * 2;
+            for (int m = 0; m < 2; m++) { B[m][0] *= ps[m]; B[m][1] *= ps[m]; }
+            for (int q = 0; q < 4; q++) {
+                int nb = p->nbr[4 * u + q];
+                double Sx = p->S[8 * u + 2 * q], Sy = p->S[8 * u + 2 * q + 1];
+                for (int m = 0; m < 2; m++) {
+                    double t = (B[m][0] * Sx + B[m][1] * Sy) / V;
+                    if (nb >= 0) {
+                        E[((size_t)u * nv + k) * 2 + m] += 0.5 * t;
+                        E[((size_t)nb * nv + k) * 2 + m] += 0.5 * t;
+                    } else {
+                        E[((size_t)u * nv + k) * 2 + m] += t;
+                    }
+                }
+            }
+        }
+    }
+}
+
 void or_adjoint_init(or_problem *p)
 {
     memset(p->phi, 0, sizeof(double) * (size_t)p->nc * p->nv * 2);
+    if (p->order == 2) {
+        /* limiter factors of the converged f, frozen for the adjoint */
+        double *G = malloc(sizeof(double) * 4 * (size_t)p->nc * p->nv);
+        so_slopes(p, p->f, G, p->psi);
+        free(G);
+        p->acorr_ok = 0;
+    }
 }
 
 /* Jacobi sweeps of eq. (numerad_gov) with the converged f frozen.  Returns
@@ -809,6 +1190,12 @@ double or_adjoint_iterate(or_problem *p, int niter)
     double r = 0;
     for (int it = 0; it < niter; it++) {
         adjoint_moments(p, p->phi, What, rtau, Phi);
+        const int so = p->order == 2;
+        if (so && (!p->acorr_ok || p->asince == p->kcorr)) {
+            so_adjoint_term(p, p->phi, Phi, p->acorr);
+            p->acorr_ok = 1;
+            p->asince = 0;
+        }
 #pragma omp parallel for schedule(static) num_threads(p->nthreads)
         for (int c = 0; c < p->nc; c++) {
             double V = p->vol[c];
@@ -823,6 +1210,10 @@ double or_adjoint_iterate(or_problem *p, int niter)
                         outflow_adjoint(p, p->phi, Phi, c, q, k, 1, &b1, &b2);
                         a1 += s * b1; a2 += s * b2; out += s;
                     }
+                }
+                if (so) {
+                    a1 -= p->acorr[((size_t)c * nv + k) * 2];
+                    a2 -= p->acorr[((size_t)c * nv + k) * 2 + 1];
                 }
                 double s1, s2, itau;
                 adjoint_source(p, c, k, What, rtau, &s1, &s2, &itau);
@@ -842,6 +1233,7 @@ double or_adjoint_iterate(or_problem *p, int niter)
         for (int c = 0; c < p->nc; c++) { num += p->cellred[2 * c]; den += p->cellred[2 * c + 1]; }
         r = den > 0 ? sqrt(num / den) : 0.0;
         double *t = p->phi; p->phi = p->phin; p->phin = t;
+        if (so) p->asince++;
     }
     free(What); free(rtau); free(Phi);
     return r;
@@ -858,6 +1250,11 @@ void or_adjoint_operator(or_problem *p, const double *phi, int with_source, doub
     double *mJsave = NULL;
     if (!with_source) { mJsave = p->mJ; p->mJ = calloc(nv, sizeof(double)); }
     adjoint_moments(p, phi, What, rtau, Phi);
+    double *E = NULL;
+    if (p->order == 2) {
+        E = malloc(sizeof(double) * 2 * (size_t)p->nc * nv);
+        so_adjoint_term(p, phi, Phi, E);
+    }
     for (int c = 0; c < p->nc; c++) {
         double V = p->vol[c];
         for (int k = 0; k < nv; k++) {
@@ -874,10 +1271,12 @@ void or_adjoint_operator(or_problem *p, const double *phi, int with_source, doub
             }
             double s1, s2, itau;
             adjoint_source(p, c, k, What, rtau, &s1, &s2, &itau);
+            if (E) { r1 += E[((size_t)c * nv + k) * 2]; r2 += E[((size_t)c * nv + k) * 2 + 1]; }
             out[((size_t)c * nv + k) * 2] = r1 + V * (pi[0] * itau - s1);
             out[((size_t)c * nv + k) * 2 + 1] = r2 + V * (pi[1] * itau - s2);
         }
     }
+    free(E);
     if (!with_source) { free(p->mJ); p->mJ = mJsave; }
     free(What); free(rtau); free(Phi);
 }
@@ -1020,7 +1419,7 @@ static void gauss_grad(const or_problem *p, int c, int k, double g[2][2])
         double Sx = p->S[8 * c + 2 * q], Sy = p->S[8 * c + 2 * q + 1];
         double s = v1 * Sx + v2 * Sy, a1, a2;
         if (s > 0) { a1 = fc[0]; a2 = fc[1]; }
-        else inflow_value(p, p->f, c, q, k, &a1, &a2);
+        else inflow_value(p, p->f, p->F, c, q, k, &a1, &a2);
         g[0][0] += a1 * Sx; g[0][1] += a1 * Sy;
         g[1][0] += a2 * Sx; g[1][1] += a2 * Sy;
     }

@@ -65,6 +65,7 @@ enum { DVM_FP64 = 0, DVM_MIXED = 1 };   /* MIXED: f, phi and per-pair arithmetic
 enum { DVM_OBJ_DRAG = 0, DVM_OBJ_HEAT = 1 };
 enum { DVM_VG_MIDPOINT = 0, DVM_VG_NEWTON_COTES = 1, DVM_VG_SINH = 2 };
 enum { DVM_STATE_F = 0, DVM_STATE_PHI = 1 };
+enum { DVM_LIMITER_NONE = 0, DVM_LIMITER_VENKAT = 1 };   /* second-order slope limiter */
 #define DVM_MAX_PARAMS 64
 
 typedef struct {
@@ -114,6 +115,27 @@ void dvm_vgrid_destroy(dvm_vgrid *g);
  * = 0 leaves the adjoint buffers out of the workspace. */
 int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flow, int precision,
                       int want_adjoint, dvm_solver **out);
+/* Spatial scheme of the solve, set before dvm_solver_bind (the workspace
+ * grows with order 2; DVM_ESTATE once bound).  Sec. 3.1 states second-order
+ * accuracy in physical space for eqs. (numerpr_gov) and (numerad_gov) and
+ * defers the scheme; order 1 (the default) takes face values from the
+ * upwind cell.  order 2: cell values at the area centroids, Green-Gauss
+ * slopes (face mean of the two cell values; the cell value on boundary
+ * faces), limiter DVM_LIMITER_VENKAT (Venkatakrishnan, per cell, velocity
+ * and component, smoothing e = 1e-3 |f_c|) or DVM_LIMITER_NONE, face values
+ * reconstructed on the upwind side; far-field and wall inflow are not reconstructed and the wall flux
+ * F_l sums the reconstructed outgoing values; the drag uses the same wall
+ * values.  It is iterated by defect correction: every correction_interval
+ * (K >= 1) sweeps the difference between the second- and first-order face
+ * fluxes is evaluated from the current state and held, and the sweeps
+ * between are the first-order Jacobi sweep with that difference moved to
+ * the right-hand side; a fixed point solves the second-order balance (K = 1
+ * is unstable where transport dominates; K >= 3 is advised).  The adjoint
+ * freezes the limiter factors of the converged f (at dvm_adjoint_init) and
+ * solves the transpose of that linearisation the same way.  Loading a state
+ * re-evaluates the correction at the next sweep.  Batches, the wall, shape
+ * and mesh sensitivities are first-order only (DVM_EINVAL). */
+int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_interval);
 /* Exact device bytes the solver needs (used for admission by footprint). */
 size_t dvm_solver_workspace_bytes(const dvm_solver *s);
 /* Bind a caller-owned device buffer (>= workspace bytes, 256-byte aligned)

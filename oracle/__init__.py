@@ -139,7 +139,7 @@ class Problem:
 
     def set_scheme(self, order: int = 2, limiter: bool = True, correction_every: int = 5):
         """Spatial order 1 (first-order upwind) or 2 (Green-Gauss slopes with an
-        optional Barth-Jespersen limiter, iterated by defect correction with the
+        optional Venkatakrishnan limiter, iterated by defect correction with the
         correction re-evaluated every `correction_every` sweeps)."""
         if lib().or_set_scheme(self._h, int(order), 1 if limiter else 0, int(correction_every)) != 0:
             raise ValueError("oracle: invalid scheme")

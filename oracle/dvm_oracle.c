@@ -63,8 +63,8 @@
  * coordinate by complex step) is pinned by translation invariance and by
  * central differences of the re-converged drag under shape change.
  * Second-order scheme (tests/test_oracle_second_order.py): exact slopes and
- * face values for linear fields on equal parallelograms; Barth-Jespersen
- * bounds; the defect-correction fixed point solves R2 = 0 independently of
+ * face values for linear fields on equal parallelograms; the limiter's
+ * overshoot bound and smoothness; the defect-correction fixed point solves R2 = 0 independently of
  * the correction interval; drag converges at second order under O-grid
  * refinement (first order for the first-order scheme); dot-product identity
  * of the frozen-limiter adjoint against the complex twin of R2 and J;
@@ -81,6 +81,7 @@
 #endif
 
 #define OR_PI 3.14159265358979323846
+#define OR_VK_KAPPA 1e-3   /* Venkatakrishnan limiter: e = OR_VK_KAPPA |f_c| */
 
 /* face order per cell: 0 = j-, 1 = i+, 2 = j+, 3 = i- ; neighbour code:
  * >= 0 interior cell, -1 far field, -2 - l wall element l */
@@ -538,10 +539,13 @@ static void inflow_value(const or_problem *p, const double *f, const double *Fw,
  *   - a cell value sits at the cell's area centroid x_c; the gradient is
  *     Green-Gauss, grad f_c = (1/V_c) sum_q fbar_q S_cq, with fbar the mean
  *     of the two cell values on an interior face and f_c on a boundary face;
- *   - Barth-Jespersen limiter, per cell, velocity and component: psi is the
- *     largest factor in [0, 1] for which f_c + psi grad f_c . (m_q - x_c)
- *     stays between the minimum and maximum of f over the cell and its
- *     interior neighbours at every face midpoint m_q;
+ *   - Venkatakrishnan limiter, per cell, velocity and component (so_limit),
+ *     with its smoothing e = 1e-3 |f_c| relative to the cell value, so that
+ *     it acts alike on the Maxwellian's core and on its tail values many
+ *     decades smaller; smooth, it lets the defect-correction iteration
+ *     converge to rounding and keeps the frozen factors of the adjoint
+ *     well-conditioned (Barth-Jespersen, the non-smooth alternative, stalls
+ *     the iteration and makes psi jump where f is flat);
  *   - the value of a face is reconstructed on its upwind side,
  *     f_u + psi_u grad f_u . (m_q - x_u); inflow from the far field stays
  *     f_d, inflow from the wall stays F_l gbar, with F_l summed over the
@@ -580,7 +584,14 @@ static void so_grad(const or_problem *p, const double *f, int c, int k, double g
     for (int m = 0; m < 2; m++) { g[m][0] /= p->vol[c]; g[m][1] /= p->vol[c]; }
 }
 
-/* Barth-Jespersen factor of each component for the gradient g */
+/* Venkatakrishnan limiter factor of each component for the gradient g: per
+ * face q, with d the unlimited increment g . (m_q - x_c), D = hi - f_c for
+ * d > 0 and lo - f_c otherwise (hi, lo: max and min over the cell and its
+ * interior neighbours) and e = kappa |f_c|,
+ *   phi_q = (D^2 + e^2 + 2 d D) / (D^2 + 2 d^2 + d D + e^2),
+ * psi = min(1, min_q phi_q).  A smooth function of the cell values: flat
+ * regions (|d|, |D| << e) give psi -> 1 and a face value overshoots
+ * [lo, hi] by at most e / (2 sqrt 2). */
 static void so_limit(const or_problem *p, const double *f, int c, int k, const double g[2][2], double psi[2])
 {
     const int nv = p->nv;
@@ -596,12 +607,13 @@ static void so_limit(const or_problem *p, const double *f, int c, int k, const d
             if (v < lo) lo = v;
             if (v > hi) hi = v;
         }
+        const double e2 = (OR_VK_KAPPA * fc[m]) * (OR_VK_KAPPA * fc[m]);
         for (int q = 0; q < 4; q++) {
             double rx = p->fm[8 * c + 2 * q] - p->cen[2 * c], ry = p->fm[8 * c + 2 * q + 1] - p->cen[2 * c + 1];
             double d = g[m][0] * rx + g[m][1] * ry;
-            double r = 1.0;
-            if (d > 0) r = (hi - fc[m]) / d;
-            else if (d < 0) r = (lo - fc[m]) / d;
+            double D = d > 0 ? hi - fc[m] : lo - fc[m];
+            double den = D * D + 2.0 * d * d + d * D + e2;
+            double r = den > 0 ? (D * D + e2 + 2.0 * d * D) / den : 1.0;
             if (r < psi[m]) psi[m] = r;
         }
     }
@@ -685,7 +697,7 @@ static void so_alloc(or_problem *p)
     if (!p->acorr) p->acorr = calloc(n, sizeof(double));
 }
 
-/* order 1 or 2; limiter 0 (none) or 1 (Barth-Jespersen); K >= 1 sweeps
+/* order 1 or 2; limiter 0 (none) or 1 (Venkatakrishnan); K >= 1 sweeps
  * between evaluations of the held correction.  Returns 0, or -1 for an
  * invalid setting. */
 int or_set_scheme(or_problem *p, int order, int limiter, int kcorr)

@@ -64,6 +64,19 @@ __device__ __forceinline__ double uni(double x)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Workgroups are handed to the 8 XCDs round-robin; give each XCD a
+// contiguous stretch of the sweep order (n items: cells or patches) so that
+// the neighbour rows a workgroup reads were fetched moments before by a
+// workgroup of the same XCD and are still in its L2.  Returns -1 for the
+// padding workgroups of the last stretch.
+__device__ __forceinline__ int xcd_item(int n, int b)
+{
+    const int per = (n + 7) >> 3;
+    const int idx = (b & 7) * per + (b >> 3);
+    return idx < n ? idx : -1;
+}
+static inline int xcd_grid(int n) { return ((n + 7) >> 3) << 3; }
+
 // Instantiate for the storage type of a solve: float (mixed) or double (FP64).
 #define DVM_DISPATCH(mixed, ...) \
     do {                          \

@@ -53,6 +53,8 @@ struct dvm_mesh {
     std::vector<int32_t> wall_cell;  // [nw]
     std::vector<double> S;           // [nc][4][2]
     std::vector<double> vol;         // [nc]
+    std::vector<double> cen;         // [nc][2] area centroids
+    std::vector<double> fm;          // [nc][4][2] face midpoints
     std::vector<double> wA, wn, wx, wa, wb;
     std::vector<int32_t> perm;       // [nc] device (storage) number of each cell
     std::vector<int32_t> pstart;     // [np + 1] first device cell of each patch
@@ -107,6 +109,8 @@ int build_mesh(dvm_mesh &m)
     m.nbr.assign((size_t)4 * m.nc, 0);
     m.S.assign((size_t)8 * m.nc, 0.0);
     m.vol.assign(m.nc, 0.0);
+    m.cen.assign((size_t)2 * m.nc, 0.0);
+    m.fm.assign((size_t)8 * m.nc, 0.0);
     for (int j = 0; j < nj; j++) {
         for (int i = 0; i < ni; i++) {
             const int c = cell(i, j);
@@ -117,10 +121,21 @@ int build_mesh(dvm_mesh &m)
             const double area = 0.5 * (d1x * d2y - d1y * d2x);
             if (!(area > 0.0)) return fail(DVM_EINVAL, "cell (%d,%d) has non-positive area %g", i, j, area);
             m.vol[c] = area;
+            // centroid: the two triangles (q0 q1 q2), (q0 q2 q3), relative to q0
+            {
+                const double r1x = q[1][0] - q[0][0], r1y = q[1][1] - q[0][1];
+                const double r2x = q[2][0] - q[0][0], r2y = q[2][1] - q[0][1];
+                const double r3x = q[3][0] - q[0][0], r3y = q[3][1] - q[0][1];
+                const double a1 = r1x * r2y - r1y * r2x, a2 = r2x * r3y - r2y * r3x;
+                m.cen[2 * c] = q[0][0] + (a1 * (r1x + r2x) + a2 * (r2x + r3x)) / (3.0 * (a1 + a2));
+                m.cen[2 * c + 1] = q[0][1] + (a1 * (r1y + r2y) + a2 * (r2y + r3y)) / (3.0 * (a1 + a2));
+            }
             for (int e = 0; e < 4; e++) {
                 const P2 &s = q[e], &t = q[(e + 1) & 3];
                 m.S[8 * c + 2 * e] = t[1] - s[1];       // (dy, -dx): outward for a CCW walk
                 m.S[8 * c + 2 * e + 1] = s[0] - t[0];
+                m.fm[8 * c + 2 * e] = 0.5 * (s[0] + t[0]);
+                m.fm[8 * c + 2 * e + 1] = 0.5 * (s[1] + t[1]);
             }
             int32_t *nb = &m.nbr[4 * c];
             // face 0: j-   (wall, wake cut or interior)
@@ -241,16 +256,19 @@ struct dvm_solver {
     // device cell d is mesh cell cell_of[d])
     std::vector<int32_t> nbr, wall_cell, perm, cell_of, pstart;
     std::vector<double> S, vol, wA, wn, wa, wb, D;
+    std::vector<double> rf, rn;   // [nc][4][2] face midpoint - own / neighbour centroid (order 2)
     std::vector<double> x1, w1, x2, w2;
     std::vector<double> fd;   // [nv][2]
     std::vector<double> gM;   // [nv]
     std::vector<double> gw2;  // [nv][2]
     double inv_tau_inf, u_inf, theta_w, cd_scale;
+    // spatial scheme: order 1, or 2 with limiter and K sweeps between corrections
+    int order = 1, limiter = DVM_LIMITER_VENKAT, kcorr = 5;
     // workspace
     struct {
         size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
-        size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, msens, dJdx, out,
-            total;
+        size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, msens, dJdx, out;
+        size_t rf, rn, G, corr, psi, dF, total;
     } off;
     char *base = nullptr;
     hipStream_t stream = nullptr;
@@ -260,6 +278,8 @@ struct dvm_solver {
     int fpar = 0, ppar = 0, frozen_fpar = 0;
     int iters[2] = {0, 0};
     int in_batch = 0;
+    // order 2: is a held correction valid, and sweeps since it was evaluated
+    int corr_ok[2] = {0, 0}, since[2] = {0, 0};
 };
 
 namespace {
@@ -319,6 +339,16 @@ void layout(dvm_solver &s)
     }
     o.Jl = take(nw * sizeof(double));
     o.out = take(16 * sizeof(double));
+    if (s.order == 2) {
+        o.rf = take(8 * nc * sizeof(double));
+        o.rn = take(8 * nc * sizeof(double));
+        o.G = take(4 * nc * nv * e);
+        o.corr = take(2 * nc * nv * e);
+        o.dF = take(nw * sizeof(double));
+        o.psi = s.want_adjoint ? take(2 * nc * nv * e) : (size_t)-1;
+    } else {
+        o.rf = o.rn = o.G = o.corr = o.dF = o.psi = (size_t)-1;
+    }
     o.total = cur;
 }
 
@@ -342,6 +372,8 @@ void fill_dev(dvm_solver &s)
     d.topo = s.topo;
     d.objective = s.objective;
     d.mixed = s.mixed;
+    d.order = s.order;
+    d.limiter = s.limiter;
     d.nbr = at<int32_t>(s, s.off.nbr);
     d.patch = at<int32_t>(s, s.off.patch);
     d.cell_of = at<int32_t>(s, s.off.cell_of);
@@ -383,6 +415,12 @@ void fill_dev(dvm_solver &s)
     d.msens = at<double>(s, s.off.msens);
     d.dJdx = at<double>(s, s.off.dJdx);
     d.out = at<double>(s, s.off.out);
+    d.rf = at<double>(s, s.off.rf);
+    d.rn = at<double>(s, s.off.rn);
+    d.G = at<void>(s, s.off.G);
+    d.corr = at<void>(s, s.off.corr);
+    d.psi = at<void>(s, s.off.psi);
+    d.dF = at<double>(s, s.off.dF);
 }
 
 int upload(dvm_solver &s, size_t off, const void *src, size_t bytes)
@@ -432,9 +470,20 @@ int check_bound(const dvm_solver *s)
     return DVM_OK;
 }
 
+// Order 2 (defect correction): before a sweep, re-evaluate the held
+// correction from the current state when there is none or K sweeps have
+// used it.
 int sweeps(dvm_solver &s, int adjoint, int n)
 {
     for (int i = 0; i < n; i++) {
+        if (s.order == 2 && (!s.corr_ok[adjoint] || s.since[adjoint] == s.kcorr)) {
+            if (adjoint)
+                HIP_OK(dvm::launch_so_adjoint_term(s.dev, s.ppar, s.stream));
+            else
+                HIP_OK(dvm::launch_so_correction(s.dev, s.fpar, s.stream));
+            s.corr_ok[adjoint] = 1;
+            s.since[adjoint] = 0;
+        }
         if (adjoint) {
             HIP_OK(dvm::launch_adjoint_sweep(s.dev, s.ppar, s.stream));
             s.ppar ^= 1;
@@ -442,6 +491,7 @@ int sweeps(dvm_solver &s, int adjoint, int n)
             HIP_OK(dvm::launch_primal_sweep(s.dev, s.fpar, s.stream));
             s.fpar ^= 1;
         }
+        s.since[adjoint]++;
     }
     s.iters[adjoint] += n;
     return DVM_OK;
@@ -684,6 +734,18 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
             for (int e = 0; e < 8; e++) s->S[8 * dc + e] = m->S[8 * c + e];
             s->vol[dc] = m->vol[c];
         }
+        s->rf.assign((size_t)8 * m->nc, 0.0);
+        s->rn.assign((size_t)8 * m->nc, 0.0);
+        for (int c = 0; c < m->nc; c++) {
+            const int32_t dc = m->perm[c];
+            for (int q = 0; q < 4; q++)
+                for (int x = 0; x < 2; x++) {
+                    const double mid = m->fm[8 * c + 2 * q + x];
+                    const int32_t n = m->nbr[4 * c + q];
+                    s->rf[8 * dc + 2 * q + x] = mid - m->cen[2 * c + x];
+                    if (n >= 0) s->rn[8 * dc + 2 * q + x] = mid - m->cen[2 * n + x];
+                }
+        }
         s->wall_cell.resize(m->nw);
         for (int l = 0; l < m->nw; l++) s->wall_cell[l] = m->perm[m->wall_cell[l]];
         s->wA = m->wA;
@@ -708,6 +770,20 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
 
 size_t dvm_solver_workspace_bytes(const dvm_solver *s) { return s ? s->off.total : 0; }
 
+int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_interval)
+{
+    if (!s) return fail(DVM_EINVAL, "null solver");
+    if (s->base) return fail(DVM_ESTATE, "the scheme is set before dvm_solver_bind");
+    if (order != 1 && order != 2) return fail(DVM_EINVAL, "order must be 1 or 2 (got %d)", order);
+    if (limiter != DVM_LIMITER_NONE && limiter != DVM_LIMITER_VENKAT) return fail(DVM_EINVAL, "unknown limiter %d", limiter);
+    if (correction_interval < 1) return fail(DVM_EINVAL, "correction interval must be >= 1");
+    s->order = order;
+    s->limiter = limiter;
+    s->kcorr = correction_interval;
+    layout(*s);
+    return DVM_OK;
+}
+
 int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
 {
     if (!s || !dev_ptr) return fail(DVM_EINVAL, "null argument");
@@ -725,6 +801,7 @@ int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream
     s->phase = -1;
     s->fpar = s->ppar = s->frozen_fpar = 0;
     s->iters[0] = s->iters[1] = 0;
+    s->corr_ok[0] = s->corr_ok[1] = 0;
     fill_dev(*s);
     const auto &o = s->off;
     int e = 0;
@@ -743,6 +820,10 @@ int dvm_solver_bind(dvm_solver *s, void *dev_ptr, size_t bytes, void *hip_stream
     e = e ? e : upload(*s, o.vy, s->x2.data(), s->x2.size() * sizeof(double));
     e = e ? e : upload(*s, o.wx, s->w1.data(), s->w1.size() * sizeof(double));
     e = e ? e : upload(*s, o.wy, s->w2.data(), s->w2.size() * sizeof(double));
+    if (s->order == 2) {
+        e = e ? e : upload(*s, o.rf, s->rf.data(), s->rf.size() * sizeof(double));
+        e = e ? e : upload(*s, o.rn, s->rn.data(), s->rn.size() * sizeof(double));
+    }
     std::vector<float> fdf, gMf, gw2f;
     if (s->mixed) {
         fdf = convert<float>(s->fd);
@@ -778,6 +859,7 @@ int dvm_primal_init(dvm_solver *s)
     s->fpar = 0;
     s->phase = 0;
     s->iters[0] = s->iters[1] = 0;
+    s->corr_ok[0] = 0;
     return DVM_OK;
 }
 
@@ -833,9 +915,11 @@ int dvm_adjoint_init(dvm_solver *s)
     if (s->phase == 0) s->frozen_fpar = s->fpar;
     fill_dev(*s);
     HIP_OK(dvm::launch_adjoint_init(s->dev, s->frozen_fpar, s->stream));
+    if (s->order == 2) HIP_OK(dvm::launch_so_freeze(s->dev, s->frozen_fpar, s->stream));
     s->ppar = 0;
     s->phase = 1;
     s->iters[1] = 0;
+    s->corr_ok[1] = 0;
     return DVM_OK;
 }
 
@@ -860,10 +944,17 @@ static int run_sens(dvm_solver *s, int n_params)
     return DVM_OK;
 }
 
+static int first_order_only(const dvm_solver *s, const char *what)
+{
+    if (s->order != 1) return fail(DVM_EINVAL, "%s is implemented for the first-order scheme", what);
+    return DVM_OK;
+}
+
 int dvm_wall_sensitivity(dvm_solver *s, double *S_A, double *S_x, double *S_n, double *dJ_dnodes)
 {
     if (int e = check_bound(s)) return e;
     if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+    if (int e = first_order_only(s, "the wall sensitivity")) return e;
     if (int e = run_sens(s, 0)) return e;
     std::vector<double> sens(5 * (size_t)s->nw), dn(2 * (size_t)s->nw);
     if (int e = read_back(*s, s->dev.sens, sens.data(), sens.size())) return e;
@@ -887,6 +978,7 @@ int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, d
 {
     if (int e = check_bound(s)) return e;
     if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+    if (int e = first_order_only(s, "the wall sensitivity")) return e;
     if (n_params < 0 || n_params > dvm::kMaxParams) return fail(DVM_EINVAL, "n_params must be in [0, %d]", dvm::kMaxParams);
     if (n_params > 0 && (!wall_jac || !dJ_dalpha)) return fail(DVM_EINVAL, "null argument");
     std::vector<double> jac((size_t)2 * s->nw * dvm::kMaxParams, 0.0);
@@ -905,6 +997,7 @@ int dvm_mesh_sensitivity(dvm_solver *s, double *dJ_dx)
 {
     if (int e = check_bound(s)) return e;
     if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+    if (int e = first_order_only(s, "the mesh sensitivity")) return e;
     if (!dJ_dx) return fail(DVM_EINVAL, "null output");
     HIP_OK(dvm::launch_mesh_sens(s->dev, s->frozen_fpar, s->ppar, s->stream));
     return read_back(*s, s->dev.dJdx, dJ_dx, 2 * (size_t)(s->ni + 1) * (s->nj + 1));
@@ -967,12 +1060,14 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
             HIP_OK(dvm::launch_moments(s->dev, 0, s->stream));
             s->phase = 0;
             s->iters[0] = s->iters[1] = 0;
+            s->corr_ok[0] = 0;
         } else {
             rows_to_dev(*s, src + all, tmp.data() + all, awb);
             HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], tmp.data(), all, hipMemcpyHostToDevice, s->stream));
             HIP_OK(hipMemcpyAsync(s->dev.aW[s->ppar], tmp.data() + all, awb * s->nc, hipMemcpyHostToDevice, s->stream));
             HIP_OK(hipMemcpyAsync(s->dev.Phi[s->ppar], src + all + awb * s->nc, (size_t)s->nw * sizeof(double),
                                   hipMemcpyHostToDevice, s->stream));
+            s->corr_ok[1] = 0;
         }
         HIP_OK(hipStreamSynchronize(s->stream));   // tmp must outlive the copies
     } catch (const std::bad_alloc &) {
@@ -1041,6 +1136,7 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         for (int j = 0; j < i; j++)
             if (solvers[j] == s) return fail(DVM_EINVAL, "solver listed twice");
         if (s->phase < 0) return fail(DVM_ESTATE, "member %d has no primal or adjoint phase", i);
+        if (s->order != 1) return fail(DVM_EINVAL, "member %d: batches run the first-order scheme", i);
         if (mixed < 0) mixed = s->mixed;
         if (mixed != s->mixed) return fail(DVM_EINVAL, "batch members must share one precision");
     }

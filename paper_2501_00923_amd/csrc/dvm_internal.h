@@ -31,6 +31,8 @@ struct DevSolve {
     int topo;
     int objective;
     int mixed;
+    int order;               // spatial order of the scheme: 1, or 2 (reconstructed face values)
+    int limiter;             // order 2: 0 none, 1 Venkatakrishnan
     // mesh
     const int32_t *nbr;      // [nc][4] (device cell numbering)
     const int32_t *patch;    // [np + 1] first cell of each patch; patch p = cells [patch[p], patch[p+1])
@@ -70,6 +72,13 @@ struct DevSolve {
     double *msens;           // [nc][4][2] per mesh cell: dL/d(corner coordinates)
     double *dJdx;            // [(nj+1)(ni+1)][2] dL/d(node coordinates), mesh node numbering
     double *out;             // [16] small scalar outputs
+    // second-order scheme (order 2 only; null otherwise)
+    const double *rf;        // [nc][4][2] face midpoint minus the cell's centroid
+    const double *rn;        // [nc][4][2] face midpoint minus the neighbour's centroid (interior faces)
+    void *G;                 // [nc][nv][4] limited slopes (f1x, f1y, f2x, f2y); adjoint: B (storage type)
+    void *corr;              // [nc][nv][2] held flux correction c; adjoint: held term E (storage type)
+    void *psi;               // [nc][nv][2] limiter factors of the frozen f (storage type)
+    double *dF;              // [nw] held wall-flux correction
 };
 
 // launches (all on `st`); par = index of the current f / phi buffer
@@ -82,6 +91,14 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st);
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
 hipError_t launch_mesh_sens(const DevSolve &d, int fpar, int ppar, hipStream_t st);
+
+// second-order scheme: the held primal correction c, dF from f[par]; the
+// limiter factors psi of f[fpar] for the adjoint; the held adjoint term E
+// from phi[par]; the drag with reconstructed wall values (per element)
+hipError_t launch_so_correction(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_so_freeze(const DevSolve &d, int fpar, hipStream_t st);
+hipError_t launch_so_adjoint_term(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_so_objective_elem(const DevSolve &d, int par, hipStream_t st);
 
 // batched: table of DevSolve on the device, per-block (solve, patch) map,
 // per-solve buffer parity at batch creation; step = sweeps done since batch

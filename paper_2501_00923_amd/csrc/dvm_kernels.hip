@@ -28,19 +28,6 @@
 
 namespace dvm {
 
-// Workgroups are handed to the 8 XCDs round-robin; give each XCD a
-// contiguous stretch of the sweep order (n items: cells or patches) so that
-// the neighbour rows a workgroup reads were fetched moments before by a
-// workgroup of the same XCD and are still in its L2.  Returns -1 for the
-// padding workgroups of the last stretch.
-__device__ __forceinline__ int xcd_item(int n, int b)
-{
-    const int per = (n + 7) >> 3;
-    const int idx = (b & 7) * per + (b >> 3);
-    return idx < n ? idx : -1;
-}
-static inline int xcd_grid(int n) { return ((n + 7) >> 3) << 3; }
-
 // In FP32 a lane can take two adjacent velocities of one velocity-grid row
 // (n1 even): the pair's (f1, f2, f1', f2') is one 16-byte load or store, as
 // one velocity is in FP64.  Measured on the 256x128 C-grid with 2304
@@ -112,8 +99,10 @@ __device__ __forceinline__ void patch_tables(const DevSolve &d, PatchLds<T, XCH>
 // ---------------------------------------------------------------------------
 // primal sweep of one patch: eq. (numerpr_gov), first-order upwind, Jacobi
 // point-implicit: f^{n+1} = (sum_in |v.S| f_up + V g/tau) / (sum_out v.S + V/tau)
+// SO (second-order scheme, defect correction): the held correction c is
+// subtracted from the numerator and the wall flux is F + dF.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool SO>
 __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
 {
     using T2 = typename Vec2<T>::type;
@@ -125,6 +114,7 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
     const int nv = d.nv, n1 = d.n1;
     const T2 *__restrict__ fin = static_cast<const T2 *>(d.f[par]);
     T2 *__restrict__ fout = static_cast<T2 *>(d.f[par ^ 1]);
+    const T2 *__restrict__ corr = static_cast<const T2 *>(d.corr);
 
     const double *Win = d.W[par] + 4 * c;
     const double W0 = uni(Win[0]), W1 = uni(Win[1]), W2 = uni(Win[2]), W3 = uni(Win[3]);
@@ -147,7 +137,7 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
     T wcoef = 0;
     double S0x = 0, S0y = 0;
     if (wl >= 0) {
-        wcoef = uni((T)(d.F[par][wl] / d.D[wl]));
+        wcoef = uni((T)((SO ? d.F[par][wl] + d.dF[wl] : d.F[par][wl]) / d.D[wl]));
         S0x = uni(d.S[8 * c]);
         S0y = uni(d.S[8 * c + 1]);
     }
@@ -170,7 +160,7 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
     double m0 = 0, m1 = 0, m2 = 0, m3 = 0, mF = 0;
     // one velocity (1-D indices a, b): the point-implicit update from the
     // four face sources, and the new value's share of the FP64 moments
-    auto update = [&](int a, int b, const T2 (&up)[4]) {
+    auto update = [&](int a, int b, const T2 (&up)[4], T2 cr) {
         const T v1 = (T)sm.vx[a], v2 = (T)sm.vy[b];
         T out = 0, in1 = 0, in2 = 0;
 #pragma unroll
@@ -182,6 +172,10 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
                 in1 -= s * (sc[q] * up[q].x);
                 in2 -= s * (sc[q] * up[q].y);
             }
+        }
+        if constexpr (SO) {
+            in1 -= cr.x;
+            in2 -= cr.y;
         }
         const T g1 = gc * sm.ex[w][a] * sm.ey[w][b];
         const T g2 = th2 * g1;
@@ -217,7 +211,7 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
                 f4 u4[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) u4[q] = *reinterpret_cast<const f4 *>(src[q] + k);
-                T2 u0[4], u1[4];
+                T2 u0[4], u1[4], cr0 = {0, 0}, cr1 = {0, 0};
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     u0[q].x = u4[q].x;
@@ -225,7 +219,14 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
                     u1[q].x = u4[q].z;
                     u1[q].y = u4[q].w;
                 }
-                const T2 r0 = update(a, b, u0), r1 = update(a + 1, b, u1);
+                if constexpr (SO) {
+                    const f4 c4 = *reinterpret_cast<const f4 *>(corr + row + k);
+                    cr0.x = c4.x;
+                    cr0.y = c4.y;
+                    cr1.x = c4.z;
+                    cr1.y = c4.w;
+                }
+                const T2 r0 = update(a, b, u0, cr0), r1 = update(a + 1, b, u1, cr1);
                 const f4 r4 = {(float)r0.x, (float)r0.y, (float)r1.x, (float)r1.y};
                 __builtin_nontemporal_store(r4, reinterpret_cast<f4 *>(fout + row + k));
                 accumulate(a, b, r0);
@@ -247,10 +248,11 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
             if (act && k < nv) {
                 // the face kind is uniform over the wave, only the sign of
                 // v.S differs between lanes: issue every face's load first
-                T2 up[4];
+                T2 up[4], cr = {0, 0};
 #pragma unroll
                 for (int q = 0; q < 4; q++) up[q] = src[q][k];
-                const T2 r = update(a, b, up);
+                if constexpr (SO) cr = corr[row + k];
+                const T2 r = update(a, b, up, cr);
                 // streaming stores: the new row is not read again in this sweep
                 __builtin_nontemporal_store(r.x, &fout[row + k].x);
                 __builtin_nontemporal_store(r.y, &fout[row + k].y);
@@ -355,8 +357,10 @@ __device__ __forceinline__ void moments_wave(const DevSolve &d, int c, int par)
 // phi^{n+1} = (sum_out v.S phi_down + V (phi_eq/tau + phi_tau)) / (sum_out v.S + V/tau)
 // Epilogue: What (eq. adjoint_macdefines, via primitive variables),
 // rho_tau, the wall multiplier Phi_l and the residual partials of phi^{n+1}.
+// SO (second-order scheme): the held reconstruction term E is subtracted
+// from the numerator.
 // ---------------------------------------------------------------------------
-template <typename T, bool XCH>
+template <typename T, bool XCH, bool SO>
 __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
 {
     using T2 = typename Vec2<T>::type;
@@ -369,6 +373,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
     const T2 *__restrict__ pin = static_cast<const T2 *>(d.phi[par]);
     T2 *__restrict__ pout = static_cast<T2 *>(d.phi[par ^ 1]);
     const T2 *__restrict__ fst = static_cast<const T2 *>(d.fstar);
+    const T2 *__restrict__ eterm = static_cast<const T2 *>(d.corr);
 
     const double *ac = d.acoef + 16 * c;
     const double rho = uni(ac[0]), u1 = uni(ac[1]), u2 = uni(ac[2]), th = uni(ac[3]), itau = uni(ac[4]);
@@ -417,7 +422,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
     // one velocity (1-D indices a, b): the point-implicit update from the
     // downstream values of the four faces, and the new value's share of the
     // FP64 adjoint moments, the wall multiplier and the residual
-    auto update = [&](int a, int b, const T2 (&dwn)[4]) {
+    auto update = [&](int a, int b, const T2 (&dwn)[4], T2 e) {
         const double v1d = sm.vx[a], v2d = sm.vy[b];
         const T v1 = (T)v1d, v2 = (T)v2d;
         const T mj = (T)mJ_of(obj, v1d, v2d);
@@ -434,6 +439,10 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
                     a1 += s * (Phi_w - mj);
                 }
             }
+        }
+        if constexpr (SO) {
+            a1 -= e.x;
+            a2 -= e.y;
         }
         const T vv2 = (T)0.5 * (v1 * v1 + v2 * v2);
         const T s1 = Ct0 + Ct1 * v1 + Ct2 * v2 + Ct3 * vv2;
@@ -470,11 +479,12 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
         int a = lane % n1, b = lane / n1;
         const int da = kWave % n1, db = kWave / n1;
         const int nstep = (nv + kWave - 1) / kWave;
-        T2 own_n = {0, 0}, fs_n = {0, 0}, dwn_n[4] = {};
+        T2 own_n = {0, 0}, fs_n = {0, 0}, e_n = {0, 0}, dwn_n[4] = {};
         if (act) {
             const int k = min(lane, nv - 1);
             own_n = pin[row + k];
             fs_n = fst[row + k];
+            if constexpr (SO) e_n = eterm[row + k];
 #pragma unroll
             for (int q = 0; q < 4; q++) dwn_n[q] = dsrc[q][k];
         }
@@ -484,7 +494,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
             // every wave publishes its own values of this step, then the
             // next step's loads go out before this step's arithmetic
             sm.xch[buf][w][lane] = own_n;
-            const T2 old = own_n, fs = fs_n;
+            const T2 old = own_n, fs = fs_n, e = e_n;
             T2 dwn[4];
 #pragma unroll
             for (int q = 0; q < 4; q++) dwn[q] = dwn_n[q];
@@ -493,6 +503,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
                 const int kn = min(k + kWave, nv - 1);
                 own_n = pin[row + kn];
                 fs_n = fst[row + kn];
+                if constexpr (SO) e_n = eterm[row + kn];
 #pragma unroll
                 for (int q = 0; q < 4; q++) dwn_n[q] = dsrc[q][kn];
             }
@@ -500,7 +511,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
             for (int q = 0; q < 4; q++)
                 if (slot[q] >= 0) dwn[q] = sm.xch[buf][slot[q]][lane];
             if (act && k < nv) {
-                const T2 r = update(a, b, dwn);
+                const T2 r = update(a, b, dwn, e);
                 __builtin_nontemporal_store(r.x, &pout[row + k].x);
                 __builtin_nontemporal_store(r.y, &pout[row + k].y);
                 accumulate(a, b, k, r, fs, old);
@@ -524,7 +535,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
                 f4 d4[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) d4[q] = *reinterpret_cast<const f4 *>(dsrc[q] + k);
-                T2 d0[4], d1[4];
+                T2 d0[4], d1[4], e0 = {0, 0}, e1 = {0, 0};
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     d0[q].x = d4[q].x;
@@ -532,7 +543,14 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
                     d1[q].x = d4[q].z;
                     d1[q].y = d4[q].w;
                 }
-                const T2 r0 = update(a, b, d0), r1 = update(a + 1, b, d1);
+                if constexpr (SO) {
+                    const f4 e4 = *reinterpret_cast<const f4 *>(eterm + row + k);
+                    e0.x = e4.x;
+                    e0.y = e4.y;
+                    e1.x = e4.z;
+                    e1.y = e4.w;
+                }
+                const T2 r0 = update(a, b, d0, e0), r1 = update(a + 1, b, d1, e1);
                 const f4 r4 = {(float)r0.x, (float)r0.y, (float)r1.x, (float)r1.y};
                 __builtin_nontemporal_store(r4, reinterpret_cast<f4 *>(pout + row + k));
                 T2 fs0, fs1, old0, old1;
@@ -562,10 +580,11 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
             const int k = t * kWave + lane;
             if (act && k < nv) {
                 const T2 old = pin[row + k], fs = fst[row + k];
-                T2 dwn[4];
+                T2 dwn[4], e = {0, 0};
 #pragma unroll
                 for (int q = 0; q < 4; q++) dwn[q] = dsrc[q][k];
-                const T2 r = update(a, b, dwn);
+                if constexpr (SO) e = eterm[row + k];
+                const T2 r = update(a, b, dwn, e);
                 __builtin_nontemporal_store(r.x, &pout[row + k].x);
                 __builtin_nontemporal_store(r.y, &pout[row + k].y);
                 accumulate(a, b, k, r, fs, old);
@@ -606,12 +625,12 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
 constexpr int kPatchBlock = kPatchCells * kWave;   // threads of a patch workgroup
 static_assert(kPatchCells >= 4, "the velocity tables are loaded by the first 256 threads");
 
-template <typename T>
+template <typename T, bool SO>
 __global__ __launch_bounds__(kPatchBlock) void k_primal_sweep(DevSolve d, int par)
 {
     const int p = xcd_item(d.np, blockIdx.x);
     if (p < 0) return;
-    primal_patch<T>(d, p, par);
+    primal_patch<T, SO>(d, p, par);
 }
 
 template <typename T>
@@ -621,12 +640,12 @@ __global__ __launch_bounds__(kBlock) void k_moments(DevSolve d, int par)
     if (c < d.nc) moments_wave<T>(d, c, par);
 }
 
-template <typename T>
+template <typename T, bool SO>
 __global__ __launch_bounds__(kPatchBlock) void k_adjoint_sweep(DevSolve d, int par)
 {
     const int p = xcd_item(d.np, blockIdx.x);
     if (p < 0) return;
-    adjoint_patch<T, kAdjointExchange<T>>(d, p, par);
+    adjoint_patch<T, kAdjointExchange<T>, SO>(d, p, par);
 }
 
 // one sweep of the primal-phase (or adjoint-phase) members of a batch; a
@@ -640,7 +659,7 @@ __global__ __launch_bounds__(kPatchBlock) void k_batch_primal(const DevSolve *__
 {
     const int s = blk_solve[blockIdx.x];
     if (s < 0) return;
-    primal_patch<T>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
+    primal_patch<T, false>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
 }
 
 template <typename T>
@@ -651,7 +670,7 @@ __global__ __launch_bounds__(kPatchBlock) void k_batch_adjoint(const DevSolve *_
 {
     const int s = blk_solve[blockIdx.x];
     if (s < 0) return;
-    adjoint_patch<T, kAdjointExchange<T>>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
+    adjoint_patch<T, kAdjointExchange<T>, false>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
 }
 
 // f = far-field Maxwellian everywhere (storage type)
@@ -814,7 +833,12 @@ hipError_t launch_moments(const DevSolve &d, int par, hipStream_t st)
 
 hipError_t launch_primal_sweep(const DevSolve &d, int par, hipStream_t st)
 {
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_primal_sweep<T>, dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0, st, d, par));
+    if (d.order == 2)
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL((k_primal_sweep<T, true>), dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0,
+                                                 st, d, par));
+    else
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL((k_primal_sweep<T, false>), dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0,
+                                                 st, d, par));
     return hipGetLastError();
 }
 
@@ -826,8 +850,12 @@ hipError_t launch_residual(const DevSolve &d, int adjoint, hipStream_t st)
 
 hipError_t launch_objective(const DevSolve &d, int par, hipStream_t st)
 {
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_objective_elem<T>, dim3(d.nw), dim3(kBlock), 0, st, d, par));
-    if (hipError_t e = hipGetLastError()) return e;
+    if (d.order == 2) {
+        if (hipError_t e = launch_so_objective_elem(d, par, st)) return e;
+    } else {
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_objective_elem<T>, dim3(d.nw), dim3(kBlock), 0, st, d, par));
+        if (hipError_t e = hipGetLastError()) return e;
+    }
     hipLaunchKernelGGL(k_objective_sum, dim3(1), dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }
@@ -855,7 +883,12 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
 
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st)
 {
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_adjoint_sweep<T>, dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0, st, d, par));
+    if (d.order == 2)
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL((k_adjoint_sweep<T, true>), dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0,
+                                                 st, d, par));
+    else
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL((k_adjoint_sweep<T, false>), dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0,
+                                                 st, d, par));
     return hipGetLastError();
 }
 

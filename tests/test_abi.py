@@ -104,3 +104,26 @@ def test_workspace_bytes_exact_and_monotone():
     assert mixed >= 4 * pairs * 2 * 4 and mixed < full
     assert primal_only >= 2 * pairs * 2 * 8 and primal_only < full / 1.9
     assert dvm.lib().dvm_batch_work_bytes(3, 1000) > 0
+
+
+def test_second_order_scheme_setting_and_workspace():
+    """dvm_solver_set_scheme checks its arguments and grows the workspace by
+    the second-order buffers (slopes, correction, limiter factors, face
+    offsets, wall-flux correction); no device work."""
+    wl = I.tiny_naca()
+    m, g = dvm.Mesh.from_grid(wl.grid), dvm.VGrid.from_spec(wl.vgrid)
+    for prec, e in ((dvm.FP64, 8), (dvm.MIXED, 4)):
+        for adj in (True, False):
+            s1 = dvm.Solver(m, g, 0.5, 0.8, precision=prec, want_adjoint=adj, bind=False)
+            s2 = dvm.Solver(m, g, 0.5, 0.8, precision=prec, want_adjoint=adj, bind=False, order=2)
+            nc, nv, nw = s1.nc, s1.nv, s1.nw
+            need = 2 * 8 * nc * 8 + (4 + 2 + (2 if adj else 0)) * nc * nv * e + nw * 8
+            extra = s2.workspace_bytes - s1.workspace_bytes
+            assert need <= extra <= need + 6 * 256
+    s = dvm.Solver(m, g, 0.5, 0.8, bind=False)
+    for args in ((3, 1, 5), (0, 1, 5), (2, 2, 5), (2, 1, 0)):
+        with pytest.raises(dvm.DvmError) as e:
+            dvm._check(dvm.lib().dvm_solver_set_scheme(s._h, *args))
+        assert e.value.code == dvm.DVM_EINVAL
+    dvm._check(dvm.lib().dvm_solver_set_scheme(s._h, 2, dvm.LIMITER_NONE, 1))
+    dvm._check(dvm.lib().dvm_solver_set_scheme(s._h, 1, dvm.LIMITER_VENKAT, 5))

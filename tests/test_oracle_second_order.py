@@ -5,12 +5,12 @@ header of that part).
 
 * Green-Gauss slopes are exact for a linear field on a grid of equal
   parallelograms (the face mean of the two cell values is then the value at
-  the face midpoint), the Barth-Jespersen factor of a linear field is 1, and
+  the face midpoint), the limiter factor of a linear field is 1, and
   the reconstructed face values are the field's values at the face
   midpoints.
-* Barth-Jespersen: every limited face value lies within the minimum and
-  maximum of the cell and its interior neighbours, and a limited cell
-  (psi < 1) reaches that bound at one of its faces.
+* Venkatakrishnan limiter: a limited face value leaves the range of the
+  cell and its interior neighbours by at most e / (2 sqrt 2), e = 1e-3 |f_c|
+  (a bound derived from the limiter function), and psi moves smoothly with f.
 * Defect correction: the converged state solves the second-order balance
   R2 = 0 and does not depend on the correction interval K.
 * Order of accuracy: under refinement of the circle's O-grid the drag's
@@ -57,7 +57,7 @@ def test_linear_field_is_reconstructed_exactly():
         for i in range(1, ni - 1):
             c = i + ni * j
             assert np.max(np.abs(G[c] - b)) < 1e-12 * np.max(np.abs(b))
-            assert np.all(psi[c] == 1.0)
+            assert np.all(psi[c] >= 1.0 - 1e-14)
             if 2 <= i <= ni - 3 and 2 <= j <= nj - 3:
                 Q = _corners(nodes, i, j)
                 for q in range(4):
@@ -66,8 +66,15 @@ def test_linear_field_is_reconstructed_exactly():
                     assert np.max(np.abs(faces[c, q] - exact)) < 1e-13 * np.max(np.abs(exact))
 
 
+KAPPA = 1e-3      # Venkatakrishnan smoothing relative to the cell value
+
+
 @pytest.mark.parametrize("wl", [I.tiny_circle(), I.tiny_naca()], ids=lambda w: w.name)
-def test_barth_jespersen_bounds(wl):
+def test_limiter_bounds_and_smoothness(wl):
+    """Venkatakrishnan: with D the room to the neighbourhood's max (min) and
+    d the unlimited increment, phi d - D = (e^2 (d - D) - D^3) / den with
+    den >= 2 d^2 + e^2, so a limited face value leaves [lo, hi] by at most
+    e / (2 sqrt 2), e = kappa |f_c|; and psi is a smooth function of f."""
     p = _problem(wl)
     m = p.mesh()
     nbr, cen = m["nbr"], m["cen"]
@@ -76,7 +83,7 @@ def test_barth_jespersen_bounds(wl):
     f = np.exp(rng.standard_normal((p.nc, p.nv, 2)))
     G, psi = p.so_slopes(f)
     assert np.all(psi >= 0.0) and np.all(psi <= 1.0)
-    assert np.mean(psi < 1.0) > 0.5          # a rough field is limited almost everywhere
+    assert np.mean(psi < 0.5) > 0.3          # a rough field is limited strongly in many cells
     for c in range(p.nc):
         i, j = c % g.ni, c // g.ni
         Q = _corners(g.nodes, i, j)
@@ -85,11 +92,12 @@ def test_barth_jespersen_bounds(wl):
         lo = np.minimum(f[c], f[nb].min(axis=0))
         hi = np.maximum(f[c], f[nb].max(axis=0))
         vals = f[c][None] + np.einsum("kmd,qd->qkm", G[c], mids - cen[c])    # [q, k, m]
-        tol = 1e-12 * np.abs(f[c]).max()
-        assert np.all(vals >= lo[None] - tol) and np.all(vals <= hi[None] + tol)
-        # a limited component touches a bound at some face
-        gap = np.minimum(vals - lo[None], hi[None] - vals).min(axis=0)       # [k, m]
-        assert np.all(gap[psi[c] < 1.0] < tol)
+        slack = KAPPA * np.abs(f[c])[None] / (2 * np.sqrt(2)) * (1 + 1e-9) + 1e-14 * np.abs(f[c]).max()
+        assert np.all(vals >= lo[None] - slack) and np.all(vals <= hi[None] + slack)
+    # smooth: a relative perturbation of 1e-12 moves psi by O(1e-12 / kappa) at most
+    f2 = f * (1 + 1e-12 * rng.standard_normal(f.shape))
+    _, psi2 = p.so_slopes(f2)
+    assert np.max(np.abs(psi2 - psi)) < 1e-7
 
 
 @pytest.mark.parametrize("wl", [I.tiny_circle(Kn=1.0, Ma=0.5), I.tiny_naca(Kn=0.7, Ma=1.2)],
@@ -109,11 +117,14 @@ def test_defect_correction_fixed_point(wl):
     q.primal_init()
     q.primal_solve(1e-14, 20000, 100)
     assert abs(q.objective() - Js[0]) > 1e-3 * abs(Js[0])     # the reconstruction is active
-    # with the limiter the iteration settles to the limiter's noise level
-    p = _problem(wl, limiter=True, K=10)
+    # with the (smooth) limiter the iteration converges as well, to a state
+    # that differs from the unlimited one
+    p = _problem(wl, limiter=True, K=5)
     p.primal_init()
-    p.primal_iterate(4000)
-    assert np.max(np.abs(p.primal_residual())) < 1e-3 * np.max(np.abs(p.f))
+    it, r = p.primal_solve(1e-14, 20000, 100)
+    assert r < 1e-14
+    assert np.max(np.abs(p.primal_residual())) < 1e-13 * np.max(np.abs(p.f))
+    assert abs(p.objective() - Js[0]) > 1e-5 * abs(Js[0])
 
 
 def test_grid_convergence_order():
@@ -132,7 +143,7 @@ def test_grid_convergence_order():
     assert 3.4 < ratio[2] < 6.0, ratio
 
 
-@pytest.mark.parametrize("limiter", [False, True], ids=["unlimited", "barth_jespersen"])
+@pytest.mark.parametrize("limiter", [False, True], ids=["unlimited", "venkatakrishnan"])
 @pytest.mark.parametrize("wl", [I.tiny_circle(Kn=1.0, Ma=0.5), I.tiny_naca(Kn=0.7, Ma=1.2)],
                          ids=lambda w: w.name)
 def test_adjoint_dot_product_identity(wl, limiter):

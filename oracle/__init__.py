@@ -297,8 +297,6 @@ class Problem:
         return lib().or_adjoint_dJdp(self._h, which)
 
     def wall_sensitivity(self):
-        if self.order != 1:
-            raise ValueError("oracle: the wall sensitivity is implemented for the first-order scheme")
         SA = np.zeros(self.nw)
         Sx = np.zeros((self.nw, 2))
         Sn = np.zeros((self.nw, 2))

@@ -1419,9 +1419,43 @@ void or_mesh_sensitivity(or_problem *p, double h, double *out)
 /* wall sensitivity                                                    */
 /* ------------------------------------------------------------------ */
 
+/* The scheme's values the sensitivity formulas read: order 1 takes the
+ * upwind cell values and the wall flux F_l; order 2 the reconstructed
+ * values (slopes G of f) and F_l + dF_l.  The paper evaluates its formulas
+ * with the values of its (second-order) scheme. */
+typedef struct { double *G; double *Fw; } wall_ctx;
+
+static wall_ctx wall_ctx_make(const or_problem *p)
+{
+    wall_ctx w = { NULL, malloc(sizeof(double) * (p->nw > 0 ? p->nw : 1)) };
+    if (p->order == 2) {
+        w.G = malloc(sizeof(double) * 4 * (size_t)p->nc * p->nv);
+        so_slopes(p, p->f, w.G, NULL);
+        so_wall_dF(p, w.G, w.Fw);
+        for (int l = 0; l < p->nw; l++) w.Fw[l] += p->F[l];
+    } else {
+        for (int l = 0; l < p->nw; l++) w.Fw[l] = p->F[l];
+    }
+    return w;
+}
+
+static void wall_ctx_free(wall_ctx *w) { free(w->G); free(w->Fw); }
+
+/* wall value of component m at element l, velocity k: the wall cell's
+ * (reconstructed) value on Xi^+, the diffuse value on Xi^- */
+static double wall_fx(const or_problem *p, const wall_ctx *w, int l, int k, int m)
+{
+    int c = p->wall_cell[l];
+    double vn = p->v[2 * k] * p->wn[2 * l] + p->v[2 * k + 1] * p->wn[2 * l + 1];
+    if (vn > 0)
+        return p->f[((size_t)c * p->nv + k) * 2 + m] + (w->G ? so_delta(p, w->G, c, p->wall_face[l], k, m, 1.0) : 0.0);
+    double g1 = w->Fw[l] * p->gM[k] / p->D[l];
+    return m == 0 ? g1 : 0.5 * p->theta_w * g1;
+}
+
 /* Green-Gauss gradient of eq. (gaussgrad) at cell c, velocity k, with the
- * first-order upwind face values of the primal scheme */
-static void gauss_grad(const or_problem *p, int c, int k, double g[2][2])
+ * scheme's face values (upwind side; reconstructed at order 2) */
+static void gauss_grad(const or_problem *p, const wall_ctx *w, int c, int k, double g[2][2])
 {
     double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
     const double *fc = p->f + ((size_t)c * p->nv + k) * 2;
@@ -1431,7 +1465,8 @@ static void gauss_grad(const or_problem *p, int c, int k, double g[2][2])
         double Sx = p->S[8 * c + 2 * q], Sy = p->S[8 * c + 2 * q + 1];
         double s = v1 * Sx + v2 * Sy, a1, a2;
         if (s > 0) { a1 = fc[0]; a2 = fc[1]; }
-        else inflow_value(p, p->f, p->F, c, q, k, &a1, &a2);
+        else inflow_value(p, p->f, w->Fw, c, q, k, &a1, &a2);
+        if (w->G) { a1 += so_delta(p, w->G, c, q, k, 0, s); a2 += so_delta(p, w->G, c, q, k, 1, s); }
         g[0][0] += a1 * Sx; g[0][1] += a1 * Sy;
         g[1][0] += a2 * Sx; g[1][1] += a2 * Sy;
     }
@@ -1444,6 +1479,7 @@ static void gauss_grad(const or_problem *p, int c, int k, double g[2][2])
 void or_wall_sensitivity(or_problem *p, double *SA, double *Sx, double *Sn, double *dJdnodes)
 {
     const int nv = p->nv, nw = p->nw;
+    wall_ctx wc = wall_ctx_make(p);
     for (int l = 0; l < nw; l++) {
         int c = p->wall_cell[l];
         double n1 = p->wn[2 * l], n2 = p->wn[2 * l + 1], A = p->wA[l];
@@ -1452,9 +1488,9 @@ void or_wall_sensitivity(or_problem *p, double *SA, double *Sx, double *Sn, doub
         double Phi = 0, jn[2] = { 0, 0 };
         for (int k = 0; k < nv; k++) {
             double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], vn = v1 * n1 + v2 * n2, wk = p->w[k];
-            double f1 = wall_f1(p, p->f, l, k);
+            double f1 = wall_fx(p, &wc, l, k, 0);
             double gr[2][2];
-            gauss_grad(p, c, k, gr);
+            gauss_grad(p, &wc, c, k, gr);
             sa += wk * p->mJ[k] * vn * f1;
             jx[0] += wk * p->mJ[k] * vn * gr[0][0];
             jx[1] += wk * p->mJ[k] * vn * gr[0][1];
@@ -1479,6 +1515,7 @@ void or_wall_sensitivity(or_problem *p, double *SA, double *Sx, double *Sn, doub
         Sn[2 * l] = A * (jn[0] - Phi * M[0]);
         Sn[2 * l + 1] = A * (jn[1] - Phi * M[1]);
     }
+    wall_ctx_free(&wc);
     if (!dJdnodes) return;
     for (int m = 0; m < 2 * nw; m++) dJdnodes[m] = 0;
     for (int l = 0; l < nw; l++) {
@@ -1513,14 +1550,15 @@ double or_wall_JB(or_problem *p, int l, double A, double x1, double x2, double n
     double on1 = p->wn[2 * l], on2 = p->wn[2 * l + 1];
     double dx1 = x1 - p->wx[2 * l], dx2 = x2 - p->wx[2 * l + 1];
     const double *ph = p->phi + (size_t)c * nv * 2;
+    wall_ctx wc = wall_ctx_make(p);
     /* F and D at (x, n) */
     double F = 0, D = 0;
     for (int k = 0; k < nv; k++) {
         double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
         double vn0 = v1 * on1 + v2 * on2, vn = v1 * n1 + v2 * n2;
         double gr[2][2];
-        gauss_grad(p, c, k, gr);
-        if (vn0 > 0) F += p->w[k] * vn * (wall_f1(p, p->f, l, k) + gr[0][0] * dx1 + gr[0][1] * dx2);
+        gauss_grad(p, &wc, c, k, gr);
+        if (vn0 > 0) F += p->w[k] * vn * (wall_fx(p, &wc, l, k, 0) + gr[0][0] * dx1 + gr[0][1] * dx2);
         else D -= p->w[k] * vn * p->gM[k];
     }
     double J = 0, B = 0;
@@ -1528,9 +1566,9 @@ double or_wall_JB(or_problem *p, int l, double A, double x1, double x2, double n
         double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
         double vn0 = v1 * on1 + v2 * on2, vn = v1 * n1 + v2 * n2;
         double gr[2][2];
-        gauss_grad(p, c, k, gr);
-        double f1l = wall_f1(p, p->f, l, k);
-        double f2l = vn0 > 0 ? p->f[((size_t)c * nv + k) * 2 + 1] : 0.5 * p->theta_w * f1l;
+        gauss_grad(p, &wc, c, k, gr);
+        double f1l = wall_fx(p, &wc, l, k, 0);
+        double f2l = wall_fx(p, &wc, l, k, 1);
         double f1x = f1l + gr[0][0] * dx1 + gr[0][1] * dx2;
         double f2x = f2l + gr[1][0] * dx1 + gr[1][1] * dx2;
         J += p->w[k] * p->mJ[k] * vn * f1x;
@@ -1540,5 +1578,6 @@ double or_wall_JB(or_problem *p, int l, double A, double x1, double x2, double n
             B += p->w[k] * (pw1 * (f1x - F * gb1) + pw2 * (f2x - F * gb2));
         }
     }
+    wall_ctx_free(&wc);
     return A * (J + B);
 }

@@ -3,7 +3,7 @@
 * Element derivatives (eqs. sens_J_itf, sens_B_itf with eq. gaussgrad)
   against central differences of the discrete J_l + B_w,l expressions
   (eqs. numer_J, numer_B) evaluated at perturbed element attributes with f
-  and phi frozen.
+  and phi frozen; for the first- and the second-order scheme.
 * Node transform (eq. sens_nod) against central differences of the
   element geometry (length, midpoint, unit normal into the solid) as
   functions of the two end nodes.
@@ -20,8 +20,10 @@ import oracle
 from paper_2501_00923_amd import inputs as I
 
 
-def _solved(wl, adjoint=True):
+def _solved(wl, adjoint=True, order=1):
     p = oracle.Problem.from_workload(wl, nthreads=4)
+    if order == 2:
+        p.set_scheme(2, True, 5)
     p.primal_init()
     p.primal_solve(1e-14, 30000)
     if adjoint:
@@ -30,10 +32,13 @@ def _solved(wl, adjoint=True):
     return p
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("wl", [I.tiny_circle(Kn=1.0, Ma=0.5), I.tiny_naca(Kn=0.7, Ma=1.2)],
                          ids=lambda w: w.name)
-def test_element_derivatives_match_discrete_definitions(wl):
-    p = _solved(wl)
+def test_element_derivatives_match_discrete_definitions(wl, order):
+    """order 2: the same formulas with the second-order scheme's values
+    (reconstructed wall and face values, F_l + dF_l)."""
+    p = _solved(wl, order=order)
     s = p.wall_sensitivity()
     m = p.mesh()
     for l in range(0, p.nw, 3):
@@ -85,23 +90,25 @@ def test_node_transform_matches_geometry_differences():
             assert abs(fd - s["dJ_dnodes"][mm, d]) < 1e-6 * (np.max(np.abs(s["dJ_dnodes"])) + 1e-12)
 
 
-def test_circle_sine_modes_have_zero_sensitivity():
+@pytest.mark.parametrize("order", [1, 2])
+def test_circle_sine_modes_have_zero_sensitivity(order):
     wl = I.tiny_circle(Kn=1.0, Ma=0.5)
-    p = _solved(wl)
+    p = _solved(wl, order=order)
     s = p.wall_sensitivity()
     dJ = np.einsum("md,mdp->p", s["dJ_dnodes"], wl.grid.wall_jac)
     assert np.max(np.abs(dJ[4:])) < 1e-12 * abs(dJ[0])
     assert abs(dJ[0]) > 0.1
 
 
-def test_symmetric_profile_mirrored_bumps_equal():
+@pytest.mark.parametrize("order", [1, 2])
+def test_symmetric_profile_mirrored_bumps_equal(order):
     h = np.array([0.3, 0.6, 0.3, 0.6])
     wl = I.tiny_naca(Kn=0.7, Ma=1.2, perturb={"kind": "hicks_henne", "h": h, "n_up": 2,
                                               "amp": np.zeros(4)})
     g = I.naca_cgrid(4, 8, 6, t=0.12, m=0.0, r_outer=4.0, h1=0.05,
                      perturb={"kind": "hicks_henne", "h": h, "n_up": 2, "amp": np.zeros(4)})
     wl.grid = g
-    p = _solved(wl)
+    p = _solved(wl, order=order)
     s = p.wall_sensitivity()
     dJ = np.einsum("md,mdp->p", s["dJ_dnodes"], g.wall_jac)
     np.testing.assert_allclose(dJ[:2], dJ[2:], rtol=1e-11)

@@ -30,9 +30,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
-# the sweep kernels, their layout constants and the host-built sweep order
+# the sweep and second-order kernels, their layout constants and the host-built sweep order
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2501_00923_amd", "csrc", f)
-               for f in ("dvm_kernels.hip", "dvm_device.h", "dvm_internal.h", "dvm_host.cpp")]
+               for f in ("dvm_kernels.hip", "dvm_so.hip", "dvm_device.h", "dvm_internal.h", "dvm_host.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_naca0012_c256x128_v48_traffic.json")
 
 
@@ -51,13 +51,27 @@ def bytes_per_update(kind: str, mixed: bool) -> int:
     return (4 if kind == "primal" else 6) * e
 
 
-def run_gpu(wl, precision, sweeps, steps, warmup):
+def so_bytes_per_update(kind: str, mixed: bool, k: int) -> dict:
+    """Bytes per (cell, velocity) of the second-order path as built, per
+    sweep: the sweep's own row traffic plus the held correction it reads,
+    and the correction kernels' traffic spread over the K sweeps that use
+    it (primal: slopes read f, write G (4 values); correction reads G, writes
+    c.  Adjoint: B reads phi and psi, writes B (4); E reads B, writes E)."""
+    e = 4 if mixed else 8
+    if kind == "primal":
+        sweep, corr = 6 * e, (2 + 4) * e + (4 + 2) * e
+    else:
+        sweep, corr = 8 * e, (2 + 2 + 4) * e + (4 + 2) * e
+    return {"sweep": sweep, "correction": corr, "per_sweep": sweep + corr / k}
+
+
+def run_gpu(wl, precision, sweeps, steps, warmup, order=1, correction_every=10):
     import numpy as np
     import torch
 
     from paper_2501_00923_amd import dvm
 
-    s = dvm.Solver.from_workload(wl, precision=precision)
+    s = dvm.Solver.from_workload(wl, precision=precision, order=order, correction_every=correction_every)
     jac = wl.grid.wall_jac
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     tp, ta = [], []
@@ -73,7 +87,7 @@ def run_gpu(wl, precision, sweeps, steps, warmup):
         ev[2].record()
         s.adjoint_sweeps(sweeps)
         ev[3].record()
-        dJ = s.param_sensitivity(jac)
+        dJ = s.param_sensitivity(jac) if order == 1 else None
         if record:
             torch.cuda.synchronize()
             tp.append(ev[0].elapsed_time(ev[1]) / sweeps)
@@ -204,13 +218,15 @@ def precision_sweep(sweeps, kns, oracle_check_sweeps=2):
     return rows
 
 
-def fd_check(h, tol, params=None):
+def fd_check(h, tol, params=None, order=1):
     """The differentiation workload (seed-drawn NACA thickness and camber,
     192x96 C-grid, 48x48 Newton-Cotes grid, Kn 0.5, Ma 2, 24 B-spline
     offsets): dJ/dalpha from the adjoint through the autograd wrapper
     (primal f snapshotted every 50 sweeps), in the paper's wall-only form and
     in the exact discrete form, against central differences J(alpha +- h e_p)
-    of re-converged primal solves."""
+    of re-converged primal solves.  order 2: the second-order scheme
+    (Venkatakrishnan limiter, correction every 10 sweeps); the wall-only form
+    only."""
     import numpy as np
     import torch
 
@@ -218,6 +234,7 @@ def fd_check(h, tol, params=None):
 
     opts = AG.SolveOptions(max_iter=60000, tol=tol, adjoint_max_iter=60000, adjoint_tol=tol, check_every=100)
     case, a0 = AG.naca_bspline_case(seed=0, options=opts, checkpoint_every=50, keep_checkpoints=1)
+    case.order = order
     rec = AG.ForwardRecord()
     alpha = torch.tensor(a0, requires_grad=True)
     t0 = time.perf_counter()
@@ -225,11 +242,13 @@ def fd_check(h, tol, params=None):
     J.backward()
     t_grad = time.perf_counter() - t0
     g = alpha.grad.numpy().copy()
-    case.exact = True
-    alpha_e = torch.tensor(a0, requires_grad=True)
-    AG.drag(alpha_e, case).backward()
-    ge = alpha_e.grad.numpy().copy()
-    case.exact = False
+    ge = np.full_like(g, np.nan)
+    if order == 1:
+        case.exact = True
+        alpha_e = torch.tensor(a0, requires_grad=True)
+        AG.drag(alpha_e, case).backward()
+        ge = alpha_e.grad.numpy().copy()
+        case.exact = False
     print(f"[fd] J {J.item():.12e}, primal {rec.iters} sweeps (resid {rec.resid:.1e}), adjoint "
           f"{rec.adjoint_iters} sweeps (resid {rec.adjoint_resid:.1e}), {t_grad:.1f} s", file=sys.stderr, flush=True)
     case.checkpoint_every = 0
@@ -243,23 +262,26 @@ def fd_check(h, tol, params=None):
         Jp = AG.drag(torch.tensor(a0 + e), case, rp).item()
         Jm = AG.drag(torch.tensor(a0 - e), case, rm).item()
         fd = (Jp - Jm) / (2 * h)
-        rows.append({"param": p, "adjoint": float(g[p]), "adjoint_exact": float(ge[p]), "fd": fd,
+        rows.append({"param": p, "adjoint": float(g[p]), "adjoint_exact": float(ge[p]) if order == 1 else None,
+                     "fd": fd,
                      "sweeps": [rp.iters, rm.iters]})
         print(f"[fd] p {p:2d}: adjoint (wall-only) {g[p]: .6e}  adjoint (exact) {ge[p]: .10e}  fd {fd: .10e}",
               file=sys.stderr, flush=True)
     gv = np.array([r["adjoint"] for r in rows])
-    ev = np.array([r["adjoint_exact"] for r in rows])
+    ev = np.array([r["adjoint_exact"] if order == 1 else np.nan for r in rows], dtype=float)
     fv = np.array([r["fd"] for r in rows])
     scale = float(np.max(np.abs(fv)))
-    return {"workload": "naca_bspline_c192x96_v48nc_kn0.5_ma2 (seed 0)", "h": h, "tol": tol, "J": J.item(),
+    return {"workload": "naca_bspline_c192x96_v48nc_kn0.5_ma2 (seed 0)", "order": order, "h": h, "tol": tol,
+            "J": J.item(),
             "primal_sweeps": rec.iters, "adjoint_sweeps": rec.adjoint_iters,
             "checkpoints_kept": len(rec.checkpoints), "last_checkpoint_sweep": rec.checkpoint_iters[-1],
             "grad_seconds": t_grad, "fd_seconds": time.perf_counter() - t0,
             "wall_only": {"max_abs_diff_over_max_fd": float(np.max(np.abs(gv - fv)) / scale),
                           "median_rel_diff": float(np.median(np.abs(gv - fv) / np.maximum(np.abs(fv), 1e-3 * scale))),
                           "cosine": float(gv @ fv / (np.linalg.norm(gv) * np.linalg.norm(fv)))},
-            "exact": {"max_abs_diff_over_max_fd": float(np.max(np.abs(ev - fv)) / scale),
-                      "median_rel_diff": float(np.median(np.abs(ev - fv) / np.maximum(np.abs(fv), 1e-3 * scale)))},
+            "exact": None if order != 1 else {
+                "max_abs_diff_over_max_fd": float(np.max(np.abs(ev - fv)) / scale),
+                "median_rel_diff": float(np.median(np.abs(ev - fv) / np.maximum(np.abs(fv), 1e-3 * scale)))},
             "rows": rows}
 
 
@@ -313,6 +335,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-second-order", action="store_true",
+                    help="skip the second-order leg (Green-Gauss slopes, Venkatakrishnan limiter)")
+    ap.add_argument("--correction-every", type=int, default=10,
+                    help="second-order leg: sweeps between evaluations of the held correction")
     ap.add_argument("--serving-requests", type=int, default=64,
                     help="requests in the solve-server leg (0 skips it; 512 is the full stream)")
     ap.add_argument("--serving-cap", type=int, default=1000, help="sweep cap per phase per request")
@@ -325,6 +351,8 @@ def main():
                     help="print the adjoint-vs-central-difference table of the 24-parameter B-spline NACA case and exit")
     ap.add_argument("--fd-h", type=float, default=1e-6)
     ap.add_argument("--fd-tol", type=float, default=1e-12)
+    ap.add_argument("--fd-order", type=int, default=1, choices=(1, 2),
+                    help="spatial order of the scheme the --fd-check runs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -356,7 +384,7 @@ def main():
         print(json.dumps({"precision_sweep": rows}))
         return
     if args.fd_check:
-        print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol)}))
+        print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol, order=args.fd_order)}))
         return
     wl = I.c2_naca(seed=0)
     print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",
@@ -404,6 +432,25 @@ def main():
                                      "frac": b / t / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": mixed[key],
                                      "algorithmic_bytes_per_launch": b,
                                      "traffic": tr.get(f"{kind}_mixed_bytes_per_launch")}
+    second = None
+    if not args.no_second_order:
+        K = args.correction_every
+        r2 = run_gpu(wl, dvm.FP64, args.sweeps, args.steps, args.warmup, order=2, correction_every=K)
+        second = {"value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"], "dtype": "f64",
+                  "limiter": "venkatakrishnan", "correction_every": K,
+                  "vs_first_order": r2["updates_per_s"] / r64["updates_per_s"],
+                  "J": r2["J"], "J_rel_diff_vs_first_order": abs(r2["J"] - r64["J"]) / abs(r64["J"]),
+                  "roofline": {}}
+        for kind in ("primal", "adjoint"):
+            t = r2[f"{kind}_sweep_ms"] * 1e-3
+            bb = so_bytes_per_update(kind, False, K)
+            second["roofline"][kind] = {
+                "avg_sweep_ms": r2[f"{kind}_sweep_ms"],
+                "note": "sweep plus its share of the correction kernels",
+                "bytes_per_update": bb, "achieved": bb["per_sweep"] * pairs / t / 1e9,
+                "frac": bb["per_sweep"] * pairs / t / 1e9 / HBM_PEAK_GBS}
+        print(f"[bench] second order {r2['updates_per_s']:.3e} upd/s, primal {r2['primal_sweep_ms']:.3f} ms, "
+              f"adjoint {r2['adjoint_sweep_ms']:.3f} ms per sweep", file=sys.stderr, flush=True)
     serving = None
     if args.serving_requests > 0:
         print(f"[bench] serving leg: {args.serving_requests} requests", file=sys.stderr, flush=True)
@@ -423,7 +470,7 @@ def main():
                    "sweeps_per_step": {"primal": args.sweeps, "adjoint": args.sweeps},
                    "Kn": wl.flow.Kn, "Ma": wl.flow.Ma, "shape_params": int(wl.grid.wall_jac.shape[-1]),
                    "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "serving": serving,
+        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "second_order": second, "serving": serving,
         "J": r64["J"], "Cd": r64["Cd"],
     }
     print(json.dumps(line))

@@ -123,18 +123,24 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
  * slopes (face mean of the two cell values; the cell value on boundary
  * faces), limiter DVM_LIMITER_VENKAT (Venkatakrishnan, per cell, velocity
  * and component, smoothing e = 1e-3 |f_c|) or DVM_LIMITER_NONE, face values
- * reconstructed on the upwind side; far-field and wall inflow are not reconstructed and the wall flux
- * F_l sums the reconstructed outgoing values; the drag uses the same wall
- * values.  It is iterated by defect correction: every correction_interval
- * (K >= 1) sweeps the difference between the second- and first-order face
- * fluxes is evaluated from the current state and held, and the sweeps
- * between are the first-order Jacobi sweep with that difference moved to
- * the right-hand side; a fixed point solves the second-order balance (K = 1
- * is unstable where transport dominates; K >= 3 is advised).  The adjoint
+ * reconstructed on the upwind side; far-field and wall inflow are not
+ * reconstructed and the wall flux F_l sums the reconstructed outgoing
+ * values; the drag uses the same wall values.  It is iterated by defect
+ * correction: every correction_interval (K >= 1) sweeps the difference
+ * between the second- and first-order face fluxes is evaluated from the
+ * current state and held, and the sweeps between are the first-order Jacobi
+ * sweep with that difference moved to the right-hand side; a fixed point
+ * solves the second-order balance.  K must be large enough for the
+ * first-order sweeps to approximate the first-order inverse: K = 1 is
+ * unstable where transport dominates, and K = 5 diverged on C-grids of
+ * 192x96 and 256x128 cells where K = 10 and 20 converge (small grids
+ * converge with K = 3).  Default K = 10.  The adjoint
  * freezes the limiter factors of the converged f (at dvm_adjoint_init) and
  * solves the transpose of that linearisation the same way.  Loading a state
- * re-evaluates the correction at the next sweep.  Batches, the wall, shape
- * and mesh sensitivities are first-order only (DVM_EINVAL). */
+ * re-evaluates the correction at the next sweep.  The wall sensitivity
+ * (and its chain to shape parameters) evaluates the paper's formulas with
+ * the second-order values: reconstructed wall and face values, F_l + dF_l.
+ * Batches and the exact mesh sensitivity are first-order only (DVM_EINVAL). */
 int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_interval);
 /* Exact device bytes the solver needs (used for admission by footprint). */
 size_t dvm_solver_workspace_bytes(const dvm_solver *s);

@@ -47,6 +47,9 @@ class ShapeCase:
     keep_checkpoints: Optional[int] = None   # None: keep every snapshot; n: only the last n
     offload: bool = False
     exact: bool = False      # exact discrete derivative (every mesh node moves) instead of the wall-only form
+    order: int = 1           # spatial scheme: 1, or 2 (wall-only derivative only)
+    limiter: int = dvm.LIMITER_VENKAT
+    correction_every: int = 10
 
 
 @dataclass
@@ -91,7 +94,8 @@ class _DragFn(torch.autograd.Function):
         a = alpha.detach().cpu().double().numpy()
         grid = case.make_grid(a)
         solver = dvm.Solver(dvm.Mesh.from_grid(grid), dvm.VGrid.from_spec(case.vgrid), case.flow.Kn,
-                            case.flow.Ma, case.flow.Tw, case.flow.objective, case.precision, True)
+                            case.flow.Ma, case.flow.Tw, case.flow.objective, case.precision, True,
+                            order=case.order, limiter=case.limiter, correction_every=case.correction_every)
         solver.primal_init()
         _primal(case, solver, rec)
         J, Cd = solver.objective()

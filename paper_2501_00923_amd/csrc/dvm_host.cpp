@@ -263,7 +263,7 @@ struct dvm_solver {
     std::vector<double> gw2;  // [nv][2]
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // spatial scheme: order 1, or 2 with limiter and K sweeps between corrections
-    int order = 1, limiter = DVM_LIMITER_VENKAT, kcorr = 5;
+    int order = 1, limiter = DVM_LIMITER_VENKAT, kcorr = 10;
     // workspace
     struct {
         size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
@@ -954,7 +954,6 @@ int dvm_wall_sensitivity(dvm_solver *s, double *S_A, double *S_x, double *S_n, d
 {
     if (int e = check_bound(s)) return e;
     if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
-    if (int e = first_order_only(s, "the wall sensitivity")) return e;
     if (int e = run_sens(s, 0)) return e;
     std::vector<double> sens(5 * (size_t)s->nw), dn(2 * (size_t)s->nw);
     if (int e = read_back(*s, s->dev.sens, sens.data(), sens.size())) return e;
@@ -978,7 +977,6 @@ int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, d
 {
     if (int e = check_bound(s)) return e;
     if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
-    if (int e = first_order_only(s, "the wall sensitivity")) return e;
     if (n_params < 0 || n_params > dvm::kMaxParams) return fail(DVM_EINVAL, "n_params must be in [0, %d]", dvm::kMaxParams);
     if (n_params > 0 && (!wall_jac || !dJ_dalpha)) return fail(DVM_EINVAL, "null argument");
     std::vector<double> jac((size_t)2 * s->nw * dvm::kMaxParams, 0.0);

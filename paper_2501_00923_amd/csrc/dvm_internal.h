@@ -92,9 +92,11 @@ hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
 hipError_t launch_mesh_sens(const DevSolve &d, int fpar, int ppar, hipStream_t st);
 
-// second-order scheme: the held primal correction c, dF from f[par]; the
+// second-order scheme: the slopes G and dF of f[par]; the held primal
+// correction c (with G and dF) from f[par]; the
 // limiter factors psi of f[fpar] for the adjoint; the held adjoint term E
 // from phi[par]; the drag with reconstructed wall values (per element)
+hipError_t launch_so_slopes(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_so_correction(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_so_freeze(const DevSolve &d, int fpar, hipStream_t st);
 hipError_t launch_so_adjoint_term(const DevSolve &d, int par, hipStream_t st);

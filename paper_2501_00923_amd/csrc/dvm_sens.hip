@@ -10,9 +10,12 @@ namespace dvm {
 
 // ---------------------------------------------------------------------------
 // wall sensitivity, eqs. (sens_J_itf), (gaussgrad), (sens_B_itf): one block
-// per wall element
+// per wall element.  SO (second-order scheme): the formulas take that
+// scheme's values -- wall and face values reconstructed on the upwind side
+// from the slopes G of f (k_so_slope of the same f, which also leaves dF)
+// and the wall flux F + dF.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool SO>
 __global__ __launch_bounds__(kBlock) void k_wall_sens(DevSolve d, int fpar, int ppar)
 {
     using T2 = typename Vec2<T>::type;
@@ -24,14 +27,21 @@ __global__ __launch_bounds__(kBlock) void k_wall_sens(DevSolve d, int fpar, int 
     const T2 *fd = static_cast<const T2 *>(d.fd);
     const T *gM = static_cast<const T *>(d.gM);
     const double n1 = d.wall_n[2 * l], n2 = d.wall_n[2 * l + 1], A = d.wall_A[l];
-    const double iD = 1.0 / d.D[l], F = d.F[fpar][l], thw2 = 0.5 * d.theta_w;
+    const double iD = 1.0 / d.D[l], F = SO ? d.F[fpar][l] + d.dF[l] : d.F[fpar][l], thw2 = 0.5 * d.theta_w;
     const double iV = 1.0 / d.vol[c];
+    const T2 *G = static_cast<const T2 *>(d.G);
     int nb[4];
-    double Sx[4], Sy[4];
+    double Sx[4], Sy[4], rx[4] = {}, ry[4] = {}, nx[4] = {}, ny[4] = {};
     for (int q = 0; q < 4; q++) {
         nb[q] = d.nbr[4 * c + q];
         Sx[q] = d.S[8 * c + 2 * q];
         Sy[q] = d.S[8 * c + 2 * q + 1];
+        if (SO) {
+            rx[q] = d.rf[8 * c + 2 * q];
+            ry[q] = d.rf[8 * c + 2 * q + 1];
+            nx[q] = d.rn[8 * c + 2 * q];
+            ny[q] = d.rn[8 * c + 2 * q + 1];
+        }
     }
     double sa = 0, jx0 = 0, jx1 = 0, jn0 = 0, jn1 = 0, M0 = 0, M1 = 0, G0 = 0, G1 = 0, bx0 = 0, bx1 = 0, Pw = 0;
     const size_t row = (size_t)c * d.nv;
@@ -42,7 +52,13 @@ __global__ __launch_bounds__(kBlock) void k_wall_sens(DevSolve d, int fpar, int 
         const double mj = mJ_of(d.objective, v1, v2);
         const T2 fc = f[row + k];
         const double gw1 = F * (double)gM[k] * iD;
-        const double f1l = vn > 0 ? (double)fc.x : gw1;
+        T2 gc1 = {0, 0}, gc2 = {0, 0};
+        if (SO) {
+            gc1 = G[2 * (row + k)];
+            gc2 = G[2 * (row + k) + 1];
+        }
+        // the outgoing wall value: the cell value, reconstructed at order 2
+        const double f1l = vn > 0 ? (double)fc.x + (SO ? (double)(gc1.x * (T)rx[0] + gc1.y * (T)ry[0]) : 0.0) : gw1;
         // Green-Gauss gradient with the scheme's upwind face values
         double g10 = 0, g11 = 0, g20 = 0, g21 = 0;
         for (int q = 0; q < 4; q++) {
@@ -51,10 +67,20 @@ __global__ __launch_bounds__(kBlock) void k_wall_sens(DevSolve d, int fpar, int 
             if (s > 0) {
                 a1 = (double)fc.x;
                 a2 = (double)fc.y;
+                if (SO) {
+                    a1 += (double)(gc1.x * (T)rx[q] + gc1.y * (T)ry[q]);
+                    a2 += (double)(gc2.x * (T)rx[q] + gc2.y * (T)ry[q]);
+                }
             } else if (nb[q] >= 0) {
-                const T2 u = f[(size_t)nb[q] * d.nv + k];
+                const size_t nr = (size_t)nb[q] * d.nv + k;
+                const T2 u = f[nr];
                 a1 = (double)u.x;
                 a2 = (double)u.y;
+                if (SO) {
+                    const T2 h1 = G[2 * nr], h2 = G[2 * nr + 1];
+                    a1 += (double)(h1.x * (T)nx[q] + h1.y * (T)ny[q]);
+                    a2 += (double)(h2.x * (T)nx[q] + h2.y * (T)ny[q]);
+                }
             } else if (nb[q] == -1) {
                 const T2 u = fd[k];
                 a1 = (double)u.x;
@@ -326,7 +352,14 @@ __global__ __launch_bounds__(kBlock) void k_mesh_sens_nodes(DevSolve d)
 // ---------------------------------------------------------------------------
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st)
 {
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_wall_sens<T>, dim3(d.nw), dim3(kBlock), 0, st, d, fpar, ppar));
+    if (d.order == 2) {
+        // slopes and dF of the frozen f (the slope buffer holds the adjoint's
+        // B between corrections; B is recomputed at the next one)
+        if (hipError_t e = launch_so_slopes(d, fpar, st)) return e;
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL((k_wall_sens<T, true>), dim3(d.nw), dim3(kBlock), 0, st, d, fpar, ppar));
+    } else {
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL((k_wall_sens<T, false>), dim3(d.nw), dim3(kBlock), 0, st, d, fpar, ppar));
+    }
     if (hipError_t e = hipGetLastError()) return e;
     hipLaunchKernelGGL(k_nodes_params, dim3(1), dim3(kBlock), 0, st, d, n_params);
     return hipGetLastError();

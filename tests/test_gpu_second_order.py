@@ -73,6 +73,11 @@ def _case(name):
     raise KeyError(name)
 
 
+def _sens_err(gs, go):
+    sc = max(np.max(np.abs(go[k])) for k in ("S_A", "S_x", "S_n", "dJ_dnodes"))
+    return max(np.max(np.abs(gs[k] - go[k])) for k in ("S_A", "S_x", "S_n", "dJ_dnodes")) / sc
+
+
 def _run(wl, precision, n_primal, n_adjoint, limiter=True, k=K):
     _say(f"[gpu-so] {wl.name} precision={precision} limiter={limiter} K={k} primal={n_primal} adjoint={n_adjoint}")
     s = dvm.Solver.from_workload(wl, precision=precision, order=2,
@@ -92,6 +97,7 @@ def _run(wl, precision, n_primal, n_adjoint, limiter=True, k=K):
         o.adjoint_init()
         o.adjoint_iterate(n_adjoint)
         res["phi"] = s.state_array(dvm.STATE_PHI)
+        res["sens"] = _sens_err(s.wall_sensitivity(), o.wall_sensitivity())
     return res
 
 
@@ -107,8 +113,8 @@ def test_fp64_second_order_parity(name, limiter):
     o = r["o"]
     ef, eW, ep = _rel(r["f"], o.f), _rel(r["W"], o.W), _rel(r["phi"], o.phi)
     eJ = abs(r["J"] - r["Jo"]) / max(abs(r["Jo"]), 1e-300)
-    _say(f"[fp64-so] {name}: f {ef:.1e} W {eW:.1e} J {eJ:.1e} phi {ep:.1e}")
-    assert ef <= 1e-11 and eW <= 1e-11 and ep <= 1e-11
+    _say(f"[fp64-so] {name}: f {ef:.1e} W {eW:.1e} J {eJ:.1e} phi {ep:.1e} sens {r['sens']:.1e}")
+    assert ef <= 1e-11 and eW <= 1e-11 and ep <= 1e-11 and r["sens"] <= 1e-10
     assert abs(r["J"] - r["Jo"]) <= 1e-10 * abs(r["Jo"]) + 1e-14
 
 
@@ -119,8 +125,8 @@ def test_mixed_second_order_parity(name):
     o = r["o"]
     ef, ep = _rel(r["f"], o.f), _rel(r["phi"], o.phi)
     eJ = abs(r["J"] - r["Jo"]) / abs(r["Jo"])
-    _say(f"[mixed-so] {name}: f {ef:.2e} J {eJ:.2e} phi {ep:.2e}")
-    assert ef <= 5e-5 and eJ <= 5e-5 and ep <= 5e-5
+    _say(f"[mixed-so] {name}: f {ef:.2e} J {eJ:.2e} phi {ep:.2e} sens {r['sens']:.2e}")
+    assert ef <= 5e-5 and eJ <= 5e-5 and ep <= 5e-5 and r["sens"] <= 1e-3
 
 
 def test_c2_naca_second_order_sampled():
@@ -137,6 +143,7 @@ def test_c2_naca_second_order_sampled():
                                       [0, s.nc - 1, 255, 256]]))
     assert _rel(r["f"][cells], o.f[cells]) <= 1e-11
     assert _rel(r["phi"][cells], o.phi[cells]) <= 1e-11
+    assert r["sens"] <= 1e-10
 
 
 def test_second_order_checkpoint_continues_bitwise():
@@ -165,8 +172,17 @@ def test_second_order_argument_and_state_errors():
     s.primal_iterate(6)
     s.adjoint_init()
     s.adjoint_iterate(3)
-    for call in (lambda: s.wall_sensitivity(), lambda: s.mesh_sensitivity(),
-                 lambda: s.param_sensitivity(wl.grid.wall_jac)):
-        with pytest.raises(dvm.DvmError) as e:
-            call()
-        assert e.value.code == dvm.DVM_EINVAL
+    with pytest.raises(dvm.DvmError) as e:
+        s.mesh_sensitivity()
+    assert e.value.code == dvm.DVM_EINVAL
+    # the wall sensitivity reuses the slope buffer; the adjoint continues as
+    # if it had not run (the held term is kept, the slopes are recomputed)
+    t = dvm.Solver.from_workload(wl, order=2)
+    t.primal_init()
+    t.primal_iterate(6)
+    t.adjoint_init()
+    t.adjoint_iterate(3)
+    s.wall_sensitivity()
+    s.adjoint_iterate(9)
+    t.adjoint_iterate(9)
+    assert np.array_equal(s.state_array(dvm.STATE_PHI), t.state_array(dvm.STATE_PHI))

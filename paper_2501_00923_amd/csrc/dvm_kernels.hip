@@ -208,9 +208,17 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
         for (int t = 0; t < nstep; t++) {
             const int k = 2 * (t * kWave + lane);
             if (act && k < nv) {
+                // a face's source row only where it is upwind for either velocity
                 f4 u4[4];
+                {
+                    const T v1a = (T)sm.vx[a], v1b = (T)sm.vx[a + 1], v2 = (T)sm.vy[b];
 #pragma unroll
-                for (int q = 0; q < 4; q++) u4[q] = *reinterpret_cast<const f4 *>(src[q] + k);
+                    for (int q = 0; q < 4; q++) {
+                        u4[q] = f4{0, 0, 0, 0};
+                        if (!(v1a * Sx[q] + v2 * Sy[q] > 0) || !(v1b * Sx[q] + v2 * Sy[q] > 0))
+                            u4[q] = *reinterpret_cast<const f4 *>(src[q] + k);
+                    }
+                }
                 T2 u0[4], u1[4], cr0 = {0, 0}, cr1 = {0, 0};
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
@@ -246,11 +254,20 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
         for (int t = 0; t < nstep; t++) {
             const int k = t * kWave + lane;
             if (act && k < nv) {
-                // the face kind is uniform over the wave, only the sign of
-                // v.S differs between lanes: issue every face's load first
+                // a face's source row only where the face is upwind (the
+                // lanes of a wave split by the sign of v.S): about half the
+                // L2 requests of loading all four (primal 557 -> 511 us on
+                // the 256x128 C-grid with 2304 velocities; the adjoint's
+                // downstream loads gain nothing from the same masking)
                 T2 up[4], cr = {0, 0};
+                {
+                    const T v1 = (T)sm.vx[a], v2 = (T)sm.vy[b];
 #pragma unroll
-                for (int q = 0; q < 4; q++) up[q] = src[q][k];
+                    for (int q = 0; q < 4; q++) {
+                        up[q] = T2{0, 0};
+                        if (!(v1 * Sx[q] + v2 * Sy[q] > 0)) up[q] = src[q][k];
+                    }
+                }
                 if constexpr (SO) cr = corr[row + k];
                 const T2 r = update(a, b, up, cr);
                 // streaming stores: the new row is not read again in this sweep

@@ -441,14 +441,21 @@ def main():
                   "vs_first_order": r2["updates_per_s"] / r64["updates_per_s"],
                   "J": r2["J"], "J_rel_diff_vs_first_order": abs(r2["J"] - r64["J"]) / abs(r64["J"]),
                   "roofline": {}}
+        counted = tr.get("order2_bytes_per_launch", {})   # per kernel, from the counter runs
+        kernels = {"primal": ("k_primal_sweep<double, true>", "k_so_slope<double, false>", "k_so_corr<double>"),
+                   "adjoint": ("k_adjoint_sweep<double, true>", "k_so_adj_b<double>", "k_so_adj_e<double>")}
         for kind in ("primal", "adjoint"):
             t = r2[f"{kind}_sweep_ms"] * 1e-3
             bb = so_bytes_per_update(kind, False, K)
+            ks = kernels[kind]
+            tb = [v for name in ks for k_, v in counted.items() if name in k_]
             second["roofline"][kind] = {
                 "avg_sweep_ms": r2[f"{kind}_sweep_ms"],
                 "note": "sweep plus its share of the correction kernels",
+                "kernels": list(ks),
                 "bytes_per_update": bb, "achieved": bb["per_sweep"] * pairs / t / 1e9,
-                "frac": bb["per_sweep"] * pairs / t / 1e9 / HBM_PEAK_GBS}
+                "frac": bb["per_sweep"] * pairs / t / 1e9 / HBM_PEAK_GBS,
+                "traffic_per_sweep": (tb[0] + (tb[1] + tb[2]) / K) if len(tb) == 3 else None}
         print(f"[bench] second order {r2['updates_per_s']:.3e} upd/s, primal {r2['primal_sweep_ms']:.3f} ms, "
               f"adjoint {r2['adjoint_sweep_ms']:.3f} ms per sweep", file=sys.stderr, flush=True)
     serving = None

@@ -458,6 +458,14 @@ def main():
                 "traffic_per_sweep": (tb[0] + (tb[1] + tb[2]) / K) if len(tb) == 3 else None}
         print(f"[bench] second order {r2['updates_per_s']:.3e} upd/s, primal {r2['primal_sweep_ms']:.3f} ms, "
               f"adjoint {r2['adjoint_sweep_ms']:.3f} ms per sweep", file=sys.stderr, flush=True)
+        if not args.no_mixed:
+            r2m = run_gpu(wl, dvm.MIXED, args.sweeps, args.steps, args.warmup, order=2, correction_every=K)
+            second["mixed"] = {"value": r2m["updates_per_s"], "ms_per_step": r2m["ms_per_step"],
+                               "speedup_vs_fp64": r2m["updates_per_s"] / r2["updates_per_s"],
+                               "primal_sweep_ms": r2m["primal_sweep_ms"], "adjoint_sweep_ms": r2m["adjoint_sweep_ms"],
+                               "J_rel_err_vs_fp64": abs(r2m["J"] - r2["J"]) / abs(r2["J"]),
+                               "dtype": "f32 state / f64 moments and limiter"}
+            print(f"[bench] second order mixed {r2m['updates_per_s']:.3e} upd/s", file=sys.stderr, flush=True)
     serving = None
     if args.serving_requests > 0:
         print(f"[bench] serving leg: {args.serving_requests} requests", file=sys.stderr, flush=True)

@@ -140,7 +140,7 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
  * re-evaluates the correction at the next sweep.  The wall sensitivity
  * (and its chain to shape parameters) evaluates the paper's formulas with
  * the second-order values: reconstructed wall and face values, F_l + dF_l.
- * Batches and the exact mesh sensitivity are first-order only (DVM_EINVAL). */
+ * The exact mesh sensitivity is first-order only (DVM_EINVAL). */
 int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_interval);
 /* Exact device bytes the solver needs (used for admission by footprint). */
 size_t dvm_solver_workspace_bytes(const dvm_solver *s);
@@ -218,9 +218,12 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
  * A batch groups n bound solvers of one precision.  Each member takes part
  * in the phase it is in when the batch is created: primal (after
  * dvm_primal_init) or adjoint (after dvm_adjoint_init).  dvm_batch_run
- * advances every member by `iters` Jacobi sweeps with two kernel launches
- * per sweep (one over the cells of the primal-phase members, one over those
- * of the adjoint-phase members), on the batch's stream.  Each launch gives
+ * advances every member by `iters` Jacobi sweeps with up to four kernel
+ * launches per sweep (over the cells of the primal-phase members of the
+ * first- and of the second-order scheme, then those of the adjoint-phase
+ * members), on the batch's stream; a second-order member's held correction
+ * is re-evaluated before the sweep on its own cadence, with the kernels of
+ * a single solve.  Each launch gives
  * every one of the 8 XCDs one eighth of every member, so a mix of mesh and
  * velocity-grid sizes keeps all XCDs equally loaded.  A member's sweep
  * computes exactly what its own dvm_*_sweeps computes alone (same kernels,

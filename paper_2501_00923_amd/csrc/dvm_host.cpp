@@ -585,7 +585,7 @@ struct dvm_batch {
     char *work = nullptr;
     hipStream_t stream = nullptr;
     int nblocks = 0, mixed = 0;
-    int nb_primal = 0, nb_adjoint = 0;   // blocks of each phase's group (group 0 first)
+    int nb_group[4] = {0, 0, 0, 0};      // blocks of group 2 * phase + (order == 2), in that order
     int step = 0;
     size_t off_tab = 0, off_par = 0, off_phase = 0, off_bs = 0, off_bc = 0, off_out = 0;
 };
@@ -1134,20 +1134,21 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         for (int j = 0; j < i; j++)
             if (solvers[j] == s) return fail(DVM_EINVAL, "solver listed twice");
         if (s->phase < 0) return fail(DVM_ESTATE, "member %d has no primal or adjoint phase", i);
-        if (s->order != 1) return fail(DVM_EINVAL, "member %d: batches run the first-order scheme", i);
         if (mixed < 0) mixed = s->mixed;
         if (mixed != s->mixed) return fail(DVM_EINVAL, "batch members must share one precision");
     }
-    // two groups of workgroups, primal-phase members then adjoint-phase
-    // members, one workgroup per (member, patch). Workgroup b of a group
-    // runs on XCD b % 8, so within a group XCD x takes the x-th eighth (in
-    // sweep order) of every member's patches: each XCD gets the same share
-    // of every member's work, whatever the mix of mesh and velocity-grid
-    // sizes, and its L2 sees contiguous tiles as in a single-solve sweep.
-    int64_t per_phase[2] = {0, 0};
-    for (int i = 0; i < n; i++) per_phase[solvers[i]->phase] += (solvers[i]->np + 7) / 8;
-    const int64_t nbp = 8 * per_phase[0], nba = 8 * per_phase[1];
-    const int64_t nblocks = nbp + nba;
+    // four groups of workgroups -- primal-phase first-order members, primal
+    // second-order, adjoint first-order, adjoint second-order (one kernel
+    // launch each) -- one workgroup per (member, patch). Workgroup b of a
+    // group runs on XCD b % 8, so within a group XCD x takes the x-th eighth
+    // (in sweep order) of every member's patches: each XCD gets the same
+    // share of every member's work, whatever the mix of mesh and
+    // velocity-grid sizes, and its L2 sees contiguous tiles as in a
+    // single-solve sweep.
+    auto group = [](const dvm_solver *s) { return 2 * s->phase + (s->order == 2 ? 1 : 0); };
+    int64_t per_group[4] = {0, 0, 0, 0};
+    for (int i = 0; i < n; i++) per_group[group(solvers[i])] += (solvers[i]->np + 7) / 8;
+    const int64_t nblocks = 8 * (per_group[0] + per_group[1] + per_group[2] + per_group[3]);
     if (nblocks > INT32_MAX) return fail(DVM_EINVAL, "batch too large");
     size_t need;
     try {
@@ -1161,8 +1162,7 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         b->work = static_cast<char *>(work_dev);
         b->stream = static_cast<hipStream_t>(hip_stream);
         b->nblocks = (int)nblocks;
-        b->nb_primal = (int)nbp;
-        b->nb_adjoint = (int)nba;
+        for (int g = 0; g < 4; g++) b->nb_group[g] = (int)(8 * per_group[g]);
         b->mixed = mixed;
         std::vector<dvm::DevSolve> tab(n);
         std::vector<int32_t> par(n), phase(n);
@@ -1173,11 +1173,11 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
         }
         std::vector<int32_t> bs(nblocks, -1), bc(nblocks, 0);
         int64_t base = 0;
-        for (int ph = 0; ph < 2; ph++) {
+        for (int gr = 0; gr < 4; gr++) {
             std::vector<int64_t> pos(8, 0);   // next slot of each XCD
             for (int i = 0; i < n; i++) {
                 const dvm_solver *s = solvers[i];
-                if (s->phase != ph) continue;
+                if (group(s) != gr) continue;
                 const int64_t per = (s->np + 7) / 8;
                 for (int x = 0; x < 8; x++) {
                     const int64_t p0 = x * per, p1 = std::min<int64_t>(s->np, p0 + per);
@@ -1188,7 +1188,7 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
                     }
                 }
             }
-            base += 8 * per_phase[ph];
+            base += 8 * per_group[gr];
         }
         char *w = b->work;
         hipStream_t st = b->stream;
@@ -1223,9 +1223,28 @@ int dvm_batch_run(dvm_batch *b, int iters)
     const auto *bc = reinterpret_cast<const int32_t *>(w + b->off_bc);
     const auto *par = reinterpret_cast<const int32_t *>(w + b->off_par);
     for (int it = 0; it < iters; it++) {
-        HIP_OK(dvm::launch_batch(tab, bs, bc, par, b->step + it, b->nb_primal, b->mixed, 0, b->stream));
-        HIP_OK(dvm::launch_batch(tab, bs + b->nb_primal, bc + b->nb_primal, par, b->step + it, b->nb_adjoint,
-                                 b->mixed, 1, b->stream));
+        // second-order members: the held correction of the current state,
+        // on the same cadence as a single solve's
+        for (dvm_solver *s : b->members) {
+            if (s->order != 2) continue;
+            const int ph = s->phase;
+            if (!s->corr_ok[ph] || s->since[ph] == s->kcorr) {
+                const int cur = (ph == 0 ? s->fpar : s->ppar) ^ (it & 1);
+                if (ph == 0)
+                    HIP_OK(dvm::launch_so_correction(s->dev, cur, b->stream));
+                else
+                    HIP_OK(dvm::launch_so_adjoint_term(s->dev, cur, b->stream));
+                s->corr_ok[ph] = 1;
+                s->since[ph] = 0;
+            }
+            s->since[ph]++;
+        }
+        int off = 0;
+        for (int g = 0; g < 4; g++) {
+            HIP_OK(dvm::launch_batch(tab, bs + off, bc + off, par, b->step + it, b->nb_group[g], b->mixed, g >> 1,
+                                     g & 1, b->stream));
+            off += b->nb_group[g];
+        }
     }
     b->step += iters;
     for (dvm_solver *s : b->members) {

@@ -104,9 +104,10 @@ hipError_t launch_so_objective_elem(const DevSolve &d, int par, hipStream_t st);
 
 // batched: table of DevSolve on the device, per-block (solve, patch) map,
 // per-solve buffer parity at batch creation; step = sweeps done since batch
-// creation; adjoint selects the kernel of that phase
+// creation; adjoint selects the kernel of that phase, so the scheme (the
+// blocks of one launch are members of one phase and one scheme)
 hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_patch,
-                        const int32_t *par0, int step, int nblocks, int mixed, int adjoint, hipStream_t st);
+                        const int32_t *par0, int step, int nblocks, int mixed, int adjoint, int so, hipStream_t st);
 hipError_t launch_batch_residual(const DevSolve *tab, int n, double *out, hipStream_t st);
 
 }  // namespace dvm

@@ -678,10 +678,11 @@ __global__ __launch_bounds__(kPatchBlock) void k_adjoint_sweep(DevSolve d, int p
     adjoint_patch<T, kAdjointExchange<T>, SO>(d, p, par);
 }
 
-// one sweep of the primal-phase (or adjoint-phase) members of a batch; a
-// workgroup owns one (solve, patch).  The two phases are separate kernels
-// so that each gets the occupancy of its own register footprint.
-template <typename T>
+// one sweep of the primal-phase (or adjoint-phase) members of a batch that
+// run one scheme (SO: second order, the held corrections evaluated before
+// the launch); a workgroup owns one (solve, patch).  Phases and schemes are
+// separate kernels so that each gets the occupancy of its own registers.
+template <typename T, bool SO>
 __global__ __launch_bounds__(kPatchBlock) void k_batch_primal(const DevSolve *__restrict__ tab,
                                                               const int32_t *__restrict__ blk_solve,
                                                               const int32_t *__restrict__ blk_patch,
@@ -689,10 +690,10 @@ __global__ __launch_bounds__(kPatchBlock) void k_batch_primal(const DevSolve *__
 {
     const int s = blk_solve[blockIdx.x];
     if (s < 0) return;
-    primal_patch<T, false>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
+    primal_patch<T, SO>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
 }
 
-template <typename T>
+template <typename T, bool SO>
 __global__ __launch_bounds__(kPatchBlock) void k_batch_adjoint(const DevSolve *__restrict__ tab,
                                                                const int32_t *__restrict__ blk_solve,
                                                                const int32_t *__restrict__ blk_patch,
@@ -700,7 +701,7 @@ __global__ __launch_bounds__(kPatchBlock) void k_batch_adjoint(const DevSolve *_
 {
     const int s = blk_solve[blockIdx.x];
     if (s < 0) return;
-    adjoint_patch<T, kAdjointExchange<T>, false>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
+    adjoint_patch<T, kAdjointExchange<T>, SO>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
 }
 
 // f = far-field Maxwellian everywhere (storage type)
@@ -923,15 +924,21 @@ hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st)
 }
 
 hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_patch,
-                        const int32_t *par0, int step, int nblocks, int mixed, int adjoint, hipStream_t st)
+                        const int32_t *par0, int step, int nblocks, int mixed, int adjoint, int so, hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
-    if (adjoint)
-        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_adjoint<T>, dim3(nblocks), dim3(kPatchBlock), 0, st, tab,
-                                               blk_solve, blk_patch, par0, step));
+    if (adjoint && so)
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL((k_batch_adjoint<T, true>), dim3(nblocks), dim3(kPatchBlock), 0, st,
+                                               tab, blk_solve, blk_patch, par0, step));
+    else if (adjoint)
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL((k_batch_adjoint<T, false>), dim3(nblocks), dim3(kPatchBlock), 0, st,
+                                               tab, blk_solve, blk_patch, par0, step));
+    else if (so)
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL((k_batch_primal<T, true>), dim3(nblocks), dim3(kPatchBlock), 0, st,
+                                               tab, blk_solve, blk_patch, par0, step));
     else
-        DVM_DISPATCH(mixed, hipLaunchKernelGGL(k_batch_primal<T>, dim3(nblocks), dim3(kPatchBlock), 0, st, tab,
-                                               blk_solve, blk_patch, par0, step));
+        DVM_DISPATCH(mixed, hipLaunchKernelGGL((k_batch_primal<T, false>), dim3(nblocks), dim3(kPatchBlock), 0, st,
+                                               tab, blk_solve, blk_patch, par0, step));
     return hipGetLastError();
 }
 

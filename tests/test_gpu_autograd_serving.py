@@ -25,9 +25,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _oracle_grad(grid, vg, flow, n_primal, n_adjoint):
+def _oracle_grad(grid, vg, flow, n_primal, n_adjoint, order=1, correction_every=10):
     o = oracle.Problem(grid.topology, grid.ni, grid.nj, grid.n_wake, grid.nodes, vg.kind, vg.n1, vg.n2,
                        vg.vmax, vg.param, flow.Kn, flow.Ma, flow.Tw, flow.objective, nthreads=16)
+    if order == 2:
+        o.set_scheme(2, True, correction_every)
     o.primal_init()
     o.primal_iterate(n_primal)
     J = o.objective()
@@ -56,6 +58,31 @@ def test_autograd_matches_oracle_adjoint_and_offload_is_identical():
     assert J2.item() == J.item()
     assert np.array_equal(alpha2.grad.numpy(), 3.0 * alpha.grad.numpy())
     assert len(rec.checkpoints) == 3 and rec.iters == 300
+
+
+def test_autograd_second_order_matches_oracle_and_offload_is_identical():
+    """The autograd wrapper with the second-order scheme (correction every 5
+    sweeps): J and dJ/dalpha equal the oracle's after the same sweeps; the
+    offloaded backward (f reloaded, correction re-evaluated) is bitwise the
+    same when the checkpoint falls on a multiple of K."""
+    opts = AG.SolveOptions(max_iter=300, adjoint_max_iter=300, fixed_iters=True)
+    case, a0 = AG.circle_fourier_case(16, 8, 8, 5.0, Kn=1.0, Ma=0.5, r_outer=5.0, stretch=1.2, options=opts)
+    case.order, case.correction_every = 2, 5
+    alpha = torch.tensor(a0 + np.array([0.02, -0.01, 0.015, 0.0, 0.0, 0.01, 0.0, 0.0]), requires_grad=True)
+    _say("[gpu] autograd circle 16x8, order 2")
+    J = AG.drag(alpha, case)
+    J.backward()
+    Jo, go = _oracle_grad(case.make_grid(alpha.detach().numpy()), case.vgrid, case.flow, 300, 300,
+                          order=2, correction_every=5)
+    assert abs(J.item() - Jo) <= 1e-10 * abs(Jo)
+    assert np.max(np.abs(alpha.grad.numpy() - go)) <= 1e-10 * np.max(np.abs(go))
+    case.offload = True
+    case.checkpoint_every = 100
+    alpha2 = alpha.detach().clone().requires_grad_(True)
+    J2 = AG.drag(alpha2, case)
+    J2.backward()
+    assert J2.item() == J.item()
+    assert np.array_equal(alpha2.grad.numpy(), alpha.grad.numpy())
 
 
 def test_autograd_fd_agreement_paper_mode():

@@ -71,6 +71,46 @@ def test_batch_alone_vs_mix_bitwise(precision):
     assert np.array_equal(ref.state_save(dvm.STATE_F), extra.state_save(dvm.STATE_F))
 
 
+@pytest.mark.parametrize("precision", [dvm.FP64, dvm.MIXED])
+def test_batch_second_order_members_bitwise(precision):
+    """Second-order members (correction every 3 sweeps, so corrections fall
+    inside batch runs and across their boundaries) next to first-order ones:
+    every member ends bitwise where it ends alone."""
+    _say(f"[gpu] batch with second-order members precision={precision}")
+    orders = [2, 1, 2, 2]
+
+    def make(wl, order):
+        s = dvm.Solver.from_workload(wl, precision=precision, order=order, correction_every=3)
+        s.primal_init()
+        return s
+    alone = []
+    for wl, order in zip(MIX, orders):
+        s = make(wl, order)
+        s.primal_sweeps(8)
+        s.adjoint_init()
+        s.adjoint_sweeps(7)
+        alone.append((s.state_save(dvm.STATE_F), s.state_save(dvm.STATE_PHI), s.objective()))
+    mixed = [make(wl, order) for wl, order in zip(MIX, orders)]
+    mixed[0].primal_sweeps(2)                  # alone first, so it joins mid-cadence
+    b = dvm.Batch(mixed[1:])
+    b.run(2)
+    b.close()
+    b = dvm.Batch(mixed)
+    b.run(1)
+    b.run(5)
+    b.close()
+    for s in mixed:
+        s.adjoint_init()
+    b = dvm.Batch(mixed)
+    b.run(4)
+    b.run(3)
+    b.close()
+    for (f, phi, obj), s in zip(alone, mixed):
+        assert np.array_equal(f, s.state_save(dvm.STATE_F))
+        assert np.array_equal(phi, s.state_save(dvm.STATE_PHI))
+        assert s.objective() == obj
+
+
 def test_batch_residuals_match_single():
     s1 = _solver(MIX[1], dvm.FP64)
     it, r1 = s1.primal_iterate(9)

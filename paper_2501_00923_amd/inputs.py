@@ -418,6 +418,7 @@ class Request:
     arrival: float           # seconds after stream start
     workload: Workload
     want_adjoint: bool
+    order: int = 1           # spatial scheme of the solve: 1, or 2 (second-order reconstruction)
 
 
 def serve_request(rid: int, rng: np.random.Generator, mesh_choices=None, vgrid_choices=None) -> tuple:

@@ -230,7 +230,7 @@ class GpuBackend(Backend):
             wl = req.workload
             s = self.dvm.Solver(self.dvm.Mesh.from_grid(wl.grid), self.dvm.VGrid.from_spec(wl.vgrid), wl.flow.Kn,
                                 wl.flow.Ma, wl.flow.Tw, wl.flow.objective, self.precision, req.want_adjoint,
-                                bind=False)
+                                bind=False, order=getattr(req, "order", 1))
             self._fp_cache[key] = s.workspace_bytes
         return self._fp_cache[key]
 
@@ -238,7 +238,7 @@ class GpuBackend(Backend):
         wl = req.workload
         s = self.dvm.Solver(self.dvm.Mesh.from_grid(wl.grid), self.dvm.VGrid.from_spec(wl.vgrid), wl.flow.Kn,
                             wl.flow.Ma, wl.flow.Tw, wl.flow.objective, self.precision, req.want_adjoint,
-                            stream=self.stream)
+                            stream=self.stream, order=getattr(req, "order", 1))
         s.primal_init()
         return s
 

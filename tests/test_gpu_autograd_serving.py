@@ -146,6 +146,8 @@ def test_server_results_alone_equal_mix(precision):
     reqs = _small_stream(10, 11, 1e6)
     for r in reqs:       # keep the solves short: moderate Kn
         r.workload.flow.Kn = max(r.workload.flow.Kn, 0.3)
+    for r in reqs[::3]:  # some requests ask for the second-order scheme
+        r.order = 2
     cfg = S.ServeConfig(memory_budget=1 << 34, sweeps_per_check=10, tol=1e-4, adjoint_tol=1e-4, max_iter=400)
     _say(f"[gpu] server mix precision={precision}")
     mix = S.serve(reqs, S.GpuBackend(precision), cfg, realtime=False)

@@ -65,7 +65,7 @@ def so_bytes_per_update(kind: str, mixed: bool, k: int) -> dict:
     return {"sweep": sweep, "correction": corr, "per_sweep": sweep + corr / k}
 
 
-def run_gpu(wl, precision, sweeps, steps, warmup, order=1, correction_every=10):
+def run_gpu(wl, precision, sweeps, steps, warmup, order=1, correction_every=40):
     import numpy as np
     import torch
 
@@ -164,13 +164,15 @@ def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every):
             "p99_ratio_fp64_over_mixed": one["p99_ms"] / mix["p99_ms"]}
 
 
-def precision_sweep(sweeps, kns, oracle_check_sweeps=2):
+def precision_sweep(sweeps, kns, oracle_check_sweeps=2, order=1):
     """Mixed precision (FP32 f/phi, FP64 moments and integrals) against the
     FP64 path on the NACA0012 256x128 C-grid with the 64x64 sinh velocity
     grid, Ma 0.5, for each Kn: the same number of primal and adjoint sweeps
     from the free stream on both; errors of J, C_d, the 16 bump
     sensitivities and the cell moments.  The FP64 path is itself checked
-    against the oracle at full size after a few sweeps (first Kn)."""
+    against the oracle at full size after a few sweeps (first Kn).  order 2:
+    the second-order scheme (Venkatakrishnan limiter, correction every 40
+    sweeps) on both paths."""
     import numpy as np
 
     from paper_2501_00923_amd import dvm
@@ -181,7 +183,7 @@ def precision_sweep(sweeps, kns, oracle_check_sweeps=2):
         wl = I.c3_naca_sinh(Kn)
         res = {}
         for prec, name in ((dvm.FP64, "fp64"), (dvm.MIXED, "mixed")):
-            s = dvm.Solver.from_workload(wl, precision=prec)
+            s = dvm.Solver.from_workload(wl, precision=prec, order=order)
             s.primal_init()
             _, rp = s.primal_iterate(sweeps)
             J, Cd = s.objective()
@@ -192,7 +194,7 @@ def precision_sweep(sweeps, kns, oracle_check_sweeps=2):
             res[name] = dict(J=J, Cd=Cd, W=W, g=g, rp=rp, ra=ra)
             del s
         a, b = res["mixed"], res["fp64"]
-        row = {"Kn": Kn, "sweeps": sweeps, "J_fp64": b["J"], "Cd_fp64": b["Cd"],
+        row = {"Kn": Kn, "order": order, "sweeps": sweeps, "J_fp64": b["J"], "Cd_fp64": b["Cd"],
                "primal_resid_fp64": b["rp"], "primal_resid_mixed": a["rp"],
                "adjoint_resid_fp64": b["ra"], "adjoint_resid_mixed": a["ra"],
                "J_rel_err": abs(a["J"] - b["J"]) / abs(b["J"]),
@@ -203,9 +205,11 @@ def precision_sweep(sweeps, kns, oracle_check_sweeps=2):
             import oracle
             nthreads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
             o = oracle.Problem.from_workload(wl, nthreads=nthreads)
+            if order == 2:
+                o.set_scheme(2, True, 40)
             o.primal_init()
             o.primal_iterate(oracle_check_sweeps)
-            s = dvm.Solver.from_workload(wl, precision=dvm.FP64)
+            s = dvm.Solver.from_workload(wl, precision=dvm.FP64, order=order)
             s.primal_init()
             s.primal_iterate(oracle_check_sweeps)
             row["fp64_vs_oracle_J_rel"] = abs(s.objective()[0] - o.objective()) / abs(o.objective())
@@ -225,7 +229,7 @@ def fd_check(h, tol, params=None, order=1):
     (primal f snapshotted every 50 sweeps), in the paper's wall-only form and
     in the exact discrete form, against central differences J(alpha +- h e_p)
     of re-converged primal solves.  order 2: the second-order scheme
-    (Venkatakrishnan limiter, correction every 10 sweeps); the wall-only form
+    (Venkatakrishnan limiter, correction every 40 sweeps); the wall-only form
     only."""
     import numpy as np
     import torch
@@ -337,7 +341,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-second-order", action="store_true",
                     help="skip the second-order leg (Green-Gauss slopes, Venkatakrishnan limiter)")
-    ap.add_argument("--correction-every", type=int, default=10,
+    ap.add_argument("--correction-every", type=int, default=40,
                     help="second-order leg: sweeps between evaluations of the held correction")
     ap.add_argument("--serving-requests", type=int, default=64,
                     help="requests in the solve-server leg (0 skips it; 512 is the full stream)")
@@ -347,6 +351,8 @@ def main():
     ap.add_argument("--precision-sweep", action="store_true",
                     help="print the per-Kn mixed-vs-FP64 error table (256x128 C-grid, 64x64 sinh grid) and exit")
     ap.add_argument("--precision-sweeps", type=int, default=2000)
+    ap.add_argument("--precision-order", type=int, default=1, choices=(1, 2),
+                    help="spatial order of the scheme the --precision-sweep runs")
     ap.add_argument("--fd-check", action="store_true",
                     help="print the adjoint-vs-central-difference table of the 24-parameter B-spline NACA case and exit")
     ap.add_argument("--fd-h", type=float, default=1e-6)
@@ -380,7 +386,7 @@ def main():
         print(f"[bench] calibration copy: {n} bytes read + {n} bytes written", file=sys.stderr, flush=True)
         del src, dst
     if args.precision_sweep:
-        rows = precision_sweep(args.precision_sweeps, [1e-3, 1e-2, 0.1, 1.0, 10.0])
+        rows = precision_sweep(args.precision_sweeps, [1e-3, 1e-2, 0.1, 1.0, 10.0], order=args.precision_order)
         print(json.dumps({"precision_sweep": rows}))
         return
     if args.fd_check:

@@ -131,10 +131,11 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
  * current state and held, and the sweeps between are the first-order Jacobi
  * sweep with that difference moved to the right-hand side; a fixed point
  * solves the second-order balance.  K must be large enough for the
- * first-order sweeps to approximate the first-order inverse: K = 1 is
- * unstable where transport dominates, and K = 5 diverged on C-grids of
- * 192x96 and 256x128 cells where K = 10 and 20 converge (small grids
- * converge with K = 3).  Default K = 10.  The adjoint
+ * first-order sweeps to approximate the first-order inverse, more so the
+ * larger the grid and the Knudsen number: K = 1 is unstable where transport
+ * dominates; on a 256x128 C-grid K = 5 diverged at Kn 0.1 (Ma 0.8), K = 10
+ * at Kn 1 and K = 20 at Kn 10, where K = 40 converges (small grids converge
+ * with K = 3).  Default K = 40.  The adjoint
  * freezes the limiter factors of the converged f (at dvm_adjoint_init) and
  * solves the transpose of that linearisation the same way.  Loading a state
  * re-evaluates the correction at the next sweep.  The wall sensitivity

@@ -137,7 +137,7 @@ class Problem:
         self.ni, self.nj = int(ni), int(nj)
         self.order = 1
 
-    def set_scheme(self, order: int = 2, limiter: bool = True, correction_every: int = 10):
+    def set_scheme(self, order: int = 2, limiter: bool = True, correction_every: int = 40):
         """Spatial order 1 (first-order upwind) or 2 (Green-Gauss slopes with an
         optional Venkatakrishnan limiter, iterated by defect correction with the
         correction re-evaluated every `correction_every` sweeps)."""

@@ -426,7 +426,7 @@ or_problem *or_create(int topo, int ni, int nj, int nwake, const double *nodes,
     p->W = malloc(sizeof(double) * 4 * p->nc);
     p->F = malloc(sizeof(double) * p->nw);
     p->cellred = malloc(sizeof(double) * 2 * p->nc);
-    p->order = 1; p->limiter = 1; p->kcorr = 10;
+    p->order = 1; p->limiter = 1; p->kcorr = 40;
     if (!p->f || !p->fn || !p->phi || !p->phin) return NULL;
     return p;
 }

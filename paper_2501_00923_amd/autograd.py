@@ -49,7 +49,7 @@ class ShapeCase:
     exact: bool = False      # exact discrete derivative (every mesh node moves) instead of the wall-only form
     order: int = 1           # spatial scheme: 1, or 2 (wall-only derivative only)
     limiter: int = dvm.LIMITER_VENKAT
-    correction_every: int = 10
+    correction_every: int = 40
 
 
 @dataclass

@@ -263,7 +263,7 @@ struct dvm_solver {
     std::vector<double> gw2;  // [nv][2]
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // spatial scheme: order 1, or 2 with limiter and K sweeps between corrections
-    int order = 1, limiter = DVM_LIMITER_VENKAT, kcorr = 10;
+    int order = 1, limiter = DVM_LIMITER_VENKAT, kcorr = 40;
     // workspace
     struct {
         size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;

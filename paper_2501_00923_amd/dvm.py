@@ -209,7 +209,7 @@ class Solver:
     def __init__(self, mesh: Mesh, vgrid: VGrid, Kn: float, Ma: float, Tw: float = 1.0,
                  objective: int = OBJ_DRAG, precision: int = FP64, want_adjoint: bool = True,
                  buffer=None, stream=None, bind: bool = True, order: int = 1, limiter: int = LIMITER_VENKAT,
-                 correction_every: int = 10):
+                 correction_every: int = 40):
         fl = _Flow(float(Kn), float(Ma), float(Tw), int(objective))
         h = C.c_void_p()
         _check(lib().dvm_solver_create(mesh._h, vgrid._h, C.byref(fl), precision, 1 if want_adjoint else 0,

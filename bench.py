@@ -51,18 +51,19 @@ def bytes_per_update(kind: str, mixed: bool) -> int:
     return (4 if kind == "primal" else 6) * e
 
 
-def so_bytes_per_update(kind: str, mixed: bool, k: int) -> dict:
+def so_bytes_per_update(kind: str, mixed: bool, corr_per_sweep: float) -> dict:
     """Bytes per (cell, velocity) of the second-order path as built, per
     sweep: the sweep's own row traffic plus the held correction it reads,
-    and the correction kernels' traffic spread over the K sweeps that use
-    it (primal: slopes read f, write G (4 values); correction reads G, writes
-    c.  Adjoint: B reads phi and psi, writes B (4); E reads B, writes E)."""
+    and the correction kernels' traffic times the corrections per sweep
+    (one at the first sweep after init, then one every K sweeps; primal:
+    slopes read f, write G (4 values); correction reads G, writes c.
+    Adjoint: B reads phi and psi, writes B (4); E reads B, writes E)."""
     e = 4 if mixed else 8
     if kind == "primal":
         sweep, corr = 6 * e, (2 + 4) * e + (4 + 2) * e
     else:
         sweep, corr = 8 * e, (2 + 2 + 4) * e + (4 + 2) * e
-    return {"sweep": sweep, "correction": corr, "per_sweep": sweep + corr / k}
+    return {"sweep": sweep, "correction": corr, "per_sweep": sweep + corr * corr_per_sweep}
 
 
 def run_gpu(wl, precision, sweeps, steps, warmup, order=1, correction_every=40):
@@ -450,9 +451,11 @@ def main():
         counted = tr.get("order2_bytes_per_launch", {})   # per kernel, from the counter runs
         kernels = {"primal": ("k_primal_sweep<double, true>", "k_so_slope<double, false>", "k_so_corr<double>"),
                    "adjoint": ("k_adjoint_sweep<double, true>", "k_so_adj_b<double>", "k_so_adj_e<double>")}
+        cps = -(-args.sweeps // K) / args.sweeps     # corrections per sweep in a step from init
+        second["corrections_per_sweep"] = cps
         for kind in ("primal", "adjoint"):
             t = r2[f"{kind}_sweep_ms"] * 1e-3
-            bb = so_bytes_per_update(kind, False, K)
+            bb = so_bytes_per_update(kind, False, cps)
             ks = kernels[kind]
             tb = [v for name in ks for k_, v in counted.items() if name in k_]
             second["roofline"][kind] = {
@@ -461,7 +464,7 @@ def main():
                 "kernels": list(ks),
                 "bytes_per_update": bb, "achieved": bb["per_sweep"] * pairs / t / 1e9,
                 "frac": bb["per_sweep"] * pairs / t / 1e9 / HBM_PEAK_GBS,
-                "traffic_per_sweep": (tb[0] + (tb[1] + tb[2]) / K) if len(tb) == 3 else None}
+                "traffic_per_sweep": (tb[0] + (tb[1] + tb[2]) * cps) if len(tb) == 3 else None}
         print(f"[bench] second order {r2['updates_per_s']:.3e} upd/s, primal {r2['primal_sweep_ms']:.3f} ms, "
               f"adjoint {r2['adjoint_sweep_ms']:.3f} ms per sweep", file=sys.stderr, flush=True)
         if not args.no_mixed:

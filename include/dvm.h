@@ -13,6 +13,9 @@
  *   adjoint solve ................. Sec. 2.5 eq. (formula_adjointbgk), Sec. 3.1 eq. (numerad_gov)
  *   objective ..................... Sec. 3.2 eq. (numer_J)
  *   wall sensitivity .............. Sec. 3.2 eqs. (sens_J_itf), (gaussgrad), (sens_B_itf), (sens_nod)
+ *   volume constraint ............. Sec. 2.4 eq. (formula_opt), Sec. 3.2 eq. (sens_con_nod)
+ *   CST design, initial fit ....... Sec. 3.3 eqs. (cstsuf), (cst_classfunc), (cst_shapefunc), (cstini)
+ *   bulk-mesh deformation ......... Sec. 3.4 Step 2 (RBF, Wendland C0)
  *
  * Discretisation (the paper omits its scheme): first-order upwind finite
  * volume, Jacobi point-implicit iteration; the adjoint is the exact
@@ -249,6 +252,69 @@ void dvm_batch_destroy(dvm_batch *b);
 int dvm_solver_iterations(const dvm_solver *s, int phase);
 /* Current phase: -1 no state, 0 primal, 1 adjoint. */
 int dvm_solver_phase(const dvm_solver *s);
+
+/* ---- outer loop of the optimisation (Sec. 3.3, Sec. 3.4) -------------
+ * CST parameterisation, the volume constraint and the bulk-mesh deformation
+ * that turn a design vector into a mesh for the next solve, and chain the
+ * solve's node sensitivities back to the design vector. */
+#define DVM_CST_MAX_NB 20
+/* CST surface (Sec. 3.3, eqs. cstsuf, cst_classfunc, cst_shapefunc).
+ * alpha[2 nb + 6] = {N1, N2, A_u[0..nb], A_l[0..nb], eta_T,u, eta_T,l},
+ * 1 <= nb <= DVM_CST_MAX_NB, N1 > 0, N2 > 0.  For n stations xi[m] in [0, 1]
+ * (chord-normalised abscissa) on the upper (upper[m] != 0) or lower surface:
+ *   eta[m] = xi^N1 (1 - xi)^N2 sum_b A_b binom(nb, b) xi^b (1 - xi)^(nb - b)
+ *            + xi eta_T
+ * with the A's and eta_T of that surface.  jac (may be NULL) receives
+ * d eta_m / d alpha as jac[m][2 nb + 6].  Host computation. */
+int dvm_cst_eval(int nb, const double *alpha, int n, const double *xi, const int32_t *upper,
+                 double *eta, double *jac);
+/* Initial design (Sec. 3.3, eq. cstini): least-squares fit of the CST
+ * surface to eta[n] at the stations xi[n], over the design variables p with
+ * fixed[p] == 0 (fixed == NULL: all but the two trailing-edge offsets);
+ * fixed variables keep their values from alpha.  Damped Gauss-Newton from
+ * N1 = 0.5, N2 = 1 (where free) with the free A's and eta_T's first fitted
+ * linearly at that class.  alpha[2 nb + 6] is in/out; *rms (may be NULL)
+ * receives sqrt(sum of squared residuals / n).  DVM_EINVAL if the free
+ * variables are not determined by the stations (e.g. n too small). */
+int dvm_cst_fit(int nb, int n, const double *xi, const int32_t *upper, const double *eta,
+                const int32_t *fixed, double *alpha, double *rms);
+/* Volume constraint (Sec. 2.4, eq. formula_opt, D = 2) of the closed wall
+ * loop wall_xy[nw][2] (wall node l starts wall element l, as in a mesh's
+ * row j = 0): Q = (1/2) sum_l A_l n_l . x_l + v_min, n_l the unit normal
+ * into the solid, x_l the element midpoint, so Q = v_min - (area of the
+ * body) for the clockwise walls of dvm_mesh_create.  dQ_dx (may be NULL)
+ * receives dQ/dx[nw][2] by eq. (sens_con_nod): half the sum of A n over the
+ * two elements that share the node. */
+int dvm_volume_constraint(int nw, const double *wall_xy, double v_min, double *Q, double *dQ_dx);
+
+/* Bulk-mesh motion by radial-basis-function interpolation with the
+ * Wendland C0 function (Sec. 3.4, Step 2): phi(r) = (1 - r/R)^2 for r < R,
+ * else 0, R = radius.  Centres c_w are the nw wall nodes of the reference
+ * mesh m (row j = 0; the two copies of the trailing-edge node of a C-grid
+ * and of the periodic column of an O-grid are one centre).  For new wall
+ * positions the weights solve M gamma = (new - c), M[w][v] = phi(|c_w - c_v|);
+ * every other node moves to x0_n + sum_w gamma_w phi(|x0_n - c_w|) from its
+ * reference position x0_n, and wall nodes take the new positions exactly.
+ * The nodes are therefore linear in the wall displacement.  create factors
+ * M (Cholesky, O(nw^3) host work; DVM_EINVAL if M is not positive definite,
+ * e.g. two coincident wall nodes) and copies the reference nodes. */
+typedef struct dvm_deform dvm_deform;
+int dvm_deform_create(const dvm_mesh *m, double radius, dvm_deform **out);
+/* Device bytes the deformer needs; bind a caller-owned buffer (256-byte
+ * aligned, >= that size) and a HIP stream (NULL: default stream) on the
+ * current device, uploading the reference nodes. */
+size_t dvm_deform_workspace_bytes(const dvm_deform *d);
+int dvm_deform_bind(dvm_deform *d, void *dev_ptr, size_t bytes, void *hip_stream);
+/* wall_xy[nw][2] (host) new wall node positions -> nodes_xy (host), every
+ * node of the mesh in dvm_mesh_create's layout.  Synchronises. */
+int dvm_deform_apply(dvm_deform *d, const double *wall_xy, double *nodes_xy);
+/* Transpose: from dJ_dx (host, every node coordinate in dvm_mesh_create's
+ * layout, e.g. dvm_mesh_sensitivity's output) to dJ_dwall[nw][2] (host),
+ * the derivative with respect to the wall node positions through
+ * dvm_deform_apply (the wall nodes' own entries plus the interpolated
+ * motion of all others).  Synchronises. */
+int dvm_deform_chain(dvm_deform *d, const double *dJ_dx, double *dJ_dwall);
+void dvm_deform_destroy(dvm_deform *d);
 
 const char *dvm_last_error(void);
 void dvm_solver_destroy(dvm_solver *s);

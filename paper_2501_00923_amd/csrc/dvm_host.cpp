@@ -593,6 +593,26 @@ struct dvm_batch {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+namespace dvm {
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+MeshNodes mesh_nodes(const dvm_mesh *m)
+{
+    return {m->topo, m->ni, m->nj, m->nwake, m->nw, m->nodes.data()};
+}
+
+}  // namespace dvm
+
 extern "C" {
 
 const char *dvm_last_error(void) { return g_err.c_str(); }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct dvm_mesh;
+
 namespace dvm {
 
 constexpr int kBlock = 256;        // threads per workgroup of the per-cell and per-element kernels
@@ -109,5 +111,29 @@ hipError_t launch_so_objective_elem(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int32_t *blk_patch,
                         const int32_t *par0, int step, int nblocks, int mixed, int adjoint, int so, hipStream_t st);
 hipError_t launch_batch_residual(const DevSolve *tab, int n, double *out, hipStream_t st);
+
+
+// radial-basis-function mesh motion (Wendland C0, support 1/inv_r):
+// apply: out[n] = wall[widx[n]] for wall nodes, else x0[n] + sum_w gamma[w]
+// phi(|x0[n] - c[w]| inv_r); chain: h[w] = sum over non-wall nodes n of
+// phi(|x0[n] - c[w]| inv_r) g[n], via per-chunk partials part[chunk][nw]
+// summed in chunk order.  Points are double2 = (x, y).
+constexpr int kRbfChainNodes = 1024;   // nodes per workgroup of the chain kernel
+constexpr int kRbfTile = 64;           // centres per workgroup of the chain kernel
+inline int rbf_chunks(int nn) { return (nn + kRbfChainNodes - 1) / kRbfChainNodes; }
+hipError_t launch_rbf_apply(const double *x0, const int32_t *widx, int nn, const double *c,
+                            const double *gamma, const double *wall, int nw, double inv_r, double *out,
+                            hipStream_t st);
+hipError_t launch_rbf_chain(const double *x0, const int32_t *widx, const double *g, int nn, const double *c,
+                            int nw, double inv_r, double *part, double *h, hipStream_t st);
+
+// for host sources other than dvm_host.cpp: set the thread's error message
+// (returns code), and the node grid of a mesh
+int set_error(int code, const char *fmt, ...);
+struct MeshNodes {
+    int topo, ni, nj, nwake, nw;
+    const double *nodes;     // [(nj+1)(ni+1)][2]
+};
+MeshNodes mesh_nodes(const dvm_mesh *m);
 
 }  // namespace dvm

@@ -39,6 +39,9 @@ EXPORTED = [
     "dvm_state_bytes", "dvm_state_save", "dvm_state_load",
     "dvm_batch_work_bytes", "dvm_batch_create", "dvm_batch_run", "dvm_batch_residual", "dvm_batch_destroy",
     "dvm_solver_iterations", "dvm_solver_phase", "dvm_last_error", "dvm_solver_destroy",
+    "dvm_cst_eval", "dvm_cst_fit", "dvm_volume_constraint",
+    "dvm_deform_create", "dvm_deform_workspace_bytes", "dvm_deform_bind", "dvm_deform_apply",
+    "dvm_deform_chain", "dvm_deform_destroy",
 ]
 
 
@@ -102,6 +105,15 @@ def lib():
         "dvm_solver_phase": (i32, [vp]),
         "dvm_last_error": (C.c_char_p, []),
         "dvm_solver_destroy": (None, [vp]),
+        "dvm_cst_eval": (i32, [i32, vp, i32, vp, vp, vp, vp]),
+        "dvm_cst_fit": (i32, [i32, i32, vp, vp, vp, vp, vp, pd]),
+        "dvm_volume_constraint": (i32, [i32, vp, d, pd, vp]),
+        "dvm_deform_create": (i32, [vp, d, pvp]),
+        "dvm_deform_workspace_bytes": (sz, [vp]),
+        "dvm_deform_bind": (i32, [vp, vp, sz, vp]),
+        "dvm_deform_apply": (i32, [vp, vp, vp]),
+        "dvm_deform_chain": (i32, [vp, vp, vp]),
+        "dvm_deform_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -1,0 +1,75 @@
+"""Host-side outer-loop calls of libdvm against the oracle (no GPU needed):
+CST evaluation and Jacobian (Sec. 3.3), the least-squares initial design
+(eq. cstini) and the volume constraint with eq. (sens_con_nod)."""
+import numpy as np
+import pytest
+
+from oracle import shape as OS
+from paper_2501_00923_amd import dvm, inputs as I
+from paper_2501_00923_amd import shape as S
+
+NB = 6
+
+
+def _stations(n):
+    q = np.arange(2 * n)
+    lower = q <= n
+    beta = np.where(lower, np.pi * (1 - q / n), np.pi * (q - n) / n)
+    return 0.5 * (1 - np.cos(beta)), ~lower
+
+
+@pytest.mark.parametrize("nb", [1, 6, 12])
+def test_cst_eval_and_jacobian_match_oracle(nb):
+    xi, up = _stations(64)
+    rng = np.random.default_rng(nb)
+    alpha = np.r_[rng.uniform(0.3, 0.8), rng.uniform(0.6, 1.4), rng.uniform(0.05, 0.3, nb + 1),
+                  -rng.uniform(0.05, 0.3, nb + 1), 0.004, -0.003]
+    eta, jac = S.cst_eval(nb, alpha, xi, up, jacobian=True)
+    eo = OS.cst_eta(nb, alpha, xi, up)
+    jo = OS.cst_jacobian(nb, alpha, xi, up)
+    assert np.max(np.abs(eta - eo)) < 1e-15 * 4
+    assert np.max(np.abs(jac - jo)) < 1e-14
+    assert np.array_equal(jac == 0, jo == 0)
+
+
+def test_cst_fit_matches_oracle_on_naca_profiles():
+    for t, n_half in ((0.12, 96), (0.09, 48)):
+        g = I.naca_cgrid(8, n_half, 16, t=t)
+        wall, xi, up = OS.airfoil_stations(g)
+        ao, ro = OS.cst_fit(NB, xi, up, wall[:, 1])
+        a, r = S.cst_fit(NB, xi, up, wall[:, 1])
+        assert abs(r - ro) < 1e-9 * ro
+        assert np.max(np.abs(a - ao)) < 1e-7 * np.max(np.abs(ao))
+        # a fitted design reproduces the wall to the fit's residual
+        assert np.sqrt(np.mean((S.cst_eval(NB, a, xi, up) - wall[:, 1]) ** 2)) == pytest.approx(r, rel=1e-9)
+
+
+def test_cst_fit_with_fixed_variables_and_errors():
+    xi, up = _stations(40)
+    true = np.r_[0.5, 1.0, np.linspace(0.1, 0.2, NB + 1), -np.linspace(0.12, 0.08, NB + 1), 0.0, 0.0]
+    eta = OS.cst_eta(NB, true, xi, up)
+    fixed = np.zeros(OS.n_params(NB), dtype=np.int32)
+    fixed[[0, 1, -2, -1]] = 1
+    a, r = S.cst_fit(NB, xi, up, eta, fixed=fixed, alpha=true * np.r_[1, 1, np.zeros(2 * NB + 2), 1, 1])
+    assert r < 1e-14 and np.max(np.abs(a - true)) < 1e-12
+    with pytest.raises(dvm.DvmError):
+        S.cst_fit(NB, xi[:5], up[:5], eta[:5])          # too few stations
+    with pytest.raises(dvm.DvmError):
+        S.cst_eval(NB, np.r_[0.0, true[1:]], xi, up)     # N1 must be positive
+    with pytest.raises(dvm.DvmError):
+        S.cst_eval(NB, true, xi + 2.0, up)               # stations outside [0, 1]
+    with pytest.raises(dvm.DvmError):
+        S.cst_eval(21, np.ones(2 * 21 + 6), xi, up)       # order above the limit
+
+
+def test_volume_constraint_matches_oracle():
+    g = I.naca_cgrid(8, 48, 16, t=0.12)
+    wall, _, _ = OS.airfoil_stations(g)
+    rng = np.random.default_rng(3)
+    for k in range(3):
+        w = wall + 1e-3 * k * rng.standard_normal(wall.shape)
+        Q, dQ = S.volume_constraint(w, 0.08)
+        Qo, dQo = OS.volume_constraint(w, 0.08)
+        assert abs(Q - Qo) < 1e-15 and np.max(np.abs(dQ - dQo)) < 1e-16
+    with pytest.raises(dvm.DvmError):
+        S.volume_constraint(wall[:2], 0.0)

@@ -65,6 +65,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not built; run paper_2501_00923_amd/build.py (or __graft_entry__.build())")
+    # torch carries its own HIP runtime; bring it up before libdvm's so that
+    # both see the device whichever the caller touches first
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, d, sz = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_size_t
     pvp, pi, pd = C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.POINTER(C.c_double)

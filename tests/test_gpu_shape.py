@@ -1,0 +1,94 @@
+"""GPU parity of the optimisation's outer loop (Sec. 3.4): the RBF mesh
+motion and its transpose against the oracle, the whole SLSQP loop against
+the oracle's loop, and the exact design gradient against finite
+differences of re-converged drags."""
+import numpy as np
+import pytest
+
+from oracle import shape as OS
+from paper_2501_00923_amd import dvm, inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _grids():
+    return [("tiny_c", I.naca_cgrid(4, 12, 8, t=0.12, r_outer=4.0, h1=0.05), 1.0),
+            ("small_c", I.naca_cgrid(4, 24, 10, t=0.12, r_outer=4.0, h1=0.02), 0.5),
+            ("c256x128", I.naca_cgrid(32, 96, 128), 2.0),
+            ("o64x32", I.ogrid(64, 32), 3.0)]
+
+
+@pytest.mark.parametrize("name,g,R", _grids(), ids=[x[0] for x in _grids()])
+def test_deform_apply_and_chain_match_oracle(name, g, R):
+    from paper_2501_00923_amd.shape import Deformer
+    print(f"[deform] {name} R={R}", flush=True)
+    mesh = dvm.Mesh.from_grid(g)
+    D = Deformer(mesh, R)
+    O = OS.RBFDeform(g.nodes, OS.wall_node_index(g.topology, g.ni, g.nj, g.n_wake), R)
+    rng = np.random.default_rng(11)
+    scale = np.max(np.abs(g.nodes))
+    # the weights solve M gamma = d: both sides agree to about cond(M) eps
+    # relative (Cholesky here, LU in the oracle)
+    kappa = np.linalg.cond(O.M) * np.finfo(np.float64).eps
+    for call in range(2):                                     # two calls in a row, different inputs
+        c = O.c
+        if call == 0:                                         # rough: independent normal offsets
+            d = 2e-3 * rng.standard_normal(c.shape)
+        else:                                                 # smooth, as a design change moves a wall
+            d = 5e-4 * np.stack([np.sin(3 * c[:, 0] + 1) * np.cos(2 * c[:, 1]), np.cos(2 * c[:, 0]) + c[:, 1]], 1)
+        wall = c + d
+        x = D.apply(wall)
+        xo = O.apply(wall).reshape(x.shape)
+        assert np.max(np.abs(x - xo)) < 1e-14 * scale + 4 * kappa * np.max(np.abs(d)), call
+        assert np.array_equal(x[0, g.n_wake:g.n_wake + mesh.nw], wall)
+        gvec = rng.standard_normal(x.shape)
+        h = D.chain(gvec)
+        ho = O.chain(gvec)
+        assert np.max(np.abs(h - ho)) < max(1e-13, 4 * kappa) * np.max(np.abs(ho)), call
+    # the moved mesh is a valid mesh
+    dvm.Mesh(g.topology, g.ni, g.nj, g.n_wake, x)
+
+
+def _small_workload(Kn=1.0):
+    g = I.naca_cgrid(4, 24, 10, t=0.12, r_outer=4.0, h1=0.02)
+    return I.Workload("small_naca", g, I.VGridSpec(I.VG_MIDPOINT, 8, 8, 5.0), I.FlowSpec(Kn, 0.5, 1.0), 0)
+
+
+@pytest.mark.parametrize("gradient", ["paper", "exact"])
+def test_optimiser_matches_oracle_loop(gradient):
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+    print(f"[optimise] small_naca gradient={gradient}", flush=True)
+    wl = _small_workload()
+    ro = OS.optimise(wl, radius=1.0, sigma=0.1, max_steps=3, gradient=gradient, solve_tol=1e-12, nthreads=8)
+    opt = ShapeOptimizer(wl, radius=1.0, sigma=0.1, gradient=gradient, solve_tol=1e-12, warm_start=False)
+    r = opt.run(max_steps=3)
+    assert abs(r["v_min"] - ro["v_min"]) < 1e-15
+    assert np.max(np.abs(r["alpha0"] - ro["alpha0"])) < 1e-9
+    assert len(r["history"]) == len(ro["history"]) == 4
+    for e, (ao, Jo, Qo) in zip(r["history"], ro["history"]):
+        assert abs(e.J - Jo) < 1e-9 * abs(Jo)
+        assert np.max(np.abs(e.alpha - ao)) < 1e-7
+        assert abs(e.Q - Qo) < 1e-9 * ro["v_min"]
+    assert r["history"][-1].J < r["history"][0].J
+    # warm-started solves (the default) follow the same path
+    rw = ShapeOptimizer(wl, radius=1.0, sigma=0.1, gradient=gradient, solve_tol=1e-12).run(max_steps=3)
+    for e, f in zip(rw["history"], r["history"]):
+        assert abs(e.J - f.J) < 1e-9 * abs(f.J)
+
+
+def test_exact_design_gradient_matches_finite_differences():
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+    print("[optimise] exact gradient vs FD", flush=True)
+    wl = _small_workload(Kn=0.5)
+    opt = ShapeOptimizer(wl, radius=1.0, gradient="exact", solve_tol=1e-14, warm_start=False)
+    a0 = opt.alpha0
+    dJ = opt.evaluate(a0).dJ
+    nb = opt.nb
+    for p in (0, 1, 2 + 3, nb + 3 + 2):
+        h = 1e-6
+        e = np.zeros_like(a0)
+        e[p] = h
+        Jp = opt.evaluate(a0 + e, gradient=False).J
+        Jm = opt.evaluate(a0 - e, gradient=False).J
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(fd - dJ[p]) < 2e-6 * np.max(np.abs(dJ)), (p, fd, dJ[p])

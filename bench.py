@@ -290,6 +290,61 @@ def fd_check(h, tol, params=None, order=1):
             "rows": rows}
 
 
+def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radius, sigma, order=1):
+    """The optimisation loop of Sec. 3.4 on a NACA0012 C-grid ((2 n_wake +
+    2 n_half) x nj cells), nv x nv Newton-Cotes velocities on [-6, 6]:
+    CST fit (N_B = 6), Wendland-C0 RBF motion, warm-started primal and
+    adjoint solves to `tol`, SLSQP under eq. (cst_constraint) and Q <= 0,
+    stopping by eq. (criterion_opt).  Reports J and Q per step, the time of
+    each stage and the host-inclusive time of one mesh motion and one
+    transpose."""
+    import numpy as np
+
+    from paper_2501_00923_amd import inputs as I
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+
+    g = I.naca_cgrid(n_wake, n_half, nj, t=0.12)
+    wl = I.Workload(f"naca0012_c{g.ni}x{nj}_v{nv}nc_kn{Kn:g}_ma{Ma:g}", g,
+                    I.VGridSpec(I.VG_NEWTON_COTES, nv, nv, 6.0), I.FlowSpec(Kn, Ma, 1.0), 0)
+    opt = ShapeOptimizer(wl, radius=radius, sigma=sigma, gradient=gradient, solve_tol=tol, order=order,
+                         progress=lambda m: print(f"[optimize] {m}", file=sys.stderr, flush=True))
+    print(f"[optimize] {wl.name}: CST fit rms {opt.fit_rms:.2e}, V_min {opt.v_min:.6f}", file=sys.stderr, flush=True)
+    r = opt.run(max_steps=max_steps)
+    hist = r["history"]
+    for k, e in enumerate(hist):
+        print(f"[optimize] step {k}: Cd {e.Cd:.8f}  Q/V_min {e.Q / r['v_min']:+.2e}  N1 {e.alpha[0]:.4f} "
+              f"N2 {e.alpha[1]:.4f}", file=sys.stderr, flush=True)
+    evs = list(opt._cache.values())
+    stages = {k: float(sum(e.times.get(k, 0.0) for e in evs)) for k in ("deform", "setup", "primal", "adjoint", "sens")}
+    sweeps = {"primal": int(sum(e.primal[0] for e in evs)), "adjoint": int(sum(e.adjoint[0] for e in evs))}
+    pairs = g.ni * g.nj * nv * nv
+    # host-inclusive mesh motion and transpose on this grid
+    wall = opt.wall0.copy()
+    gvec = np.ones((g.nj + 1, g.ni + 1, 2))
+    for _ in range(3):
+        opt.deform.apply(wall)
+        opt.deform.chain(gvec)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        opt.deform.apply(wall)
+    t_apply = (time.perf_counter() - t0) / 20
+    t0 = time.perf_counter()
+    for _ in range(20):
+        opt.deform.chain(gvec)
+    t_chain = (time.perf_counter() - t0) / 20
+    return {"workload": wl.name, "order": order, "gradient": gradient, "solve_tol": tol, "radius": radius,
+            "sigma": sigma, "n_params": len(opt.alpha0), "free_params": int(len(opt.free)),
+            "fit_rms": opt.fit_rms, "v_min": r["v_min"], "steps": len(hist) - 1, "stop": r["message"],
+            "evaluations": r["evaluations"], "gradients": int(sum(e.dJ is not None for e in evs)),
+            "Cd": [e.Cd for e in hist], "Q_over_vmin": [e.Q / r["v_min"] for e in hist],
+            "drag_change": hist[-1].Cd / hist[0].Cd - 1.0, "alpha_final": [float(x) for x in hist[-1].alpha],
+            "seconds": r["seconds"], "stage_seconds": stages, "sweeps": sweeps,
+            "solve_updates_per_s": (sweeps["primal"] + sweeps["adjoint"]) * pairs
+            / max(stages["primal"] + stages["adjoint"], 1e-9),
+            "mesh_nodes": (g.ni + 1) * (g.nj + 1), "wall_nodes": opt.deform.nw,
+            "deform_apply_ms": t_apply * 1e3, "deform_chain_ms": t_chain * 1e3}
+
+
 def oracle_rate(wl, seconds, nthreads):
     """Primal then adjoint Jacobi sweeps of the oracle, each for about
     seconds/2: (updates/s, primal sweeps, adjoint sweeps, time)."""
@@ -360,6 +415,17 @@ def main():
     ap.add_argument("--fd-tol", type=float, default=1e-12)
     ap.add_argument("--fd-order", type=int, default=1, choices=(1, 2),
                     help="spatial order of the scheme the --fd-check runs")
+    ap.add_argument("--optimize", action="store_true",
+                    help="run the shape-optimisation loop (CST, RBF mesh motion, SLSQP) instead of the bench")
+    ap.add_argument("--opt-grid", type=str, default="16,48,64", help="n_wake,n_half,nj of the NACA0012 C-grid")
+    ap.add_argument("--opt-nv", type=int, default=32)
+    ap.add_argument("--opt-kn", type=float, default=1.0)
+    ap.add_argument("--opt-ma", type=float, default=0.5)
+    ap.add_argument("--opt-steps", type=int, default=20)
+    ap.add_argument("--opt-gradient", choices=("paper", "exact"), default="paper")
+    ap.add_argument("--opt-tol", type=float, default=1e-9)
+    ap.add_argument("--opt-radius", type=float, default=2.0)
+    ap.add_argument("--opt-sigma", type=float, default=0.1)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -392,6 +458,12 @@ def main():
         return
     if args.fd_check:
         print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol, order=args.fd_order)}))
+        return
+    if args.optimize:
+        nw_, nh_, nj_ = (int(x) for x in args.opt_grid.split(","))
+        print(json.dumps({"optimize": optimize_leg(nw_, nh_, nj_, args.opt_nv, args.opt_kn, args.opt_ma,
+                                                   args.opt_steps, args.opt_gradient, args.opt_tol,
+                                                   args.opt_radius, args.opt_sigma)}))
         return
     wl = I.c2_naca(seed=0)
     print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",

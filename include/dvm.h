@@ -218,6 +218,15 @@ size_t dvm_state_bytes(const dvm_solver *s, int which);
 int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes);
 int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes);
 
+/* Device-to-device copy of a state between two bound solvers of the same
+ * grid size, topology, velocity count and precision (their geometry may
+ * differ: a warm start for the solve of a nearby shape).  DVM_STATE_F:
+ * src's f (its frozen primal solution in the adjoint phase) becomes dst's
+ * f, with its moments and wall fluxes recomputed; dst starts a primal phase.
+ * DVM_STATE_PHI: both in the adjoint phase; src's phi, adjoint moments and
+ * wall multipliers replace dst's.  Synchronises both streams. */
+int dvm_state_copy(dvm_solver *dst, const dvm_solver *src, int which);
+
 /* ---- batched serving --------------------------------------------------
  * A batch groups n bound solvers of one precision.  Each member takes part
  * in the phase it is in when the batch is created: primal (after

@@ -1094,6 +1094,41 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
     return DVM_OK;
 }
 
+int dvm_state_copy(dvm_solver *dst, const dvm_solver *src, int which)
+{
+    if (int e = check_bound(dst)) return e;
+    if (int e = check_bound(src)) return e;
+    if (dst == src) return fail(DVM_EINVAL, "source and destination are the same solver");
+    if (dst->topo != src->topo || dst->ni != src->ni || dst->nj != src->nj || dst->nv != src->nv ||
+        dst->nw != src->nw || dst->mixed != src->mixed || dst->perm != src->perm)
+        return fail(DVM_EINVAL, "solvers differ in grid size, topology, velocity count or precision");
+    if (which != DVM_STATE_F && which != DVM_STATE_PHI) return fail(DVM_EINVAL, "bad state kind %d", which);
+    if (which == DVM_STATE_F && src->phase < 0) return fail(DVM_ESTATE, "source has no primal state");
+    if (which == DVM_STATE_PHI && (src->phase != 1 || dst->phase != 1))
+        return fail(DVM_ESTATE, "copying phi needs both solvers in the adjoint phase");
+    const size_t all = (size_t)dst->nv * 2 * elt_bytes(*dst) * dst->nc;
+    HIP_OK(hipStreamSynchronize(src->stream));
+    if (which == DVM_STATE_F) {
+        const int par = src->phase == 1 ? src->frozen_fpar : src->fpar;
+        dst->fpar = 0;
+        HIP_OK(hipMemcpyAsync(dst->dev.f[0], src->dev.f[par], all, hipMemcpyDeviceToDevice, dst->stream));
+        HIP_OK(dvm::launch_moments(dst->dev, 0, dst->stream));
+        dst->phase = 0;
+        dst->iters[0] = dst->iters[1] = 0;
+        dst->corr_ok[0] = 0;
+    } else {
+        HIP_OK(hipMemcpyAsync(dst->dev.phi[dst->ppar], src->dev.phi[src->ppar], all, hipMemcpyDeviceToDevice,
+                              dst->stream));
+        HIP_OK(hipMemcpyAsync(dst->dev.aW[dst->ppar], src->dev.aW[src->ppar], 8 * sizeof(double) * dst->nc,
+                              hipMemcpyDeviceToDevice, dst->stream));
+        HIP_OK(hipMemcpyAsync(dst->dev.Phi[dst->ppar], src->dev.Phi[src->ppar], sizeof(double) * dst->nw,
+                              hipMemcpyDeviceToDevice, dst->stream));
+        dst->corr_ok[1] = 0;
+    }
+    HIP_OK(hipStreamSynchronize(dst->stream));
+    return DVM_OK;
+}
+
 int dvm_solver_iterations(const dvm_solver *s, int phase)
 {
     if (!s || phase < 0 || phase > 1) return -1;

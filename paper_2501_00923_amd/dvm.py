@@ -36,7 +36,7 @@ EXPORTED = [
     "dvm_primal_init", "dvm_primal_iterate", "dvm_primal_sweeps", "dvm_objective", "dvm_read_moments",
     "dvm_adjoint_init", "dvm_adjoint_iterate", "dvm_adjoint_sweeps",
     "dvm_wall_sensitivity", "dvm_param_sensitivity", "dvm_mesh_sensitivity",
-    "dvm_state_bytes", "dvm_state_save", "dvm_state_load",
+    "dvm_state_bytes", "dvm_state_save", "dvm_state_load", "dvm_state_copy",
     "dvm_batch_work_bytes", "dvm_batch_create", "dvm_batch_run", "dvm_batch_residual", "dvm_batch_destroy",
     "dvm_solver_iterations", "dvm_solver_phase", "dvm_last_error", "dvm_solver_destroy",
     "dvm_cst_eval", "dvm_cst_fit", "dvm_volume_constraint",
@@ -103,6 +103,7 @@ def lib():
         "dvm_state_bytes": (sz, [vp, i32]),
         "dvm_state_save": (i32, [vp, i32, vp, sz]),
         "dvm_state_load": (i32, [vp, i32, vp, sz]),
+        "dvm_state_copy": (i32, [vp, vp, i32]),
         "dvm_batch_work_bytes": (sz, [i32, i64]),
         "dvm_batch_create": (i32, [vp, i32, vp, sz, vp, pvp]),
         "dvm_batch_run": (i32, [vp, i32]),
@@ -333,6 +334,10 @@ class Solver:
     def state_load(self, which: int, blob: np.ndarray):
         blob = np.ascontiguousarray(blob)
         _check(lib().dvm_state_load(self._h, which, blob.ctypes.data, blob.nbytes))
+
+    def state_copy_from(self, src: "Solver", which: int):
+        """Device-to-device copy of src's f or phi into this solver."""
+        _check(lib().dvm_state_copy(self._h, src._h, int(which)))
 
     def iterations(self, phase: int) -> int:
         return int(lib().dvm_solver_iterations(self._h, phase))

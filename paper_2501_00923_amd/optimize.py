@@ -66,6 +66,7 @@ class Evaluation:
     primal: tuple = (0, 0.0)          # (sweeps, last residual)
     adjoint: tuple = (0, 0.0)
     seconds: float = 0.0
+    times: dict = field(default_factory=dict)      # seconds per stage: deform, setup, primal, adjoint, sens
     solver: object = field(default=None, repr=False)
     deta: object = field(default=None, repr=False)     # d eta / d alpha at the wall stations
 
@@ -77,7 +78,7 @@ class _Stop(Exception):
 class ShapeOptimizer:
     def __init__(self, wl, nb: int = 6, radius: float = 2.0, sigma: float = 0.1, gradient: str = "paper",
                  precision: int = dvm.FP64, order: int = 1, solve_tol: float = 1e-10,
-                 max_sweeps: int = 200000, check_every: int = 50, warm_start: bool = True):
+                 max_sweeps: int = 200000, check_every: int = 50, warm_start: bool = True, progress=None):
         if gradient not in ("paper", "exact"):
             raise ValueError("gradient is 'paper' (wall nodes, eq. sens_nod) or 'exact' (mesh sensitivity)")
         if gradient == "exact" and order != 1:
@@ -86,6 +87,7 @@ class ShapeOptimizer:
         self.precision, self.order = precision, order
         self.solve_tol, self.max_sweeps, self.check_every = solve_tol, max_sweeps, check_every
         self.warm_start = warm_start
+        self.progress = progress       # called with a line of text after each solve
         g = wl.grid
         self.grid = g
         self.wall0, self.xi, self.upper = airfoil_wall(g)
@@ -97,20 +99,36 @@ class ShapeOptimizer:
         self.lo, self.hi = cst_bounds(nb)
         self.free = np.nonzero(self.lo < self.hi)[0]
         self._cache = {}
-        self._buffer = None
-        self._last = None          # solver whose f warm-starts the next design
+        # two workspaces used in turn: a new design's solver binds one while
+        # the previous design's solver keeps the other, whose f and phi seed
+        # (device to device) the new solves
+        self._buffers = [None, None]
+        self._slots = [None, None]     # (solver, evaluation) bound to each workspace
+        self._turn = 0
         self.evaluations = 0
 
     # -- Steps 2-4 --------------------------------------------------------
     def _solver(self, nodes):
+        """A solver for these nodes in the workspace not holding the latest
+        design; the evaluation that held that workspace loses its state."""
         g, fl = self.grid, self.wl.flow
         mesh = dvm.Mesh(g.topology, g.ni, g.nj, g.n_wake, nodes)
         s = dvm.Solver(mesh, self.vgrid, fl.Kn, fl.Ma, fl.Tw, fl.objective, self.precision, True,
                        bind=False, order=self.order)
-        if self._buffer is None or self._buffer.numel() < s.workspace_bytes:
-            self._buffer = dvm.alloc_device(s.workspace_bytes)
-        s.bind(self._buffer)
-        return s
+        k = self._turn
+        self._turn ^= 1
+        if self._slots[k] is not None:
+            self._slots[k][1].solver = None
+            self._slots[k] = None
+        if self._buffers[k] is None or self._buffers[k].numel() < s.workspace_bytes:
+            self._buffers[k] = dvm.alloc_device(s.workspace_bytes)
+        s.bind(self._buffers[k])
+        return s, k
+
+    def _latest(self, exclude):
+        """The most recent other design's evaluation that still has its state."""
+        other = self._slots[exclude ^ 1]
+        return None if other is None else other[1]
 
     def evaluate(self, alpha, gradient: bool = True) -> Evaluation:
         alpha = np.array(alpha, dtype=np.float64)
@@ -121,25 +139,27 @@ class ShapeOptimizer:
             eta, deta = cst_eval(self.nb, alpha, self.xi, self.upper, jacobian=True)
             wall = np.stack([self.xi, eta], axis=1)
             nodes = self.deform.apply(wall)                                                 # Step 2
-            warm = self._last.state_save(dvm.STATE_F) if (self.warm_start and self._last is not None) else None
-            # the shared workspace is rebound: the previous solver's state is gone after this
-            if self._last is not None:
-                self._last = None
-                for e in self._cache.values():
-                    e.solver = None
-            s = self._solver(nodes)
-            if warm is not None:
-                s.state_load(dvm.STATE_F, warm)
+            t1 = time.perf_counter()
+            s, k = self._solver(nodes)
+            prev = self._latest(k) if self.warm_start else None
+            if prev is not None:
+                s.state_copy_from(prev.solver, dvm.STATE_F)
             else:
                 s.primal_init()
+            t2 = time.perf_counter()
             ps = s.primal_iterate(self.max_sweeps, self.solve_tol, self.check_every, raise_notconv=False)  # Step 3
             J, Cd = s.objective()
+            t3 = time.perf_counter()
             Q, dQ_dwall = volume_constraint(wall, self.v_min)
             ev = Evaluation(alpha, J, Cd, Q, deta.T @ dQ_dwall[:, 1], primal=ps,
-                            seconds=time.perf_counter() - t0, solver=s, deta=deta)
+                            seconds=time.perf_counter() - t0, solver=s, deta=deta,
+                            times={"deform": t1 - t0, "setup": t2 - t1, "primal": t3 - t2})
             self._cache[key] = ev
-            self._last = s
+            self._slots[k] = (s, ev)
             self.evaluations += 1
+            if self.progress:
+                self.progress(f"design {self.evaluations}: J {J:.10e} Q {Q:+.3e}, primal {ps[0]} sweeps "
+                              f"(r {ps[1]:.1e}), {ev.seconds:.2f} s")
         if gradient and ev.dJ is None:
             t0 = time.perf_counter()
             if ev.solver is None:        # its state was dropped: solve again from the current state
@@ -147,13 +167,22 @@ class ShapeOptimizer:
                 return self.evaluate(alpha, gradient)
             s = ev.solver
             s.adjoint_init()
+            k = 0 if self._slots[0] is not None and self._slots[0][1] is ev else 1
+            prev = self._latest(k) if self.warm_start else None
+            if prev is not None and prev.dJ is not None:
+                s.state_copy_from(prev.solver, dvm.STATE_PHI)
             ev.adjoint = s.adjoint_iterate(self.max_sweeps, self.solve_tol, self.check_every, raise_notconv=False)
+            t1 = time.perf_counter()
             if self.gradient == "paper":                                                     # Step 4
                 dJ_dwall = s.wall_sensitivity()["dJ_dnodes"]
             else:
                 dJ_dwall = self.deform.chain(s.mesh_sensitivity())
             ev.dJ = ev.deta.T @ dJ_dwall[:, 1]
-            ev.seconds += time.perf_counter() - t0
+            t2 = time.perf_counter()
+            ev.times.update(adjoint=t1 - t0, sens=t2 - t1)
+            ev.seconds += t2 - t0
+            if self.progress:
+                self.progress(f"gradient: adjoint {ev.adjoint[0]} sweeps (r {ev.adjoint[1]:.1e}), {t2 - t0:.2f} s")
         return ev
 
     # -- Steps 5-6 --------------------------------------------------------

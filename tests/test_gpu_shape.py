@@ -92,3 +92,46 @@ def test_exact_design_gradient_matches_finite_differences():
         Jm = opt.evaluate(a0 - e, gradient=False).J
         fd = (Jp - Jm) / (2 * h)
         assert abs(fd - dJ[p]) < 2e-6 * np.max(np.abs(dJ)), (p, fd, dJ[p])
+
+
+def test_state_copy_matches_save_and_load():
+    print("[state copy] device-to-device vs host round trip", flush=True)
+    from paper_2501_00923_amd.shape import Deformer
+    wl = _small_workload()
+    g, vg, fl = wl.grid, wl.vgrid, wl.flow
+    mesh = dvm.Mesh.from_grid(g)
+    D = Deformer(mesh, 1.0)
+    wall = g.nodes[0, g.n_wake:g.n_wake + mesh.nw]
+    moved = D.apply(wall + np.stack([np.zeros(mesh.nw), 1e-3 * np.sin(np.pi * wall[:, 0])], 1))
+    V = dvm.VGrid.from_spec(vg)
+
+    def solver(nodes):
+        return dvm.Solver(dvm.Mesh(g.topology, g.ni, g.nj, g.n_wake, nodes), V, fl.Kn, fl.Ma, fl.Tw)
+
+    s1, s2, s3 = solver(g.nodes), solver(moved), solver(moved)
+    s1.primal_init()
+    s1.primal_sweeps(200)
+    s1.adjoint_init()
+    s1.adjoint_sweeps(100)
+    s2.state_copy_from(s1, dvm.STATE_F)
+    s3.state_load(dvm.STATE_F, s1.state_save(dvm.STATE_F))
+    assert np.array_equal(s2.state_save(dvm.STATE_F), s3.state_save(dvm.STATE_F))
+    assert np.array_equal(s2.moments(), s3.moments())
+    for s in (s2, s3):
+        s.primal_sweeps(10)
+        s.adjoint_init()
+    assert np.array_equal(s2.moments(), s3.moments())
+    s2.state_copy_from(s1, dvm.STATE_PHI)
+    s3.state_load(dvm.STATE_PHI, s1.state_save(dvm.STATE_PHI))
+    for s in (s2, s3):
+        s.adjoint_sweeps(10)
+    assert np.array_equal(s2.state_save(dvm.STATE_PHI), s3.state_save(dvm.STATE_PHI))
+    # refused: different grid size; phi into a solver not in the adjoint phase
+    other = dvm.Solver.from_workload(I.tiny_naca())
+    other.primal_init()
+    with pytest.raises(dvm.DvmError):
+        other.state_copy_from(s1, dvm.STATE_F)
+    s4 = solver(moved)
+    s4.primal_init()
+    with pytest.raises(dvm.DvmError):
+        s4.state_copy_from(s1, dvm.STATE_PHI)

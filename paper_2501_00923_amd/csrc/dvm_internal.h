@@ -118,7 +118,7 @@ hipError_t launch_batch_residual(const DevSolve *tab, int n, double *out, hipStr
 // phi(|x0[n] - c[w]| inv_r); chain: h[w] = sum over non-wall nodes n of
 // phi(|x0[n] - c[w]| inv_r) g[n], via per-chunk partials part[chunk][nw]
 // summed in chunk order.  Points are double2 = (x, y).
-constexpr int kRbfChainNodes = 1024;   // nodes per workgroup of the chain kernel
+constexpr int kRbfChainNodes = 256;    // nodes per workgroup of the chain kernel
 constexpr int kRbfTile = 64;           // centres per workgroup of the chain kernel
 inline int rbf_chunks(int nn) { return (nn + kRbfChainNodes - 1) / kRbfChainNodes; }
 hipError_t launch_rbf_apply(const double *x0, const int32_t *widx, int nn, const double *c,

@@ -347,6 +347,56 @@ def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radiu
             "deform_apply_ms": t_apply * 1e3, "deform_chain_ms": t_chain * 1e3}
 
 
+def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius):
+    """Sensitivity of the drag to the CST design variables (the check of
+    Sec. 4.1, here on a NACA0012 C-grid in free stream): at the fitted
+    initial design, dJ/dalpha from the adjoint in the paper's wall-node form
+    (eq. sens_nod) and in the exact discrete form (mesh sensitivity chained
+    through the RBF motion), against central differences J(alpha +- h e_p)
+    of re-converged primal solves, over the free variables."""
+    import numpy as np
+
+    from paper_2501_00923_amd import inputs as I
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+
+    g = I.naca_cgrid(n_wake, n_half, nj, t=0.12)
+    wl = I.Workload(f"naca0012_c{g.ni}x{nj}_v{nv}nc_kn{Kn:g}_ma{Ma:g}", g,
+                    I.VGridSpec(I.VG_NEWTON_COTES, nv, nv, 6.0), I.FlowSpec(Kn, Ma, 1.0), 0)
+    opt = ShapeOptimizer(wl, radius=radius, gradient="exact", solve_tol=tol, check_every=100)
+    a0 = opt.alpha0
+    t0 = time.perf_counter()
+    ev = opt.evaluate(a0)
+    ge = ev.dJ.copy()
+    gp = ev.deta.T @ ev.solver.wall_sensitivity()["dJ_dnodes"][:, 1]
+    t_grad = time.perf_counter() - t0
+    print(f"[cst-fd] {wl.name}: J {ev.J:.12e}, primal {ev.primal[0]} sweeps, adjoint {ev.adjoint[0]} sweeps, "
+          f"{t_grad:.1f} s", file=sys.stderr, flush=True)
+    names = ["N1", "N2"] + [f"A_u{b}" for b in range(opt.nb + 1)] + [f"A_l{b}" for b in range(opt.nb + 1)]
+    rows = []
+    t0 = time.perf_counter()
+    for p in opt.free:
+        e = np.zeros_like(a0)
+        e[p] = h
+        Jp = opt.evaluate(a0 + e, gradient=False).J
+        Jm = opt.evaluate(a0 - e, gradient=False).J
+        fd = (Jp - Jm) / (2 * h)
+        rows.append({"param": names[p], "adjoint_paper": float(gp[p]), "adjoint_exact": float(ge[p]), "fd": fd})
+        print(f"[cst-fd] {names[p]:5s}: paper {gp[p]: .6e}  exact {ge[p]: .10e}  fd {fd: .10e}",
+              file=sys.stderr, flush=True)
+    fv = np.array([r["fd"] for r in rows])
+    scale = float(np.max(np.abs(fv)))
+
+    def stats(v):
+        return {"max_abs_diff_over_max_fd": float(np.max(np.abs(v - fv)) / scale),
+                "median_rel_diff": float(np.median(np.abs(v - fv) / np.maximum(np.abs(fv), 1e-3 * scale))),
+                "cosine": float(v @ fv / (np.linalg.norm(v) * np.linalg.norm(fv)))}
+
+    return {"workload": wl.name, "h": h, "tol": tol, "radius": radius, "J": ev.J, "grad_seconds": t_grad,
+            "fd_seconds": time.perf_counter() - t0,
+            "paper": stats(np.array([r["adjoint_paper"] for r in rows])),
+            "exact": stats(np.array([r["adjoint_exact"] for r in rows])), "rows": rows}
+
+
 def oracle_rate(wl, seconds, nthreads):
     """Primal then adjoint Jacobi sweeps of the oracle, each for about
     seconds/2: (updates/s, primal sweeps, adjoint sweeps, time)."""
@@ -429,6 +479,11 @@ def main():
     ap.add_argument("--opt-radius", type=float, default=2.0)
     ap.add_argument("--opt-sigma", type=float, default=0.1)
     ap.add_argument("--opt-max-sweeps", type=int, default=200000, help="sweep cap per solve")
+    ap.add_argument("--cst-fd-check", action="store_true",
+                    help="drag sensitivity to the CST variables (adjoint, both forms) vs central differences, "
+                         "on the --opt-grid / --opt-nv / --opt-kn / --opt-ma case")
+    ap.add_argument("--cst-fd-h", type=float, default=1e-4)
+    ap.add_argument("--cst-fd-tol", type=float, default=1e-13)
     ap.add_argument("--opt-order", type=int, default=1, choices=(1, 2),
                     help="spatial order of the flow solves (2: Venkatakrishnan limiter, correction every 40 sweeps)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -463,6 +518,11 @@ def main():
         return
     if args.fd_check:
         print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol, order=args.fd_order)}))
+        return
+    if args.cst_fd_check:
+        nw_, nh_, nj_ = (int(x) for x in args.opt_grid.split(","))
+        print(json.dumps({"cst_fd_check": cst_fd_check(nw_, nh_, nj_, args.opt_nv, args.opt_kn, args.opt_ma,
+                                                       args.cst_fd_h, args.cst_fd_tol, args.opt_radius)}))
         return
     if args.optimize:
         nw_, nh_, nj_ = (int(x) for x in args.opt_grid.split(","))

@@ -291,7 +291,7 @@ def fd_check(h, tol, params=None, order=1):
 
 
 def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radius, sigma, order=1,
-                 max_sweeps=200000):
+                 max_sweeps=200000, mixed=False):
     """The optimisation loop of Sec. 3.4 on a NACA0012 C-grid ((2 n_wake +
     2 n_half) x nj cells), nv x nv Newton-Cotes velocities on [-6, 6]:
     CST fit (N_B = 6), Wendland-C0 RBF motion, warm-started primal and
@@ -307,8 +307,9 @@ def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radiu
     g = I.naca_cgrid(n_wake, n_half, nj, t=0.12)
     wl = I.Workload(f"naca0012_c{g.ni}x{nj}_v{nv}nc_kn{Kn:g}_ma{Ma:g}", g,
                     I.VGridSpec(I.VG_NEWTON_COTES, nv, nv, 6.0), I.FlowSpec(Kn, Ma, 1.0), 0)
+    from paper_2501_00923_amd import dvm
     opt = ShapeOptimizer(wl, radius=radius, sigma=sigma, gradient=gradient, solve_tol=tol, order=order,
-                         max_sweeps=max_sweeps, progress=lambda m: print(f"[optimize] {m}", file=sys.stderr, flush=True))
+                         precision=dvm.MIXED if mixed else dvm.FP64, max_sweeps=max_sweeps, progress=lambda m: print(f"[optimize] {m}", file=sys.stderr, flush=True))
     print(f"[optimize] {wl.name}: CST fit rms {opt.fit_rms:.2e}, V_min {opt.v_min:.6f}", file=sys.stderr, flush=True)
     r = opt.run(max_steps=max_steps)
     hist = r["history"]
@@ -333,7 +334,8 @@ def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radiu
     for _ in range(20):
         opt.deform.chain(gvec)
     t_chain = (time.perf_counter() - t0) / 20
-    return {"workload": wl.name, "order": order, "gradient": gradient, "solve_tol": tol, "max_sweeps": max_sweeps,
+    return {"workload": wl.name, "order": order, "precision": "mixed" if mixed else "fp64", "gradient": gradient,
+            "solve_tol": tol, "max_sweeps": max_sweeps,
             "radius": radius,
             "sigma": sigma, "n_params": len(opt.alpha0), "free_params": int(len(opt.free)),
             "fit_rms": opt.fit_rms, "v_min": r["v_min"], "steps": len(hist) - 1, "stop": r["message"],
@@ -479,6 +481,7 @@ def main():
     ap.add_argument("--opt-radius", type=float, default=2.0)
     ap.add_argument("--opt-sigma", type=float, default=0.1)
     ap.add_argument("--opt-max-sweeps", type=int, default=200000, help="sweep cap per solve")
+    ap.add_argument("--opt-mixed", action="store_true", help="FP32 f and phi (FP64 moments, J, sensitivities)")
     ap.add_argument("--cst-fd-check", action="store_true",
                     help="drag sensitivity to the CST variables (adjoint, both forms) vs central differences, "
                          "on the --opt-grid / --opt-nv / --opt-kn / --opt-ma case")
@@ -529,7 +532,7 @@ def main():
         print(json.dumps({"optimize": optimize_leg(nw_, nh_, nj_, args.opt_nv, args.opt_kn, args.opt_ma,
                                                    args.opt_steps, args.opt_gradient, args.opt_tol,
                                                    args.opt_radius, args.opt_sigma, order=args.opt_order,
-                                                   max_sweeps=args.opt_max_sweeps)}))
+                                                   max_sweeps=args.opt_max_sweeps, mixed=args.opt_mixed)}))
         return
     wl = I.c2_naca(seed=0)
     print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",

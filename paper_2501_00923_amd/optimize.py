@@ -220,6 +220,10 @@ class ShapeOptimizer:
             message = r.message
         except _Stop:
             message = "criterion" if abs(hist[-1].J - hist[-2].J) / abs(hist[-2].J) < criterion else "step limit"
+        except dvm.DvmError as e:
+            # a trial design the optimiser proposed moved the mesh into an
+            # invalid one (a cell of non-positive area): stop with what was reached
+            message = f"invalid trial design: {e}"
         return dict(alpha0=a0, fit_rms=self.fit_rms, v_min=self.v_min, history=hist,
                     converged=message == "criterion", message=message, evaluations=self.evaluations,
                     seconds=time.perf_counter() - t0)

@@ -73,3 +73,18 @@ def test_volume_constraint_matches_oracle():
         assert abs(Q - Qo) < 1e-15 and np.max(np.abs(dQ - dQo)) < 1e-16
     with pytest.raises(dvm.DvmError):
         S.volume_constraint(wall[:2], 0.0)
+
+
+def test_airfoil_stations_and_bounds():
+    from paper_2501_00923_amd.optimize import airfoil_wall, cst_bounds
+    g = I.naca_cgrid(8, 48, 16, t=0.12)
+    wall, xi, up = airfoil_wall(g)
+    wo, xo, uo = OS.airfoil_stations(g)
+    assert np.array_equal(wall, wo) and np.array_equal(xi, xo) and np.array_equal(up, uo)
+    assert up.sum() == 47 and not up[0] and not up[48]            # trailing edge, leading edge
+    with pytest.raises(ValueError):
+        airfoil_wall(I.ogrid(16, 8))                               # not an airfoil C-grid
+    lo, hi = cst_bounds(NB)
+    lo_o, hi_o = OS.cst_bounds(NB)
+    assert np.array_equal(lo, lo_o) and np.array_equal(hi, hi_o)
+    assert np.sum(lo < hi) == 2 * NB + 4                           # trailing-edge offsets fixed

@@ -326,14 +326,15 @@ def optimise(wl, nb: int = 6, radius: float = 2.0, sigma: float = 0.01, max_step
         cache[key] = (J, dJ, Q, dQ)
         return cache[key]
 
-    J0 = evaluate(alpha0)[0]
-
     def design(x):
         a = alpha0.copy()
         a[free] = x * sigma
         return a
 
-    hist = [(alpha0.copy(), J0, evaluate(alpha0)[2])]
+    x0 = alpha0[free] / sigma
+    a_start = design(x0)
+    J0, _, Q0, _ = evaluate(a_start)
+    hist = [(a_start, J0, Q0)]
 
     def step_done(x):                                                        # Step 6
         a = design(x)
@@ -352,7 +353,7 @@ def optimise(wl, nb: int = 6, radius: float = 2.0, sigma: float = 0.01, max_step
     bounds = [(None if not np.isfinite(b[0]) else b[0], None if not np.isfinite(b[1]) else b[1]) for b in bounds]
     converged = False
     try:                                                                     # Step 5
-        minimize(fun, alpha0[free] / sigma, jac=jac, method="SLSQP", bounds=bounds,
+        minimize(fun, x0, jac=jac, method="SLSQP", bounds=bounds,
                  constraints=[cons], callback=step_done,
                  options={"maxiter": max_steps + 5, "ftol": 1e-15})
     except _Stop:

@@ -191,14 +191,15 @@ class ShapeOptimizer:
 
         a0, free, sig = self.alpha0, self.free, self.sigma
         t0 = time.perf_counter()
-        e0 = self.evaluate(a0, gradient=True)
-        J0 = e0.J
 
         def design(x):
             a = a0.copy()
             a[free] = np.asarray(x) * sig
             return a
 
+        x0 = a0[free] / sig
+        e0 = self.evaluate(design(x0), gradient=True)     # the design the optimiser starts from, bit for bit
+        J0 = e0.J
         hist = [e0]
 
         def step_done(x):
@@ -215,7 +216,7 @@ class ShapeOptimizer:
                    None if not np.isfinite(self.hi[p]) else self.hi[p] / sig) for p in free]
         message = "iteration limit"
         try:
-            r = minimize(fun, a0[free] / sig, jac=jac, method="SLSQP", bounds=bounds, constraints=[cons],
+            r = minimize(fun, x0, jac=jac, method="SLSQP", bounds=bounds, constraints=[cons],
                          callback=step_done, options={"maxiter": max_steps + 5, "ftol": 1e-15})
             message = r.message
         except _Stop:

@@ -286,9 +286,11 @@ class _Stop(Exception):
 
 def optimise(wl, nb: int = 6, radius: float = 2.0, sigma: float = 0.01, max_steps: int = 20,
              criterion: float = 3e-5, gradient: str = "paper", solve_tol: float = 1e-12,
-             max_sweeps: int = 200000, nthreads=None):
-    """Steps 1-6 of Sec. 3.4 with the oracle solver.  Returns a dict with the
-    initial fit, and per optimisation step the design, J, Q."""
+             max_sweeps: int = 200000, nthreads=None, order: int = 1, correction_every: int = 40):
+    """Steps 1-6 of Sec. 3.4 with the oracle solver (spatial order 1, or 2
+    with the Venkatakrishnan limiter and the given correction interval).
+    Returns a dict with the initial fit, and per optimisation step the
+    design, J, Q."""
     import oracle
     from scipy.optimize import minimize
 
@@ -310,6 +312,8 @@ def optimise(wl, nb: int = 6, radius: float = 2.0, sigma: float = 0.01, max_step
         nodes = deform.apply(wall).reshape(g.nj + 1, g.ni + 1, 2)         # Step 2
         p = oracle.Problem(g.topology, g.ni, g.nj, g.n_wake, nodes, vg.kind, vg.n1, vg.n2,
                            vg.vmax, vg.param, fl.Kn, fl.Ma, fl.Tw, fl.objective, nthreads)
+        if order == 2:
+            p.set_scheme(2, True, correction_every)
         p.primal_init()                                                      # Step 3
         p.primal_solve(solve_tol, max_sweeps, 50)
         J = p.objective()

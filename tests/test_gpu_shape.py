@@ -135,3 +135,21 @@ def test_state_copy_matches_save_and_load():
     s4.primal_init()
     with pytest.raises(dvm.DvmError):
         s4.state_copy_from(s1, dvm.STATE_PHI)
+
+
+def test_second_order_optimiser_matches_oracle_loop():
+    """The loop with the second-order scheme (limited reconstruction,
+    correction every 40 sweeps) and the paper's wall-node gradient with the
+    second-order values; every solve runs to the same sweep cap or
+    tolerance on both sides."""
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+    print("[optimise] small_naca second order", flush=True)
+    wl = _small_workload()
+    ro = OS.optimise(wl, radius=1.0, sigma=0.1, max_steps=3, solve_tol=1e-11, max_sweeps=6000, nthreads=8,
+                     order=2, correction_every=40)
+    opt = ShapeOptimizer(wl, radius=1.0, sigma=0.1, solve_tol=1e-11, max_sweeps=6000, warm_start=False, order=2)
+    r = opt.run(max_steps=3)
+    assert len(r["history"]) == len(ro["history"])
+    for e, (ao, Jo, Qo) in zip(r["history"], ro["history"]):
+        assert abs(e.J - Jo) < 1e-9 * abs(Jo)
+        assert np.max(np.abs(e.alpha - ao)) < 1e-7

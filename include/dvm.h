@@ -305,8 +305,9 @@ int dvm_volume_constraint(int nw, const double *wall_xy, double v_min, double *Q
  * every other node moves to x0_n + sum_w gamma_w phi(|x0_n - c_w|) from its
  * reference position x0_n, and wall nodes take the new positions exactly.
  * The nodes are therefore linear in the wall displacement.  create factors
- * M (Cholesky, O(nw^3) host work; DVM_EINVAL if M is not positive definite,
- * e.g. two coincident wall nodes) and copies the reference nodes. */
+ * M (Cholesky, O(nw^3) host work, nw <= 8192; DVM_EINVAL if M is not
+ * positive definite, e.g. two coincident wall nodes) and copies the
+ * reference nodes. */
 typedef struct dvm_deform dvm_deform;
 int dvm_deform_create(const dvm_mesh *m, double radius, dvm_deform **out);
 /* Device bytes the deformer needs; bind a caller-owned buffer (256-byte

@@ -25,6 +25,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int kMaxCentres = 8192;   // dense host factor: 8192^2 doubles = 512 MiB
 
 // In-place Cholesky factorisation A = L L^T of a symmetric n x n matrix
 // (row-major, lower triangle used); false if A is not positive definite.
@@ -282,6 +283,8 @@ int dvm_deform_create(const dvm_mesh *m, double radius, dvm_deform **out)
     if (!(radius > 0.0) || !std::isfinite(radius)) return set_error(DVM_EINVAL, "support radius %g must be > 0", radius);
     try {
         const dvm::MeshNodes mn = dvm::mesh_nodes(m);
+        if (mn.nw > kMaxCentres)
+            return set_error(DVM_EINVAL, "%d wall nodes: the dense RBF system takes at most %d", mn.nw, kMaxCentres);
         auto *d = new dvm_deform;
         d->nn = (mn.ni + 1) * (mn.nj + 1);
         d->nw = mn.nw;

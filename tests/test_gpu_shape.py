@@ -153,3 +153,19 @@ def test_second_order_optimiser_matches_oracle_loop():
     for e, (ao, Jo, Qo) in zip(r["history"], ro["history"]):
         assert abs(e.J - Jo) < 1e-9 * abs(Jo)
         assert np.max(np.abs(e.alpha - ao)) < 1e-7
+
+
+def test_full_optimisation_matches_oracle():
+    """A whole optimisation, to the 3e-5 stopping test of eq. (criterion_opt),
+    on the library and on the oracle: same number of steps, same optimum."""
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+    print("[optimise] small_naca to the stopping test", flush=True)
+    wl = _small_workload()
+    ro = OS.optimise(wl, radius=1.0, sigma=0.1, max_steps=20, solve_tol=1e-12, nthreads=8)
+    r = ShapeOptimizer(wl, radius=1.0, sigma=0.1, solve_tol=1e-12).run(max_steps=20)
+    assert ro["converged"] and r["converged"]
+    assert len(r["history"]) == len(ro["history"])
+    Jf, Jo = r["history"][-1].J, ro["history"][-1][1]
+    assert abs(Jf - Jo) < 1e-8 * abs(Jo)
+    assert np.max(np.abs(r["history"][-1].alpha - ro["history"][-1][0])) < 1e-5
+    assert Jf < 0.97 * r["history"][0].J

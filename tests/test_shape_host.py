@@ -88,3 +88,25 @@ def test_airfoil_stations_and_bounds():
     lo_o, hi_o = OS.cst_bounds(NB)
     assert np.array_equal(lo, lo_o) and np.array_equal(hi, hi_o)
     assert np.sum(lo < hi) == 2 * NB + 4                           # trailing-edge offsets fixed
+
+
+def test_deformer_argument_and_state_errors():
+    import ctypes as C
+    L = dvm.lib()
+    mesh = dvm.Mesh.from_grid(I.naca_cgrid(4, 12, 8, t=0.12, r_outer=4.0, h1=0.05))
+    h = C.c_void_p()
+    assert L.dvm_deform_create(mesh._h, 0.0, C.byref(h)) == dvm.DVM_EINVAL
+    assert L.dvm_deform_create(mesh._h, float("nan"), C.byref(h)) == dvm.DVM_EINVAL
+    assert L.dvm_deform_create(None, 1.0, C.byref(h)) == dvm.DVM_EINVAL
+    assert L.dvm_deform_create(mesh._h, 1.0, C.byref(h)) == dvm.DVM_OK
+    nn = (mesh.nj + 1) * (mesh.ni + 1)
+    need = L.dvm_deform_workspace_bytes(h)
+    assert need >= 16 * (3 * nn + 3 * mesh.nw)
+    wall = np.zeros((mesh.nw, 2))
+    out = np.zeros((nn, 2))
+    # not bound to a device buffer yet: refused before any device work
+    assert L.dvm_deform_apply(h, wall.ctypes.data, out.ctypes.data) == dvm.DVM_ESTATE
+    assert L.dvm_deform_chain(h, out.ctypes.data, wall.ctypes.data) == dvm.DVM_ESTATE
+    assert L.dvm_deform_bind(h, None, need, None) == dvm.DVM_EINVAL
+    L.dvm_deform_destroy(h)
+    L.dvm_deform_destroy(None)

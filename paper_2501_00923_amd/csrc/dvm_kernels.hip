@@ -204,12 +204,12 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
         const double f1 = (double)r.x, f2 = (double)r.y;
         const double wf1 = wt * f1;
         m0 += wf1;
-        m1 += wf1 * v1d;
-        m2 += wf1 * v2d;
-        m3 += wf1 * (0.5 * (v1d * v1d + v2d * v2d)) + wt * f2;
+        m1 = fma(wf1, v1d, m1);
+        m2 = fma(wf1, v2d, m2);
+        m3 = fma(wf1, 0.5 * fma(v1d, v1d, v2d * v2d), fma(wt, f2, m3));
         if (wl >= 0) {
             const double s0 = v1d * S0x + v2d * S0y;
-            if (s0 > 0) mF += wf1 * s0;
+            if (s0 > 0) mF = fma(wf1, s0, mF);
         }
     };
     if (pair_velocities<T>(n1)) {
@@ -331,12 +331,12 @@ __device__ __forceinline__ void moments_wave(const DevSolve &d, int c, int par)
         const double f1 = (double)r.x, f2 = (double)r.y;
         const double wf1 = wt * f1;
         m0 += wf1;
-        m1 += wf1 * v1d;
-        m2 += wf1 * v2d;
-        m3 += wf1 * (0.5 * (v1d * v1d + v2d * v2d)) + wt * f2;
+        m1 = fma(wf1, v1d, m1);
+        m2 = fma(wf1, v2d, m2);
+        m3 = fma(wf1, 0.5 * fma(v1d, v1d, v2d * v2d), fma(wt, f2, m3));
         if (wl >= 0) {
             const double s0 = v1d * S0x + v2d * S0y;
-            if (s0 > 0) mF += wf1 * s0;
+            if (s0 > 0) mF = fma(wf1, s0, mF);
         }
     };
     const size_t row = (size_t)c * nv;
@@ -445,7 +445,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
     const T VT = uni((T)Vv), den0 = uni((T)(Vv * itau));
     const T Ct0 = uni((T)C0), Ct1 = uni((T)C1), Ct2 = uni((T)C2), Ct3 = uni((T)C3);
     const T gc = uni((T)gcoef), th2 = uni((T)(0.5 * th));
-    const double thw2 = 0.5 * d.theta_w;
+    const double thw2 = 0.5 * d.theta_w, hth = 0.5 * th;
     __syncthreads();
 
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, R = 0, Pw = 0, dn = 0, dd = 0;
@@ -488,22 +488,22 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
         const double p1 = (double)r.x, p2 = (double)r.y;
         const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
         const double g2 = (double)(th2 * (T)g1);
-        const double qq = p1 + 0.5 * th * p2;
+        const double qq = fma(hth, p2, p1);
         const double c1 = v1d - u1, c2 = v2d - u2;
-        const double wg = wt * g1;
-        A0 += wg * qq;
-        A1 += wg * qq * c1;
-        A2 += wg * qq * c2;
-        A3 += wg * qq * (c1 * c1 + c2 * c2);
-        A4 += wg * p2;
-        R += wt * (p1 * (g1 - (double)fs.x) + p2 * (g2 - (double)fs.y));
+        const double wg = wt * g1, wq = wg * qq;
+        A0 += wq;
+        A1 = fma(wq, c1, A1);
+        A2 = fma(wq, c2, A2);
+        A3 = fma(wq, fma(c1, c1, c2 * c2), A3);
+        A4 = fma(wg, p2, A4);
+        R = fma(wt, fma(p1, g1 - (double)fs.x, p2 * (g2 - (double)fs.y)), R);
         if (wl >= 0) {
             const double s0 = v1d * S0x + v2d * S0y;
             if (s0 <= 0) Pw += wt * s0 * (double)gM[k] * ((p1 + mJ_of(obj, v1d, v2d)) + thw2 * p2);
         }
         const double e1 = p1 - (double)old.x, e2 = p2 - (double)old.y;
-        dn += wt * (e1 * e1 + e2 * e2);
-        dd += wt * (p1 * p1 + p2 * p2);
+        dn = fma(wt, fma(e1, e1, e2 * e2), dn);
+        dd = fma(wt, fma(p1, p1, p2 * p2), dd);
     };
     if constexpr (XCH) {
         int a = lane % n1, b = lane / n1;

@@ -399,6 +399,37 @@ def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius):
             "exact": stats(np.array([r["adjoint_exact"] for r in rows])), "rows": rows}
 
 
+def stream_reference(nbytes_total):
+    """Device streaming rates of plain torch elementwise kernels moving about
+    `nbytes_total` bytes per launch in FP64, with the read/write mixes of the
+    sweeps: 2 reads + 1 write (c = a + b: the FP64 adjoint reads phi and f,
+    writes phi) and 1 read + 1 write (c = a: the primal reads f, writes f).
+    GB/s of algorithmic bytes, HIP events over 20 launches after 3 warm-ups."""
+    import torch
+
+    out = {}
+    for name, nin in (("read2_write1", 2), ("read1_write1", 1)):
+        n = int(nbytes_total // (8 * (nin + 1)))
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.ones(n, dtype=torch.float64, device="cuda") if nin == 2 else None
+        c = torch.empty_like(a)
+        run = (lambda: torch.add(a, b, out=c)) if nin == 2 else (lambda: c.copy_(a))
+        for _ in range(3):
+            run()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(20):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 20 * 1e-3
+        out[name] = {"GB_per_s": 8 * n * (nin + 1) / t / 1e9, "bytes_per_launch": 8 * n * (nin + 1)}
+        del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def oracle_rate(wl, seconds, nthreads):
     """Primal then adjoint Jacobi sweeps of the oracle, each for about
     seconds/2: (updates/s, primal sweeps, adjoint sweeps, time)."""
@@ -572,13 +603,22 @@ def main():
                        "frac": b_pri / t_pri / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": r64["primal_sweep_ms"],
                        "algorithmic_bytes_per_launch": b_pri,
                        "traffic": tr.get("primal_fp64_bytes_per_launch")}}
+    # what a plain streaming kernel reaches with the same read/write mix
+    sref = stream_reference(b_adj)
+    roof["stream_reference"] = sref
+    roof["frac_of_stream_reference"] = achieved / sref["read2_write1"]["GB_per_s"]
+    roof["primal"]["frac_of_stream_reference"] = roof["primal"]["achieved"] / sref["read1_write1"]["GB_per_s"]
+    print(f"[bench] stream reference: 2R1W {sref['read2_write1']['GB_per_s']:.0f} GB/s, "
+          f"1R1W {sref['read1_write1']['GB_per_s']:.0f} GB/s", file=sys.stderr, flush=True)
     if mixed is not None:
         for kind, key in (("adjoint", "adjoint_sweep_ms"), ("primal", "primal_sweep_ms")):
             b = bytes_per_update(kind, True) * pairs
             t = mixed[key] * 1e-3
+            ref = sref["read2_write1" if kind == "adjoint" else "read1_write1"]["GB_per_s"]
             roof[f"{kind}_mixed"] = {"kernel": f"k_{kind}_sweep<float>", "achieved": b / t / 1e9,
                                      "frac": b / t / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": mixed[key],
                                      "algorithmic_bytes_per_launch": b,
+                                     "frac_of_stream_reference": b / t / 1e9 / ref,
                                      "traffic": tr.get(f"{kind}_mixed_bytes_per_launch")}
     second = None
     if not args.no_second_order:

@@ -520,6 +520,8 @@ def main():
     ap.add_argument("--cst-fd-tol", type=float, default=1e-13)
     ap.add_argument("--opt-order", type=int, default=1, choices=(1, 2),
                     help="spatial order of the flow solves (2: Venkatakrishnan limiter, correction every 40 sweeps)")
+    ap.add_argument("--no-stream-reference", action="store_true",
+                    help="skip the streaming reference (its own copy and fill would sit beside a calibration copy)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -604,22 +606,24 @@ def main():
                        "algorithmic_bytes_per_launch": b_pri,
                        "traffic": tr.get("primal_fp64_bytes_per_launch")}}
     # what a plain streaming kernel reaches with the same read/write mix
-    sref = stream_reference(b_adj)
-    roof["stream_reference"] = sref
-    roof["frac_of_stream_reference"] = achieved / sref["read2_write1"]["GB_per_s"]
-    roof["primal"]["frac_of_stream_reference"] = roof["primal"]["achieved"] / sref["read1_write1"]["GB_per_s"]
-    print(f"[bench] stream reference: 2R1W {sref['read2_write1']['GB_per_s']:.0f} GB/s, "
-          f"1R1W {sref['read1_write1']['GB_per_s']:.0f} GB/s", file=sys.stderr, flush=True)
+    sref = None if args.no_stream_reference else stream_reference(b_adj)
+    if sref is not None:
+        roof["stream_reference"] = sref
+        roof["frac_of_stream_reference"] = achieved / sref["read2_write1"]["GB_per_s"]
+        roof["primal"]["frac_of_stream_reference"] = roof["primal"]["achieved"] / sref["read1_write1"]["GB_per_s"]
+        print(f"[bench] stream reference: 2R1W {sref['read2_write1']['GB_per_s']:.0f} GB/s, "
+              f"1R1W {sref['read1_write1']['GB_per_s']:.0f} GB/s", file=sys.stderr, flush=True)
     if mixed is not None:
         for kind, key in (("adjoint", "adjoint_sweep_ms"), ("primal", "primal_sweep_ms")):
             b = bytes_per_update(kind, True) * pairs
             t = mixed[key] * 1e-3
-            ref = sref["read2_write1" if kind == "adjoint" else "read1_write1"]["GB_per_s"]
             roof[f"{kind}_mixed"] = {"kernel": f"k_{kind}_sweep<float>", "achieved": b / t / 1e9,
                                      "frac": b / t / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": mixed[key],
                                      "algorithmic_bytes_per_launch": b,
-                                     "frac_of_stream_reference": b / t / 1e9 / ref,
                                      "traffic": tr.get(f"{kind}_mixed_bytes_per_launch")}
+            if sref is not None:
+                ref = sref["read2_write1" if kind == "adjoint" else "read1_write1"]["GB_per_s"]
+                roof[f"{kind}_mixed"]["frac_of_stream_reference"] = b / t / 1e9 / ref
     second = None
     if not args.no_second_order:
         K = args.correction_every

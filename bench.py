@@ -528,7 +528,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE {world}); independent solves would shard one per GPU with no exchange.",
               file=sys.stderr)
         sys.exit(2)

@@ -169,3 +169,19 @@ def test_full_optimisation_matches_oracle():
     assert abs(Jf - Jo) < 1e-8 * abs(Jo)
     assert np.max(np.abs(r["history"][-1].alpha - ro["history"][-1][0])) < 1e-5
     assert Jf < 0.97 * r["history"][0].J
+
+
+def test_mixed_precision_optimiser_follows_fp64():
+    """FP32 f and phi (FP64 moments, J and sensitivities) in every solve of
+    the loop: the same design path as FP64, J within the mixed solves'
+    accuracy."""
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+    print("[optimise] small_naca mixed vs fp64", flush=True)
+    wl = _small_workload()
+    r64 = ShapeOptimizer(wl, radius=1.0, sigma=0.1, solve_tol=1e-7).run(max_steps=3)
+    r32 = ShapeOptimizer(wl, radius=1.0, sigma=0.1, solve_tol=1e-7, precision=dvm.MIXED,
+                         max_sweeps=20000).run(max_steps=3)
+    assert len(r32["history"]) == len(r64["history"])
+    for a, b in zip(r32["history"], r64["history"]):
+        assert abs(a.J - b.J) < 1e-5 * abs(b.J)
+        assert np.max(np.abs(a.alpha - b.alpha)) < 1e-3

@@ -158,3 +158,39 @@ def circle_fourier_case(ni=64, nj=32, nv=16, vmax=5.0, Kn=1.0, Ma=0.5, r_outer=1
         return I.ogrid(ni, nj, r_outer, stretch, alpha[:4], alpha[4:])
     return (ShapeCase(make, I.VGridSpec(I.VG_MIDPOINT, nv, nv, vmax), I.FlowSpec(Kn, Ma), **kw),
             np.zeros(8))
+
+
+def cst_case(wl, nb: int = 6, radius: float = 2.0, **kw) -> tuple:
+    """The optimisation's own parameterisation as a differentiable family:
+    the airfoil of workload `wl` (a C-grid with its leading edge at (0, 0)
+    and trailing edge at (1, 0)) fitted by a CST design (Sec. 3.3, eq.
+    cstini), bodies alpha -> wall nodes (xi_m, eta_CST(xi_m)) and the bulk
+    mesh moved by the Wendland-C0 RBF interpolation (Sec. 3.4, Step 2).
+    d(nodes)/d(alpha) is exact: the motion is linear in the wall
+    displacement, so each column is one motion of the CST Jacobian's
+    column.  Returns (case, alpha0)."""
+    from .optimize import airfoil_wall
+    from .shape import Deformer, cst_eval, cst_fit, n_params
+
+    g0 = wl.grid
+    wall0, xi, upper = airfoil_wall(g0)
+    alpha0, _ = cst_fit(nb, xi, upper, wall0[:, 1])
+    deform = Deformer(dvm.Mesh.from_grid(g0), radius)
+    base = deform.apply(wall0)
+    npar = n_params(nb)
+    names = ["N1", "N2"] + [f"A_u{b}" for b in range(nb + 1)] + [f"A_l{b}" for b in range(nb + 1)] + ["eta_Tu", "eta_Tl"]
+
+    def make(alpha):
+        alpha = np.asarray(alpha, dtype=np.float64)
+        eta, deta = cst_eval(nb, alpha, xi, upper, jacobian=True)
+        nodes = deform.apply(np.stack([xi, eta], axis=1))
+        wall_jac = np.zeros((len(xi), 2, npar))
+        wall_jac[:, 1, :] = deta
+        node_jac = np.zeros(nodes.shape + (npar,))
+        for p in range(npar):
+            if np.any(deta[:, p]):
+                step = np.stack([np.zeros_like(xi), deta[:, p]], axis=1)
+                node_jac[..., p] = deform.apply(wall0 + step) - base
+        return I.GridInput(g0.topology, g0.ni, g0.nj, g0.n_wake, nodes, wall_jac, node_jac, alpha.copy(), names)
+
+    return ShapeCase(make, wl.vgrid, wl.flow, **kw), alpha0

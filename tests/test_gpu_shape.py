@@ -185,3 +185,40 @@ def test_mixed_precision_optimiser_follows_fp64():
     for a, b in zip(r32["history"], r64["history"]):
         assert abs(a.J - b.J) < 1e-5 * abs(b.J)
         assert np.max(np.abs(a.alpha - b.alpha)) < 1e-3
+
+
+@pytest.mark.parametrize("exact", [False, True], ids=["wall_nodes", "exact"])
+def test_autograd_cst_case_matches_oracle(exact):
+    """drag(alpha) over the CST design with the RBF motion: forward J and
+    backward dJ/dalpha against the oracle's solve on the same moved mesh."""
+    import torch
+    from paper_2501_00923_amd import autograd as AG
+    print(f"[autograd] CST case exact={exact}", flush=True)
+    wl = _small_workload()
+    opts = AG.SolveOptions(max_iter=60000, tol=1e-13, adjoint_max_iter=60000, adjoint_tol=1e-13, check_every=50)
+    case, a0 = AG.cst_case(wl, radius=1.0, options=opts, exact=exact)
+    alpha = a0.copy()
+    alpha[2 + 2] += 0.01                                   # a design away from the fit
+    t = torch.tensor(alpha, requires_grad=True)
+    J = AG.drag(t, case)
+    J.backward()
+    g = t.grad.numpy()
+    # oracle on the same design
+    g0 = wl.grid
+    wall0, xi, up = OS.airfoil_stations(g0)
+    D = OS.RBFDeform(g0.nodes, OS.wall_node_index(g0.topology, g0.ni, g0.nj, g0.n_wake), 1.0)
+    eta = OS.cst_eta(6, alpha, xi, up)
+    nodes = D.apply(np.stack([xi, eta], axis=1)).reshape(g0.nj + 1, g0.ni + 1, 2)
+    import oracle
+    vg, fl = wl.vgrid, wl.flow
+    p = oracle.Problem(g0.topology, g0.ni, g0.nj, g0.n_wake, nodes, vg.kind, vg.n1, vg.n2, vg.vmax, vg.param,
+                       fl.Kn, fl.Ma, fl.Tw, fl.objective, 8)
+    p.primal_init()
+    p.primal_solve(1e-13, 60000, 50)
+    Jo = p.objective()
+    p.adjoint_init()
+    p.adjoint_solve(1e-13, 60000, 50)
+    dwall = D.chain(p.mesh_sensitivity()) if exact else p.wall_sensitivity()["dJ_dnodes"]
+    go = OS.cst_jacobian(6, alpha, xi, up).T @ dwall[:, 1]
+    assert abs(J.item() - Jo) < 1e-10 * abs(Jo)
+    assert np.max(np.abs(g - go)) < 1e-8 * np.max(np.abs(go))

@@ -520,6 +520,8 @@ def main():
     ap.add_argument("--cst-fd-tol", type=float, default=1e-13)
     ap.add_argument("--opt-order", type=int, default=1, choices=(1, 2),
                     help="spatial order of the flow solves (2: Venkatakrishnan limiter, correction every 40 sweeps)")
+    ap.add_argument("--no-optimize-leg", action="store_true",
+                    help="skip the short shape optimisation (128x64 C-grid) of the default run")
     ap.add_argument("--no-stream-reference", action="store_true",
                     help="skip the streaming reference (its own copy and fill would sit beside a calibration copy)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -665,6 +667,17 @@ def main():
         print(f"[bench] serving leg: {args.serving_requests} requests", file=sys.stderr, flush=True)
         serving = serving_leg(args.serving_requests, args.serving_seed, args.serving_cap, args.serving_tol,
                               64.0, 20)
+    optimization = None
+    if not args.no_optimize_leg:
+        # a whole optimisation (Sec. 3.4) on a 128x64 NACA0012 C-grid, 32x32 velocities, Kn 1, Ma 0.5
+        print("[bench] optimisation leg", file=sys.stderr, flush=True)
+        o = optimize_leg(16, 48, 64, 32, 1.0, 0.5, 20, "paper", 1e-9, 2.0, 0.1)
+        optimization = {k: o[k] for k in ("workload", "gradient", "steps", "stop", "evaluations", "gradients",
+                                          "seconds", "sweeps", "stage_seconds", "deform_apply_ms",
+                                          "deform_chain_ms")}
+        optimization["Cd_initial"], optimization["Cd_final"] = o["Cd"][0], o["Cd"][-1]
+        optimization["drag_change"] = o["drag_change"]
+        optimization["Q_over_vmin_final"] = o["Q_over_vmin"][-1]
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
@@ -680,7 +693,7 @@ def main():
                    "Kn": wl.flow.Kn, "Ma": wl.flow.Ma, "shape_params": int(wl.grid.wall_jac.shape[-1]),
                    "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "second_order": second, "serving": serving,
-        "J": r64["J"], "Cd": r64["Cd"],
+        "optimization": optimization, "J": r64["J"], "Cd": r64["Cd"],
     }
     print(json.dumps(line))
 

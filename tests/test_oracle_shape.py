@@ -158,3 +158,29 @@ def test_rbf_chain_is_the_transposed_jacobian():
     got = D.chain(gvec).ravel()
     want = Jac.T @ gvec.ravel()
     assert np.max(np.abs(got - want)) < 1e-11 * np.max(np.abs(want))
+
+
+def test_fit_with_free_trailing_edge_offsets():
+    xi, up = _stations(80)
+    rng = np.random.default_rng(8)
+    true = np.r_[0.55, 0.95, rng.uniform(0.1, 0.2, NB + 1), -rng.uniform(0.1, 0.2, NB + 1), 0.004, -0.003]
+    eta = S.cst_eta(NB, true, xi, up)
+    alpha, rms = S.cst_fit(NB, xi, up, eta, fixed=[])
+    assert rms < 1e-12 and np.max(np.abs(alpha - true)) < 1e-7
+
+
+def test_volume_constraint_normals_are_the_meshes_wall_normals():
+    """The (dy, -dx) element vectors of the volume constraint are A_l n_l of
+    the oracle's own mesh (normal into the solid), element by element."""
+    import oracle
+    for g in (I.naca_cgrid(4, 12, 8, t=0.12, r_outer=4.0, h1=0.05), I.ogrid(16, 8)):
+        nw = g.ni - 2 * g.n_wake
+        wall = g.nodes[0, g.n_wake:g.n_wake + nw]
+        p = oracle.Problem(g.topology, g.ni, g.nj, g.n_wake, g.nodes, I.VG_MIDPOINT, 4, 4, 3.0, 0.0, 1.0, 0.5)
+        m = p.mesh()
+        An = m["wall_A"][:, None] * m["wall_n"]
+        Q, dQ = S.volume_constraint(wall, 0.0)
+        # dQ/dx_m = (A n_{m-1} + A n_m) / 2
+        assert np.max(np.abs(dQ - 0.5 * (An + np.roll(An, 1, axis=0)))) < 1e-14
+        # Q = -area of the body: the shoelace area of the clockwise wall
+        assert abs(Q - S.shoelace_area(wall)) < 1e-14 and Q < 0

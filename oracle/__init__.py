@@ -306,9 +306,9 @@ class Problem:
 
     def mesh_sensitivity(self, h: float = 1e-30):
         """dL/dx for every mesh node coordinate, shape (nj+1, ni+1, 2): the
-        exact discrete shape derivative at converged f and phi."""
-        if self.order != 1:
-            raise ValueError("oracle: the mesh sensitivity is implemented for the first-order scheme")
+        exact discrete shape derivative at converged f and phi (order 2:
+        with the limiter factors of f held fixed, exact with the limiter
+        off)."""
         out = np.zeros((self.nj + 1, self.ni + 1, 2))
         lib().or_mesh_sensitivity(self._h, float(h), out)
         return out

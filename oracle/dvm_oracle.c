@@ -61,7 +61,9 @@
  * element-level pins above).  The exact discrete shape derivative
  * (or_mesh_sensitivity, the Lagrangian differentiated in every node
  * coordinate by complex step) is pinned by translation invariance and by
- * central differences of the re-converged drag under shape change.
+ * central differences of the re-converged drag under shape change, for the
+ * first-order scheme and for the second-order one (limiter factors of f held
+ * fixed; exact with the limiter off, a percent-level approximation with it).
  * Second-order scheme (tests/test_oracle_second_order.py): exact slopes and
  * face values for linear fields on equal parallelograms; the limiter's
  * overshoot bound and smoothness; the defect-correction fixed point solves R2 = 0 independently of
@@ -1338,6 +1340,208 @@ static void cell_geometry_z(const or_problem *p, int c, int m, int d, double h, 
     *V = 0.5 * A2;
 }
 
+/* Second-order scheme: complex geometry of cell c with node coordinate
+ * (m, d) shifted by i h -- face vectors, volume, area centroid and face
+ * midpoints, by the formulas the mesh set-up uses. */
+static void cell_geometry2_z(const or_problem *p, int c, int m, int d, double h, double complex S[4][2],
+                             double complex *V, double complex cen[2], double complex fm[4][2])
+{
+    int i = c % p->ni, j = c / p->ni;
+    int cid[4] = { node_id(p, i, j), node_id(p, i + 1, j), node_id(p, i + 1, j + 1), node_id(p, i, j + 1) };
+    double complex X[4], Y[4];
+    for (int q = 0; q < 4; q++) {
+        X[q] = p->nodes[2 * cid[q]] + ((cid[q] == m && d == 0) ? I * h : 0);
+        Y[q] = p->nodes[2 * cid[q] + 1] + ((cid[q] == m && d == 1) ? I * h : 0);
+    }
+    double complex Xr[4], Yr[4], A2 = 0, cx = 0, cy = 0;
+    for (int q = 0; q < 4; q++) { Xr[q] = X[q] - X[0]; Yr[q] = Y[q] - Y[0]; }
+    for (int q = 0; q < 4; q++) {
+        int r = (q + 1) % 4;
+        double complex cr = Xr[q] * Yr[r] - Xr[r] * Yr[q];
+        A2 += cr;
+        cx += (Xr[q] + Xr[r]) * cr;
+        cy += (Yr[q] + Yr[r]) * cr;
+        S[q][0] = Y[r] - Y[q];
+        S[q][1] = -(X[r] - X[q]);
+        fm[q][0] = 0.5 * (X[q] + X[r]);
+        fm[q][1] = 0.5 * (Y[q] + Y[r]);
+    }
+    *V = 0.5 * A2;
+    cen[0] = X[0] + cx / (3.0 * A2);
+    cen[1] = Y[0] + cy / (3.0 * A2);
+}
+
+/* geometry of one cell for the second-order Lagrangian: complex when the
+ * shifted node is one of its corners, else the mesh's own values */
+typedef struct { int c; double complex S[4][2], V, cen[2], fm[4][2]; } so_geo;
+
+static void so_geo_real(const or_problem *p, int c, so_geo *g)
+{
+    g->c = c;
+    for (int q = 0; q < 4; q++) {
+        g->S[q][0] = p->S[8 * c + 2 * q]; g->S[q][1] = p->S[8 * c + 2 * q + 1];
+        g->fm[q][0] = p->fm[8 * c + 2 * q]; g->fm[q][1] = p->fm[8 * c + 2 * q + 1];
+    }
+    g->V = p->vol[c];
+    g->cen[0] = p->cen[2 * c]; g->cen[1] = p->cen[2 * c + 1];
+}
+
+/* limited slopes of cell u at velocity k with the frozen factors psi:
+ * psi_m (1/V) sum_q fbar_q S_q, over the geometry g (complex or real) */
+static void so_grad_z(const or_problem *p, const double *psi, const so_geo *g, int k, double complex G[2][2])
+{
+    const int u = g->c, nv = p->nv;
+    const double *fc = p->f + ((size_t)u * nv + k) * 2;
+    G[0][0] = G[0][1] = G[1][0] = G[1][1] = 0;
+    for (int q = 0; q < 4; q++) {
+        int nb = p->nbr[4 * u + q];
+        double b1 = fc[0], b2 = fc[1];
+        if (nb >= 0) {
+            const double *fj = p->f + ((size_t)nb * nv + k) * 2;
+            b1 = 0.5 * (fc[0] + fj[0]);
+            b2 = 0.5 * (fc[1] + fj[1]);
+        }
+        G[0][0] += b1 * g->S[q][0]; G[0][1] += b1 * g->S[q][1];
+        G[1][0] += b2 * g->S[q][0]; G[1][1] += b2 * g->S[q][1];
+    }
+    const double *ps = psi + ((size_t)u * nv + k) * 2;
+    for (int m = 0; m < 2; m++) { G[m][0] *= ps[m] / g->V; G[m][1] *= ps[m] / g->V; }
+}
+
+/* The second-order Lagrangian differentiated in every node coordinate, with
+ * f, phi and the limiter factors psi of f held fixed.  A node moves the
+ * geometry (face vectors, volume, centroid, face midpoints) of the cells it
+ * is a corner of; through their slopes and centroids it also moves the
+ * reconstructed values their neighbours receive, so the residuals of those
+ * cells and of their neighbours change, and the wall terms (F_l + dF_l, D_l,
+ * J_l) of a wall cell among the first. */
+static void mesh_sensitivity_so(or_problem *p, double h, double *out)
+{
+    const int ni = p->ni, nj = p->nj, nv = p->nv, nc = p->nc, nn = (ni + 1) * (nj + 1);
+    double *G = malloc(sizeof(double) * 4 * (size_t)nc * nv);
+    double *psi = malloc(sizeof(double) * 2 * (size_t)nc * nv);
+    double *dF = malloc(sizeof(double) * (p->nw > 0 ? p->nw : 1));
+    so_slopes(p, p->f, G, psi);
+    so_wall_dF(p, G, dF);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(p->nthreads)
+    for (int m = 0; m < nn; m++) {
+        const int im = m % (ni + 1), jm = m / (ni + 1);
+        int adj[4], na = 0, aff[20], nf = 0;
+        for (int jc = jm - 1; jc <= jm; jc++)
+            for (int ic = im - 1; ic <= im; ic++)
+                if (ic >= 0 && ic < ni && jc >= 0 && jc < nj) adj[na++] = ic + ni * jc;
+        for (int a = 0; a < na; a++) {
+            int cands[5] = { adj[a], p->nbr[4 * adj[a]], p->nbr[4 * adj[a] + 1], p->nbr[4 * adj[a] + 2],
+                             p->nbr[4 * adj[a] + 3] };
+            for (int t = 0; t < 5; t++) {
+                int c = cands[t], seen = 0;
+                if (c < 0) continue;
+                for (int e = 0; e < nf; e++) seen |= aff[e] == c;
+                if (!seen) aff[nf++] = c;
+            }
+        }
+        for (int d = 0; d < 2; d++) {
+            so_geo ga[4];
+            for (int a = 0; a < na; a++) {
+                ga[a].c = adj[a];
+                cell_geometry2_z(p, adj[a], m, d, h, ga[a].S, &ga[a].V, ga[a].cen, ga[a].fm);
+            }
+            double complex L = 0;
+            for (int e = 0; e < nf; e++) {
+                const int c = aff[e];
+                so_geo gr, *gc = NULL;
+                for (int a = 0; a < na; a++) if (adj[a] == c) gc = &ga[a];
+                if (!gc) { so_geo_real(p, c, &gr); gc = &gr; }
+                /* geometry of each upwind neighbour */
+                so_geo gn_real[4];
+                const so_geo *gn[4] = { NULL, NULL, NULL, NULL };
+                for (int q = 0; q < 4; q++) {
+                    int nb = p->nbr[4 * c + q];
+                    if (nb < 0) continue;
+                    for (int a = 0; a < na; a++) if (adj[a] == nb) gn[q] = &ga[a];
+                    if (!gn[q]) { so_geo_real(p, nb, &gn_real[q]); gn[q] = &gn_real[q]; }
+                }
+                const double *fc = p->f + (size_t)c * nv * 2;
+                const double *pc = p->phi + (size_t)c * nv * 2;
+                const int nb0 = p->nbr[4 * c];
+                const int l = nb0 <= -2 ? -2 - nb0 : -1;
+                /* wall: F_l + dF_l, D_l with this cell's normal; J_l */
+                double complex Fw = 0, Dw = 0, A = 0, n1 = 0, n2 = 0;
+                if (l >= 0) {
+                    A = csqrt(gc->S[0][0] * gc->S[0][0] + gc->S[0][1] * gc->S[0][1]);
+                    n1 = gc->S[0][0] / A;
+                    n2 = gc->S[0][1] / A;
+                    for (int k = 0; k < nv; k++) {
+                        double complex vn = p->v[2 * k] * n1 + p->v[2 * k + 1] * n2;
+                        if (creal(vn) > 0) {
+                            double complex Gk[2][2];
+                            so_grad_z(p, psi, gc, k, Gk);
+                            double complex f1 = fc[2 * k] + Gk[0][0] * (gc->fm[0][0] - gc->cen[0])
+                                                          + Gk[0][1] * (gc->fm[0][1] - gc->cen[1]);
+                            Fw += p->w[k] * vn * f1;
+                        } else {
+                            Dw -= p->w[k] * vn * p->gM[k];
+                        }
+                    }
+                    for (int k = 0; k < nv; k++) {
+                        double complex vn = p->v[2 * k] * n1 + p->v[2 * k + 1] * n2, f1;
+                        if (creal(vn) > 0) {
+                            double complex Gk[2][2];
+                            so_grad_z(p, psi, gc, k, Gk);
+                            f1 = fc[2 * k] + Gk[0][0] * (gc->fm[0][0] - gc->cen[0]) + Gk[0][1] * (gc->fm[0][1] - gc->cen[1]);
+                        } else {
+                            f1 = Fw * p->gM[k] / Dw;
+                        }
+                        L += A * p->w[k] * p->mJ[k] * vn * f1;
+                    }
+                }
+                double rho, u1, u2, th;
+                prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+                const double itau = inv_tau_of(p, rho, th);
+                for (int k = 0; k < nv; k++) {
+                    const double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+                    double complex Gc[2][2];
+                    so_grad_z(p, psi, gc, k, Gc);
+                    double complex r1 = 0, r2 = 0;
+                    for (int q = 0; q < 4; q++) {
+                        double complex sq = v1 * gc->S[q][0] + v2 * gc->S[q][1];
+                        double complex a1, a2;
+                        int nb = p->nbr[4 * c + q];
+                        if (creal(sq) > 0) {
+                            double complex rx = gc->fm[q][0] - gc->cen[0], ry = gc->fm[q][1] - gc->cen[1];
+                            a1 = fc[2 * k] + Gc[0][0] * rx + Gc[0][1] * ry;
+                            a2 = fc[2 * k + 1] + Gc[1][0] * rx + Gc[1][1] * ry;
+                        } else if (nb >= 0) {
+                            double complex Gn[2][2];
+                            so_grad_z(p, psi, gn[q], k, Gn);
+                            double complex rx = gc->fm[q][0] - gn[q]->cen[0], ry = gc->fm[q][1] - gn[q]->cen[1];
+                            const double *fj = p->f + ((size_t)nb * nv + k) * 2;
+                            a1 = fj[0] + Gn[0][0] * rx + Gn[0][1] * ry;
+                            a2 = fj[1] + Gn[1][0] * rx + Gn[1][1] * ry;
+                        } else if (nb == -1) {
+                            a1 = p->fd[2 * k];
+                            a2 = p->fd[2 * k + 1];
+                        } else {
+                            a1 = (l >= 0 && gc != &gr ? Fw / Dw : (p->F[l] + dF[l]) / p->D[l]) * p->gM[k];
+                            a2 = 0.5 * p->theta_w * a1;
+                        }
+                        r1 += sq * a1;
+                        r2 += sq * a2;
+                    }
+                    const double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+                    r1 += gc->V * itau * (fc[2 * k] - g1);
+                    r2 += gc->V * itau * (fc[2 * k + 1] - 0.5 * th * g1);
+                    L += p->w[k] * (pc[2 * k] * r1 + pc[2 * k + 1] * r2);
+                }
+            }
+            out[2 * m + d] = cimag(L) / h;
+        }
+    }
+    free(G);
+    free(psi);
+    free(dF);
+}
+
 /* d/dx of the discrete Lagrangian L = J + sum_{c,k} w_k phi_{c,k} . R_{c,k}
  * (as in or_adjoint_dJdp) for every node coordinate x, with f and phi held
  * fixed.  When f solves the primal equations and phi the adjoint equations
@@ -1350,6 +1554,10 @@ static void cell_geometry_z(const or_problem *p, int c, int m, int d, double h, 
  * [(nj+1)(ni+1)][2] entries in the node numbering of the mesh. */
 void or_mesh_sensitivity(or_problem *p, double h, double *out)
 {
+    if (p->order == 2) {
+        mesh_sensitivity_so(p, h, out);
+        return;
+    }
     const int ni = p->ni, nj = p->nj, nv = p->nv, nn = (ni + 1) * (nj + 1);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(p->nthreads)
     for (int m = 0; m < nn; m++) {

@@ -144,7 +144,8 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
  * re-evaluates the correction at the next sweep.  The wall sensitivity
  * (and its chain to shape parameters) evaluates the paper's formulas with
  * the second-order values: reconstructed wall and face values, F_l + dF_l.
- * The exact mesh sensitivity is first-order only (DVM_EINVAL). */
+ * The exact mesh sensitivity differentiates the second-order balance with
+ * the limiter factors of f held fixed (exact with DVM_LIMITER_NONE). */
 int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_interval);
 /* Exact device bytes the solver needs (used for admission by footprint). */
 size_t dvm_solver_workspace_bytes(const dvm_solver *s);
@@ -204,7 +205,11 @@ int dvm_param_sensitivity(dvm_solver *s, int n_params, const double *wall_jac, d
  * volume-mesh terms that the wall-only form (dvm_wall_sensitivity) leaves
  * out; chain it through the caller's d(nodes)/d(alpha).  The two copies of
  * a periodic O-grid column (i = 0 and i = ni) are separate entries.
- * Requires the adjoint phase (DVM_ESTATE otherwise).  Synchronises. */
+ * Second-order scheme: the slopes, centroids and face midpoints move with
+ * the nodes too; the limiter factors of f are held fixed, so the result is
+ * the exact derivative with DVM_LIMITER_NONE and the frozen-limiter one
+ * otherwise.  Requires the adjoint phase (DVM_ESTATE otherwise).
+ * Synchronises. */
 int dvm_mesh_sensitivity(dvm_solver *s, double *dJ_dx);
 
 /* Checkpoint / restore as raw bytes, cells in mesh order (c = i + ni*j)

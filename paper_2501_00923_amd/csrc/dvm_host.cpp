@@ -964,12 +964,6 @@ static int run_sens(dvm_solver *s, int n_params)
     return DVM_OK;
 }
 
-static int first_order_only(const dvm_solver *s, const char *what)
-{
-    if (s->order != 1) return fail(DVM_EINVAL, "%s is implemented for the first-order scheme", what);
-    return DVM_OK;
-}
-
 int dvm_wall_sensitivity(dvm_solver *s, double *S_A, double *S_x, double *S_n, double *dJ_dnodes)
 {
     if (int e = check_bound(s)) return e;
@@ -1015,7 +1009,6 @@ int dvm_mesh_sensitivity(dvm_solver *s, double *dJ_dx)
 {
     if (int e = check_bound(s)) return e;
     if (s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
-    if (int e = first_order_only(s, "the mesh sensitivity")) return e;
     if (!dJ_dx) return fail(DVM_EINVAL, "null output");
     HIP_OK(dvm::launch_mesh_sens(s->dev, s->frozen_fpar, s->ppar, s->stream));
     return read_back(*s, s->dev.dJdx, dJ_dx, 2 * (size_t)(s->ni + 1) * (s->nj + 1));

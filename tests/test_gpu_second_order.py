@@ -98,6 +98,7 @@ def _run(wl, precision, n_primal, n_adjoint, limiter=True, k=K):
         o.adjoint_iterate(n_adjoint)
         res["phi"] = s.state_array(dvm.STATE_PHI)
         res["sens"] = _sens_err(s.wall_sensitivity(), o.wall_sensitivity())
+        res["msens"] = _rel(s.mesh_sensitivity(), o.mesh_sensitivity())
     return res
 
 
@@ -113,8 +114,9 @@ def test_fp64_second_order_parity(name, limiter):
     o = r["o"]
     ef, eW, ep = _rel(r["f"], o.f), _rel(r["W"], o.W), _rel(r["phi"], o.phi)
     eJ = abs(r["J"] - r["Jo"]) / max(abs(r["Jo"]), 1e-300)
-    _say(f"[fp64-so] {name}: f {ef:.1e} W {eW:.1e} J {eJ:.1e} phi {ep:.1e} sens {r['sens']:.1e}")
-    assert ef <= 1e-11 and eW <= 1e-11 and ep <= 1e-11 and r["sens"] <= 1e-10
+    _say(f"[fp64-so] {name}: f {ef:.1e} W {eW:.1e} J {eJ:.1e} phi {ep:.1e} sens {r['sens']:.1e} "
+         f"mesh sens {r['msens']:.1e}")
+    assert ef <= 1e-11 and eW <= 1e-11 and ep <= 1e-11 and r["sens"] <= 1e-10 and r["msens"] <= 1e-10
     assert abs(r["J"] - r["Jo"]) <= 1e-10 * abs(r["Jo"]) + 1e-14
 
 
@@ -125,8 +127,8 @@ def test_mixed_second_order_parity(name):
     o = r["o"]
     ef, ep = _rel(r["f"], o.f), _rel(r["phi"], o.phi)
     eJ = abs(r["J"] - r["Jo"]) / abs(r["Jo"])
-    _say(f"[mixed-so] {name}: f {ef:.2e} J {eJ:.2e} phi {ep:.2e} sens {r['sens']:.2e}")
-    assert ef <= 5e-5 and eJ <= 5e-5 and ep <= 5e-5 and r["sens"] <= 1e-3
+    _say(f"[mixed-so] {name}: f {ef:.2e} J {eJ:.2e} phi {ep:.2e} sens {r['sens']:.2e} mesh sens {r['msens']:.2e}")
+    assert ef <= 5e-5 and eJ <= 5e-5 and ep <= 5e-5 and r["sens"] <= 1e-3 and r["msens"] <= 1e-3
 
 
 def test_c2_naca_second_order_sampled():
@@ -172,11 +174,10 @@ def test_second_order_argument_and_state_errors():
     s.primal_iterate(6)
     s.adjoint_init()
     s.adjoint_iterate(3)
-    with pytest.raises(dvm.DvmError) as e:
-        s.mesh_sensitivity()
-    assert e.value.code == dvm.DVM_EINVAL
-    # the wall sensitivity reuses the slope buffer; the adjoint continues as
-    # if it had not run (the held term is kept, the slopes are recomputed)
+    # the wall and mesh sensitivities reuse the slope buffer; the adjoint
+    # continues as if they had not run (the held term is kept, the slopes
+    # are recomputed)
+    s.mesh_sensitivity()
     t = dvm.Solver.from_workload(wl, order=2)
     t.primal_init()
     t.primal_iterate(6)

@@ -223,23 +223,25 @@ def precision_sweep(sweeps, kns, oracle_check_sweeps=2, order=1):
     return rows
 
 
-def fd_check(h, tol, params=None, order=1):
+def fd_check(h, tol, params=None, order=1, limiter=True):
     """The differentiation workload (seed-drawn NACA thickness and camber,
     192x96 C-grid, 48x48 Newton-Cotes grid, Kn 0.5, Ma 2, 24 B-spline
     offsets): dJ/dalpha from the adjoint through the autograd wrapper
     (primal f snapshotted every 50 sweeps), in the paper's wall-only form and
     in the exact discrete form, against central differences J(alpha +- h e_p)
     of re-converged primal solves.  order 2: the second-order scheme
-    (Venkatakrishnan limiter, correction every 40 sweeps); the wall-only form
-    only."""
+    (correction every 40 sweeps; with the Venkatakrishnan limiter the exact
+    form holds the limiter factors fixed, without it it is exact)."""
     import numpy as np
     import torch
 
     from paper_2501_00923_amd import autograd as AG
+    from paper_2501_00923_amd import dvm
 
     opts = AG.SolveOptions(max_iter=60000, tol=tol, adjoint_max_iter=60000, adjoint_tol=tol, check_every=100)
     case, a0 = AG.naca_bspline_case(seed=0, options=opts, checkpoint_every=50, keep_checkpoints=1)
     case.order = order
+    case.limiter = dvm.LIMITER_VENKAT if limiter else dvm.LIMITER_NONE
     rec = AG.ForwardRecord()
     alpha = torch.tensor(a0, requires_grad=True)
     t0 = time.perf_counter()
@@ -247,13 +249,11 @@ def fd_check(h, tol, params=None, order=1):
     J.backward()
     t_grad = time.perf_counter() - t0
     g = alpha.grad.numpy().copy()
-    ge = np.full_like(g, np.nan)
-    if order == 1:
-        case.exact = True
-        alpha_e = torch.tensor(a0, requires_grad=True)
-        AG.drag(alpha_e, case).backward()
-        ge = alpha_e.grad.numpy().copy()
-        case.exact = False
+    case.exact = True
+    alpha_e = torch.tensor(a0, requires_grad=True)
+    AG.drag(alpha_e, case).backward()
+    ge = alpha_e.grad.numpy().copy()
+    case.exact = False
     print(f"[fd] J {J.item():.12e}, primal {rec.iters} sweeps (resid {rec.resid:.1e}), adjoint "
           f"{rec.adjoint_iters} sweeps (resid {rec.adjoint_resid:.1e}), {t_grad:.1f} s", file=sys.stderr, flush=True)
     case.checkpoint_every = 0
@@ -267,16 +267,17 @@ def fd_check(h, tol, params=None, order=1):
         Jp = AG.drag(torch.tensor(a0 + e), case, rp).item()
         Jm = AG.drag(torch.tensor(a0 - e), case, rm).item()
         fd = (Jp - Jm) / (2 * h)
-        rows.append({"param": p, "adjoint": float(g[p]), "adjoint_exact": float(ge[p]) if order == 1 else None,
+        rows.append({"param": p, "adjoint": float(g[p]), "adjoint_exact": float(ge[p]),
                      "fd": fd,
                      "sweeps": [rp.iters, rm.iters]})
         print(f"[fd] p {p:2d}: adjoint (wall-only) {g[p]: .6e}  adjoint (exact) {ge[p]: .10e}  fd {fd: .10e}",
               file=sys.stderr, flush=True)
     gv = np.array([r["adjoint"] for r in rows])
-    ev = np.array([r["adjoint_exact"] if order == 1 else np.nan for r in rows], dtype=float)
+    ev = np.array([r["adjoint_exact"] for r in rows], dtype=float)
     fv = np.array([r["fd"] for r in rows])
     scale = float(np.max(np.abs(fv)))
-    return {"workload": "naca_bspline_c192x96_v48nc_kn0.5_ma2 (seed 0)", "order": order, "h": h, "tol": tol,
+    return {"workload": "naca_bspline_c192x96_v48nc_kn0.5_ma2 (seed 0)", "order": order,
+            "limiter": "venkatakrishnan" if (order == 2 and limiter) else None, "h": h, "tol": tol,
             "J": J.item(),
             "primal_sweeps": rec.iters, "adjoint_sweeps": rec.adjoint_iters,
             "checkpoints_kept": len(rec.checkpoints), "last_checkpoint_sweep": rec.checkpoint_iters[-1],
@@ -284,7 +285,7 @@ def fd_check(h, tol, params=None, order=1):
             "wall_only": {"max_abs_diff_over_max_fd": float(np.max(np.abs(gv - fv)) / scale),
                           "median_rel_diff": float(np.median(np.abs(gv - fv) / np.maximum(np.abs(fv), 1e-3 * scale))),
                           "cosine": float(gv @ fv / (np.linalg.norm(gv) * np.linalg.norm(fv)))},
-            "exact": None if order != 1 else {
+            "exact": {
                 "max_abs_diff_over_max_fd": float(np.max(np.abs(ev - fv)) / scale),
                 "median_rel_diff": float(np.median(np.abs(ev - fv) / np.maximum(np.abs(fv), 1e-3 * scale)))},
             "rows": rows}
@@ -349,7 +350,7 @@ def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radiu
             "deform_apply_ms": t_apply * 1e3, "deform_chain_ms": t_chain * 1e3}
 
 
-def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius):
+def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius, order=1, limiter=True, max_sweeps=200000):
     """Sensitivity of the drag to the CST design variables (the check of
     Sec. 4.1, here on a NACA0012 C-grid in free stream): at the fitted
     initial design, dJ/dalpha from the adjoint in the paper's wall-node form
@@ -364,7 +365,9 @@ def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius):
     g = I.naca_cgrid(n_wake, n_half, nj, t=0.12)
     wl = I.Workload(f"naca0012_c{g.ni}x{nj}_v{nv}nc_kn{Kn:g}_ma{Ma:g}", g,
                     I.VGridSpec(I.VG_NEWTON_COTES, nv, nv, 6.0), I.FlowSpec(Kn, Ma, 1.0), 0)
-    opt = ShapeOptimizer(wl, radius=radius, gradient="exact", solve_tol=tol, check_every=100)
+    from paper_2501_00923_amd import dvm
+    opt = ShapeOptimizer(wl, radius=radius, gradient="exact", solve_tol=tol, check_every=100, order=order,
+                         limiter=dvm.LIMITER_VENKAT if limiter else dvm.LIMITER_NONE, max_sweeps=max_sweeps)
     a0 = opt.alpha0
     t0 = time.perf_counter()
     ev = opt.evaluate(a0)
@@ -393,7 +396,8 @@ def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius):
                 "median_rel_diff": float(np.median(np.abs(v - fv) / np.maximum(np.abs(fv), 1e-3 * scale))),
                 "cosine": float(v @ fv / (np.linalg.norm(v) * np.linalg.norm(fv)))}
 
-    return {"workload": wl.name, "h": h, "tol": tol, "radius": radius, "J": ev.J, "grad_seconds": t_grad,
+    return {"workload": wl.name, "order": order, "limiter": bool(order == 2 and limiter), "h": h, "tol": tol,
+            "radius": radius, "J": ev.J, "grad_seconds": t_grad,
             "fd_seconds": time.perf_counter() - t0,
             "paper": stats(np.array([r["adjoint_paper"] for r in rows])),
             "exact": stats(np.array([r["adjoint_exact"] for r in rows])), "rows": rows}
@@ -498,6 +502,8 @@ def main():
                     help="print the adjoint-vs-central-difference table of the 24-parameter B-spline NACA case and exit")
     ap.add_argument("--fd-h", type=float, default=1e-6)
     ap.add_argument("--fd-tol", type=float, default=1e-12)
+    ap.add_argument("--fd-no-limiter", action="store_true",
+                    help="second-order fd check without the limiter (the exact form is then exact)")
     ap.add_argument("--fd-order", type=int, default=1, choices=(1, 2),
                     help="spatial order of the scheme the --fd-check runs")
     ap.add_argument("--optimize", action="store_true",
@@ -513,6 +519,7 @@ def main():
     ap.add_argument("--opt-sigma", type=float, default=0.1)
     ap.add_argument("--opt-max-sweeps", type=int, default=200000, help="sweep cap per solve")
     ap.add_argument("--opt-mixed", action="store_true", help="FP32 f and phi (FP64 moments, J, sensitivities)")
+    ap.add_argument("--opt-no-limiter", action="store_true", help="second order without the limiter")
     ap.add_argument("--cst-fd-check", action="store_true",
                     help="drag sensitivity to the CST variables (adjoint, both forms) vs central differences, "
                          "on the --opt-grid / --opt-nv / --opt-kn / --opt-ma case")
@@ -555,12 +562,15 @@ def main():
         print(json.dumps({"precision_sweep": rows}))
         return
     if args.fd_check:
-        print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol, order=args.fd_order)}))
+        print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol, order=args.fd_order,
+                                               limiter=not args.fd_no_limiter)}))
         return
     if args.cst_fd_check:
         nw_, nh_, nj_ = (int(x) for x in args.opt_grid.split(","))
         print(json.dumps({"cst_fd_check": cst_fd_check(nw_, nh_, nj_, args.opt_nv, args.opt_kn, args.opt_ma,
-                                                       args.cst_fd_h, args.cst_fd_tol, args.opt_radius)}))
+                                                       args.cst_fd_h, args.cst_fd_tol, args.opt_radius,
+                                                       order=args.opt_order, limiter=not args.opt_no_limiter,
+                                                       max_sweeps=args.opt_max_sweeps)}))
         return
     if args.optimize:
         nw_, nh_, nj_ = (int(x) for x in args.opt_grid.split(","))

@@ -47,7 +47,7 @@ class ShapeCase:
     keep_checkpoints: Optional[int] = None   # None: keep every snapshot; n: only the last n
     offload: bool = False
     exact: bool = False      # exact discrete derivative (every mesh node moves) instead of the wall-only form
-    order: int = 1           # spatial scheme: 1, or 2 (wall-only derivative only)
+    order: int = 1           # spatial scheme: 1, or 2 (exact form: limiter factors of f held fixed)
     limiter: int = dvm.LIMITER_VENKAT
     correction_every: int = 40
 

@@ -5,7 +5,8 @@
   Step 3  primal and adjoint solves; J (eq. numer_J) and Q (eq. formula_opt)
   Step 4  dJ/dalpha through the wall-node sensitivity (eq. sens_nod, the
           paper's form) or the exact discrete mesh sensitivity chained
-          through the RBF motion; dQ/dalpha by eq. (sens_con_nod)
+          through the RBF motion (second order: limiter factors held
+          fixed); dQ/dalpha by eq. (sens_con_nod)
   Step 5  SLSQP update (scipy's implementation of Kraft's algorithm, the one
           the paper uses through NLopt) under the bounds of eq.
           (cst_constraint) and Q <= 0
@@ -77,14 +78,13 @@ class _Stop(Exception):
 
 class ShapeOptimizer:
     def __init__(self, wl, nb: int = 6, radius: float = 2.0, sigma: float = 0.1, gradient: str = "paper",
-                 precision: int = dvm.FP64, order: int = 1, solve_tol: float = 1e-10,
+                 precision: int = dvm.FP64, order: int = 1, limiter: int = dvm.LIMITER_VENKAT,
+                 solve_tol: float = 1e-10,
                  max_sweeps: int = 200000, check_every: int = 50, warm_start: bool = True, progress=None):
         if gradient not in ("paper", "exact"):
             raise ValueError("gradient is 'paper' (wall nodes, eq. sens_nod) or 'exact' (mesh sensitivity)")
-        if gradient == "exact" and order != 1:
-            raise ValueError("the exact mesh sensitivity is first-order only")
         self.wl, self.nb, self.sigma, self.gradient = wl, nb, float(sigma), gradient
-        self.precision, self.order = precision, order
+        self.precision, self.order, self.limiter = precision, order, limiter
         self.solve_tol, self.max_sweeps, self.check_every = solve_tol, max_sweeps, check_every
         self.warm_start = warm_start
         self.progress = progress       # called with a line of text after each solve
@@ -114,7 +114,7 @@ class ShapeOptimizer:
         g, fl = self.grid, self.wl.flow
         mesh = dvm.Mesh(g.topology, g.ni, g.nj, g.n_wake, nodes)
         s = dvm.Solver(mesh, self.vgrid, fl.Kn, fl.Ma, fl.Tw, fl.objective, self.precision, True,
-                       bind=False, order=self.order)
+                       bind=False, order=self.order, limiter=self.limiter)
         k = self._turn
         self._turn ^= 1
         if self._slots[k] is not None:

@@ -137,17 +137,19 @@ def test_state_copy_matches_save_and_load():
         s4.state_copy_from(s1, dvm.STATE_PHI)
 
 
-def test_second_order_optimiser_matches_oracle_loop():
+@pytest.mark.parametrize("gradient", ["paper", "exact"])
+def test_second_order_optimiser_matches_oracle_loop(gradient):
     """The loop with the second-order scheme (limited reconstruction,
-    correction every 40 sweeps) and the paper's wall-node gradient with the
-    second-order values; every solve runs to the same sweep cap or
-    tolerance on both sides."""
+    correction every 40 sweeps), with the paper's wall-node gradient with the
+    second-order values or the exact one (limiter factors fixed); every
+    solve runs to the same sweep cap or tolerance on both sides."""
     from paper_2501_00923_amd.optimize import ShapeOptimizer
-    print("[optimise] small_naca second order", flush=True)
+    print(f"[optimise] small_naca second order gradient={gradient}", flush=True)
     wl = _small_workload()
     ro = OS.optimise(wl, radius=1.0, sigma=0.1, max_steps=3, solve_tol=1e-11, max_sweeps=6000, nthreads=8,
-                     order=2, correction_every=40)
-    opt = ShapeOptimizer(wl, radius=1.0, sigma=0.1, solve_tol=1e-11, max_sweeps=6000, warm_start=False, order=2)
+                     order=2, correction_every=40, gradient=gradient)
+    opt = ShapeOptimizer(wl, radius=1.0, sigma=0.1, solve_tol=1e-11, max_sweeps=6000, warm_start=False, order=2,
+                         gradient=gradient)
     r = opt.run(max_steps=3)
     assert len(r["history"]) == len(ro["history"])
     for e, (ao, Jo, Qo) in zip(r["history"], ro["history"]):

@@ -185,7 +185,8 @@ def test_c1_circle_full_size():
 def test_c2_naca_full_size_sampled():
     """NACA0012 C-grid 256x128, 48x48 Newton-Cotes grid, Kn 0.1, Ma 0.8, FP64
     (the benchmark workload): 3 primal + 3 adjoint sweeps on both sides;
-    J, every cell's moments, sampled f / phi rows and all sensitivities."""
+    J, every cell's moments, sampled f / phi rows and all sensitivities,
+    the exact mesh sensitivity in every node included."""
     wl = I.c2_naca()
     r = _run(wl, dvm.FP64, 3, 3)
     s, o = r["s"], r["o"]
@@ -200,3 +201,4 @@ def test_c2_naca_full_size_sampled():
     assert _rel(fs, o.f[cells]) <= 1e-11
     assert _rel(ps, o.phi[cells]) <= 1e-11
     _check_sens(s.wall_sensitivity(), o.wall_sensitivity(), 1e-10)
+    assert _rel(s.mesh_sensitivity(), o.mesh_sensitivity()) <= 1e-10

@@ -134,7 +134,8 @@ def test_mixed_second_order_parity(name):
 def test_c2_naca_second_order_sampled():
     """NACA0012 C-grid 256x128, 48x48 Newton-Cotes grid, Kn 0.1, Ma 0.8, FP64,
     order 2 with the limiter: 7 primal sweeps (corrections at 0 and 5) and 6
-    adjoint sweeps on both sides; J, every cell's moments, sampled rows."""
+    adjoint sweeps on both sides; J, every cell's moments, sampled rows,
+    the wall sensitivities and the exact mesh sensitivity in every node."""
     wl = I.c2_naca()
     r = _run(wl, dvm.FP64, 7, 6)
     o, s = r["o"], r["s"]
@@ -146,6 +147,7 @@ def test_c2_naca_second_order_sampled():
     assert _rel(r["f"][cells], o.f[cells]) <= 1e-11
     assert _rel(r["phi"][cells], o.phi[cells]) <= 1e-11
     assert r["sens"] <= 1e-10
+    assert r["msens"] <= 1e-10
 
 
 def test_second_order_checkpoint_continues_bitwise():

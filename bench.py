@@ -344,6 +344,7 @@ def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radiu
             "Cd": [e.Cd for e in hist], "Q_over_vmin": [e.Q / r["v_min"] for e in hist],
             "drag_change": hist[-1].Cd / hist[0].Cd - 1.0, "alpha_final": [float(x) for x in hist[-1].alpha],
             "seconds": r["seconds"], "stage_seconds": stages, "sweeps": sweeps,
+            "unconverged_solves": r["unconverged_solves"],
             "solve_updates_per_s": (sweeps["primal"] + sweeps["adjoint"]) * pairs
             / max(stages["primal"] + stages["adjoint"], 1e-9),
             "mesh_nodes": (g.ni + 1) * (g.nj + 1), "wall_nodes": opt.deform.nw,

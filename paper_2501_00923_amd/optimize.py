@@ -225,6 +225,10 @@ class ShapeOptimizer:
             # a trial design the optimiser proposed moved the mesh into an
             # invalid one (a cell of non-positive area): stop with what was reached
             message = f"invalid trial design: {e}"
+        # solves that stopped at the sweep cap above the tolerance (their J and
+        # gradients carry the remaining iteration error)
+        capped = sum(1 for e in self._cache.values() if e.primal[1] >= self.solve_tol
+                     or (e.dJ is not None and e.adjoint[1] >= self.solve_tol))
         return dict(alpha0=a0, fit_rms=self.fit_rms, v_min=self.v_min, history=hist,
                     converged=message == "criterion", message=message, evaluations=self.evaluations,
-                    seconds=time.perf_counter() - t0)
+                    unconverged_solves=capped, seconds=time.perf_counter() - t0)

@@ -684,8 +684,8 @@ def main():
         print("[bench] optimisation leg", file=sys.stderr, flush=True)
         o = optimize_leg(16, 48, 64, 32, 1.0, 0.5, 20, "paper", 1e-9, 2.0, 0.1)
         optimization = {k: o[k] for k in ("workload", "gradient", "steps", "stop", "evaluations", "gradients",
-                                          "seconds", "sweeps", "stage_seconds", "deform_apply_ms",
-                                          "deform_chain_ms")}
+                                          "unconverged_solves", "seconds", "sweeps", "stage_seconds",
+                                          "deform_apply_ms", "deform_chain_ms")}
         optimization["Cd_initial"], optimization["Cd_final"] = o["Cd"][0], o["Cd"][-1]
         optimization["drag_change"] = o["drag_change"]
         optimization["Q_over_vmin_final"] = o["Q_over_vmin"][-1]

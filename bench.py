@@ -292,7 +292,7 @@ def fd_check(h, tol, params=None, order=1, limiter=True):
 
 
 def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radius, sigma, order=1,
-                 max_sweeps=200000, mixed=False):
+                 max_sweeps=200000, mixed=False, adjoint_tol=None):
     """The optimisation loop of Sec. 3.4 on a NACA0012 C-grid ((2 n_wake +
     2 n_half) x nj cells), nv x nv Newton-Cotes velocities on [-6, 6]:
     CST fit (N_B = 6), Wendland-C0 RBF motion, warm-started primal and
@@ -310,6 +310,7 @@ def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radiu
                     I.VGridSpec(I.VG_NEWTON_COTES, nv, nv, 6.0), I.FlowSpec(Kn, Ma, 1.0), 0)
     from paper_2501_00923_amd import dvm
     opt = ShapeOptimizer(wl, radius=radius, sigma=sigma, gradient=gradient, solve_tol=tol, order=order,
+                         adjoint_tol=adjoint_tol,
                          precision=dvm.MIXED if mixed else dvm.FP64, max_sweeps=max_sweeps, progress=lambda m: print(f"[optimize] {m}", file=sys.stderr, flush=True))
     print(f"[optimize] {wl.name}: CST fit rms {opt.fit_rms:.2e}, V_min {opt.v_min:.6f}", file=sys.stderr, flush=True)
     r = opt.run(max_steps=max_steps)
@@ -336,7 +337,7 @@ def optimize_leg(n_wake, n_half, nj, nv, Kn, Ma, max_steps, gradient, tol, radiu
         opt.deform.chain(gvec)
     t_chain = (time.perf_counter() - t0) / 20
     return {"workload": wl.name, "order": order, "precision": "mixed" if mixed else "fp64", "gradient": gradient,
-            "solve_tol": tol, "max_sweeps": max_sweeps,
+            "solve_tol": tol, "adjoint_tol": opt.adjoint_tol, "max_sweeps": max_sweeps,
             "radius": radius,
             "sigma": sigma, "n_params": len(opt.alpha0), "free_params": int(len(opt.free)),
             "fit_rms": opt.fit_rms, "v_min": r["v_min"], "steps": len(hist) - 1, "stop": r["message"],
@@ -521,6 +522,7 @@ def main():
     ap.add_argument("--opt-max-sweeps", type=int, default=200000, help="sweep cap per solve")
     ap.add_argument("--opt-mixed", action="store_true", help="FP32 f and phi (FP64 moments, J, sensitivities)")
     ap.add_argument("--opt-no-limiter", action="store_true", help="second order without the limiter")
+    ap.add_argument("--opt-adjoint-tol", type=float, default=None, help="adjoint solve tolerance (default: --opt-tol)")
     ap.add_argument("--cst-fd-check", action="store_true",
                     help="drag sensitivity to the CST variables (adjoint, both forms) vs central differences, "
                          "on the --opt-grid / --opt-nv / --opt-kn / --opt-ma case")
@@ -578,7 +580,8 @@ def main():
         print(json.dumps({"optimize": optimize_leg(nw_, nh_, nj_, args.opt_nv, args.opt_kn, args.opt_ma,
                                                    args.opt_steps, args.opt_gradient, args.opt_tol,
                                                    args.opt_radius, args.opt_sigma, order=args.opt_order,
-                                                   max_sweeps=args.opt_max_sweeps, mixed=args.opt_mixed)}))
+                                                   max_sweeps=args.opt_max_sweeps, mixed=args.opt_mixed,
+                                                   adjoint_tol=args.opt_adjoint_tol)}))
         return
     wl = I.c2_naca(seed=0)
     print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",

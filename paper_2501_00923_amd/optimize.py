@@ -79,13 +79,15 @@ class _Stop(Exception):
 class ShapeOptimizer:
     def __init__(self, wl, nb: int = 6, radius: float = 2.0, sigma: float = 0.1, gradient: str = "paper",
                  precision: int = dvm.FP64, order: int = 1, limiter: int = dvm.LIMITER_VENKAT,
-                 solve_tol: float = 1e-10,
+                 solve_tol: float = 1e-10, adjoint_tol: Optional[float] = None,
                  max_sweeps: int = 200000, check_every: int = 50, warm_start: bool = True, progress=None):
         if gradient not in ("paper", "exact"):
             raise ValueError("gradient is 'paper' (wall nodes, eq. sens_nod) or 'exact' (mesh sensitivity)")
         self.wl, self.nb, self.sigma, self.gradient = wl, nb, float(sigma), gradient
         self.precision, self.order, self.limiter = precision, order, limiter
         self.solve_tol, self.max_sweeps, self.check_every = solve_tol, max_sweeps, check_every
+        # the gradient only steers the optimiser: its solve may stop earlier
+        self.adjoint_tol = solve_tol if adjoint_tol is None else adjoint_tol
         self.warm_start = warm_start
         self.progress = progress       # called with a line of text after each solve
         g = wl.grid
@@ -171,7 +173,7 @@ class ShapeOptimizer:
             prev = self._latest(k) if self.warm_start else None
             if prev is not None and prev.dJ is not None:
                 s.state_copy_from(prev.solver, dvm.STATE_PHI)
-            ev.adjoint = s.adjoint_iterate(self.max_sweeps, self.solve_tol, self.check_every, raise_notconv=False)
+            ev.adjoint = s.adjoint_iterate(self.max_sweeps, self.adjoint_tol, self.check_every, raise_notconv=False)
             t1 = time.perf_counter()
             if self.gradient == "paper":                                                     # Step 4
                 dJ_dwall = s.wall_sensitivity()["dJ_dnodes"]
@@ -228,7 +230,7 @@ class ShapeOptimizer:
         # solves that stopped at the sweep cap above the tolerance (their J and
         # gradients carry the remaining iteration error)
         capped = sum(1 for e in self._cache.values() if e.primal[1] >= self.solve_tol
-                     or (e.dJ is not None and e.adjoint[1] >= self.solve_tol))
+                     or (e.dJ is not None and e.adjoint[1] >= self.adjoint_tol))
         return dict(alpha0=a0, fit_rms=self.fit_rms, v_min=self.v_min, history=hist,
                     converged=message == "criterion", message=message, evaluations=self.evaluations,
                     unconverged_solves=capped, seconds=time.perf_counter() - t0)

@@ -110,3 +110,13 @@ def test_deformer_argument_and_state_errors():
     assert L.dvm_deform_bind(h, None, need, None) == dvm.DVM_EINVAL
     L.dvm_deform_destroy(h)
     L.dvm_deform_destroy(None)
+
+
+def test_optimiser_and_cst_case_reject_bad_arguments_before_device_work():
+    from paper_2501_00923_amd import autograd as AG
+    from paper_2501_00923_amd.optimize import ShapeOptimizer
+    wl = I.tiny_naca()
+    with pytest.raises(ValueError):
+        ShapeOptimizer(wl, gradient="finite-differences")
+    with pytest.raises(ValueError):
+        AG.cst_case(I.c1_circle())                    # an O-grid circle has no CST airfoil

@@ -310,7 +310,8 @@ int dvm_volume_constraint(int nw, const double *wall_xy, double v_min, double *Q
  * every other node moves to x0_n + sum_w gamma_w phi(|x0_n - c_w|) from its
  * reference position x0_n, and wall nodes take the new positions exactly.
  * The nodes are therefore linear in the wall displacement.  create factors
- * M (Cholesky, O(nw^3) host work, nw <= 8192; DVM_EINVAL if M is not
+ * M (Cholesky, O(nw^3) host work on up to 16 threads, a few seconds at the
+ * limit nw <= 8192, nw > 8192 is DVM_EINVAL; DVM_EINVAL if M is not
  * positive definite, e.g. two coincident wall nodes) and copies the
  * reference nodes. */
 typedef struct dvm_deform dvm_deform;

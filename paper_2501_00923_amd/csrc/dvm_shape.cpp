@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/dvm.h"
@@ -27,21 +28,99 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kMaxCentres = 8192;   // dense host factor: 8192^2 doubles = 512 MiB
 
+// f(r) for r in [lo, hi) on nt host threads, r going to thread r mod nt.
+// Each entry of a result is computed by one thread in a fixed order, so the
+// result does not depend on the thread count.
+template <class F>
+void parallel_rows(int lo, int hi, int nt, F &&f)
+{
+    nt = std::max(1, std::min(nt, hi - lo));
+    if (nt == 1) {
+        for (int r = lo; r < hi; r++) f(r);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; t++)
+        th.emplace_back([=, &f] {
+            for (int r = lo + t; r < hi; r += nt) f(r);
+        });
+    for (auto &x : th) x.join();
+}
+
 // In-place Cholesky factorisation A = L L^T of a symmetric n x n matrix
 // (row-major, lower triangle used); false if A is not positive definite.
+// Right-looking by column blocks of kCholBlock: factor the diagonal block,
+// solve the panel below it row by row, then subtract the panel's products
+// from the trailing lower triangle.  Every inner loop runs over contiguous
+// row segments of at most kCholBlock entries, which stay in cache.
+constexpr int kCholBlock = 64;
+
 bool cholesky(std::vector<double> &A, int n)
 {
-    for (int j = 0; j < n; j++) {
-        double d = A[(size_t)j * n + j];
-        for (int k = 0; k < j; k++) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
-        if (!(d > 0.0)) return false;
-        const double ljj = std::sqrt(d);
-        A[(size_t)j * n + j] = ljj;
-        for (int i = j + 1; i < n; i++) {
-            double s = A[(size_t)i * n + j];
-            for (int k = 0; k < j; k++) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-            A[(size_t)i * n + j] = s / ljj;
+    double *a = A.data();
+    auto at = [=](int i, int j) -> double & { return a[(size_t)i * n + j]; };
+    // up to 16 host threads for the large RBF systems, none for small ones
+    const int nt = n < 256 ? 1 : (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+    for (int k0 = 0; k0 < n; k0 += kCholBlock) {
+        const int k1 = std::min(n, k0 + kCholBlock);
+        for (int j = k0; j < k1; j++) {
+            double d = at(j, j);
+            for (int k = k0; k < j; k++) d -= at(j, k) * at(j, k);
+            if (!(d > 0.0)) return false;
+            const double ljj = std::sqrt(d);
+            at(j, j) = ljj;
+            for (int i = j + 1; i < k1; i++) {
+                double s = at(i, j);
+                for (int k = k0; k < j; k++) s -= at(i, k) * at(j, k);
+                at(i, j) = s / ljj;
+            }
         }
+        if (k1 == n) break;
+        // panel: row i's entries in columns [k0, k1) by forward substitution
+        parallel_rows(k1, n, nt, [&](int i) {
+            for (int j = k0; j < k1; j++) {
+                double s = at(i, j);
+                for (int k = k0; k < j; k++) s -= at(i, k) * at(j, k);
+                at(i, j) = s / at(j, j);
+            }
+        });
+        // trailing update A(i, j) -= sum_k L(i, k) L(j, k), k1 <= j <= i, by
+        // tiles of kCholBlock x kCholBlock (one task each, the two panel
+        // slices it reads stay in cache), inside them 4 x 4 register tiles
+        // in which every loaded panel entry serves four products
+        const int kw = k1 - k0;
+        const int nb = (n - k1 + kCholBlock - 1) / kCholBlock;
+        parallel_rows(0, nb * (nb + 1) / 2, nt, [&](int task) {
+            int bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= task) bi++;
+            const int bj = task - bi * (bi + 1) / 2;
+            const int i0 = k1 + bi * kCholBlock, i1 = std::min(n, i0 + kCholBlock);
+            const int j0 = k1 + bj * kCholBlock, j1 = std::min(n, j0 + kCholBlock);
+            for (int i = i0; i < i1; i += 4)
+                for (int j = j0; j < j1 && j <= i + 3; j += 4) {
+                    if (i + 4 <= i1 && j + 4 <= j1 && j + 3 <= i) {
+                        const double *r0 = a + (size_t)i * n + k0, *r1 = r0 + n, *r2 = r1 + n, *r3 = r2 + n;
+                        const double *c0 = a + (size_t)j * n + k0, *c1 = c0 + n, *c2 = c1 + n, *c3 = c2 + n;
+                        double acc[4][4] = {};
+                        for (int k = 0; k < kw; k++) {
+                            const double x[4] = {r0[k], r1[k], r2[k], r3[k]};
+                            const double y[4] = {c0[k], c1[k], c2[k], c3[k]};
+                            for (int u = 0; u < 4; u++)
+                                for (int v = 0; v < 4; v++) acc[u][v] += x[u] * y[v];
+                        }
+                        for (int u = 0; u < 4; u++)
+                            for (int v = 0; v < 4; v++) at(i + u, j + v) -= acc[u][v];
+                    } else {          // tiles on the diagonal or the ragged edge
+                        for (int u = i; u < std::min(i + 4, i1); u++)
+                            for (int v = j; v < std::min(j + 4, j1) && v <= u; v++) {
+                                double acc = 0.0;
+                                for (int k = k0; k < k1; k++) acc += at(u, k) * at(v, k);
+                                at(u, v) -= acc;
+                            }
+                    }
+                }
+        });
     }
     return true;
 }

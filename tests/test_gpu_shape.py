@@ -15,7 +15,11 @@ def _grids():
     return [("tiny_c", I.naca_cgrid(4, 12, 8, t=0.12, r_outer=4.0, h1=0.05), 1.0),
             ("small_c", I.naca_cgrid(4, 24, 10, t=0.12, r_outer=4.0, h1=0.02), 0.5),
             ("c256x128", I.naca_cgrid(32, 96, 128), 2.0),
-            ("o64x32", I.ogrid(64, 32), 3.0)]
+            ("o64x32", I.ogrid(64, 32), 3.0),
+            # walls of 400 and 301 nodes: the host factor of the RBF system
+            # then runs threaded, over several column blocks, with ragged edges
+            ("c_wall400", I.naca_cgrid(8, 200, 16, t=0.12, r_outer=4.0, h1=0.01), 1.5),
+            ("o301x8", I.ogrid(301, 8), 2.0)]
 
 
 @pytest.mark.parametrize("name,g,R", _grids(), ids=[x[0] for x in _grids()])

@@ -18,7 +18,7 @@ def _stations(n):
     return 0.5 * (1 - np.cos(beta)), ~lower
 
 
-@pytest.mark.parametrize("nb", [1, 6, 12])
+@pytest.mark.parametrize("nb", [1, 6, 12, 20])      # 20: the largest order the library takes
 def test_cst_eval_and_jacobian_match_oracle(nb):
     xi, up = _stations(64)
     rng = np.random.default_rng(nb)
@@ -110,6 +110,13 @@ def test_deformer_argument_and_state_errors():
     assert L.dvm_deform_bind(h, None, need, None) == dvm.DVM_EINVAL
     L.dvm_deform_destroy(h)
     L.dvm_deform_destroy(None)
+    # more wall nodes than the dense RBF system takes (8192): refused before
+    # the system is assembled
+    big = dvm.Mesh.from_grid(I.ogrid(8193, 1, r_outer=2.0))
+    assert big.nw == 8193
+    h = C.c_void_p()
+    assert L.dvm_deform_create(big._h, 0.5, C.byref(h)) == dvm.DVM_EINVAL
+    assert "8192" in L.dvm_last_error().decode()
 
 
 def test_optimiser_and_cst_case_reject_bad_arguments_before_device_work():

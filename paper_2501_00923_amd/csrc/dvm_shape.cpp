@@ -126,18 +126,25 @@ bool cholesky(std::vector<double> &A, int n)
 }
 
 // Solve L L^T x = b in place for nrhs right-hand sides stored b[i*nrhs + r].
+// Both substitutions read L by rows: forward, row i against the solved
+// entries above it; backward (L^T x = y), each solved x_i is subtracted,
+// times row i of L, from the entries before it.
 void cholesky_solve(const std::vector<double> &L, int n, double *b, int nrhs)
 {
-    for (int r = 0; r < nrhs; r++) {
-        for (int i = 0; i < n; i++) {
+    for (int i = 0; i < n; i++) {
+        const double *li = L.data() + (size_t)i * n;
+        for (int r = 0; r < nrhs; r++) {
             double s = b[(size_t)i * nrhs + r];
-            for (int k = 0; k < i; k++) s -= L[(size_t)i * n + k] * b[(size_t)k * nrhs + r];
-            b[(size_t)i * nrhs + r] = s / L[(size_t)i * n + i];
+            for (int k = 0; k < i; k++) s -= li[k] * b[(size_t)k * nrhs + r];
+            b[(size_t)i * nrhs + r] = s / li[i];
         }
-        for (int i = n - 1; i >= 0; i--) {
-            double s = b[(size_t)i * nrhs + r];
-            for (int k = i + 1; k < n; k++) s -= L[(size_t)k * n + i] * b[(size_t)k * nrhs + r];
-            b[(size_t)i * nrhs + r] = s / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        const double *li = L.data() + (size_t)i * n;
+        for (int r = 0; r < nrhs; r++) {
+            const double x = b[(size_t)i * nrhs + r] / li[i];
+            b[(size_t)i * nrhs + r] = x;
+            for (int k = 0; k < i; k++) b[(size_t)k * nrhs + r] -= li[k] * x;
         }
     }
 }

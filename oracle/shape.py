@@ -214,6 +214,16 @@ def wall_node_index(topology: int, ni: int, nj: int, n_wake: int):
     return idx
 
 
+def _distance(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """|a_i - b_j| for every pair of points: sqrt(dx^2 + dy^2)."""
+    dx = a[:, None, 0] - b[None, :, 0]
+    dy = a[:, None, 1] - b[None, :, 1]
+    dx *= dx
+    dy *= dy
+    dx += dy
+    return np.sqrt(dx, out=dx)
+
+
 class RBFDeform:
     """Interpolated motion of every mesh node from the wall nodes' motion.
 
@@ -230,8 +240,8 @@ class RBFDeform:
         for n in np.nonzero(self.widx >= 0)[0]:
             self.c[self.widx[n]] = self.x0[n]
         self.R = float(radius)
-        self.M = wendland_c0(np.linalg.norm(self.c[:, None] - self.c[None], axis=-1) / self.R)
-        self.Phi = wendland_c0(np.linalg.norm(self.x0[:, None] - self.c[None], axis=-1) / self.R)
+        self.M = wendland_c0(_distance(self.c, self.c) / self.R)
+        self.Phi = wendland_c0(_distance(self.x0, self.c) / self.R)
 
     def apply(self, wall_new: np.ndarray) -> np.ndarray:
         d = np.asarray(wall_new, dtype=np.float64) - self.c

@@ -22,8 +22,7 @@ def _grids():
             ("o301x8", I.ogrid(301, 8), 2.0)]
 
 
-@pytest.mark.parametrize("name,g,R", _grids(), ids=[x[0] for x in _grids()])
-def test_deform_apply_and_chain_match_oracle(name, g, R):
+def _deform_parity(name, g, R, cond=None):
     from paper_2501_00923_amd.shape import Deformer
     print(f"[deform] {name} R={R}", flush=True)
     mesh = dvm.Mesh.from_grid(g)
@@ -33,7 +32,7 @@ def test_deform_apply_and_chain_match_oracle(name, g, R):
     scale = np.max(np.abs(g.nodes))
     # the weights solve M gamma = d: both sides agree to about cond(M) eps
     # relative (Cholesky here, LU in the oracle)
-    kappa = np.linalg.cond(O.M) * np.finfo(np.float64).eps
+    kappa = (np.linalg.cond(O.M) if cond is None else cond(O.M)) * np.finfo(np.float64).eps
     for call in range(2):                                     # two calls in a row, different inputs
         c = O.c
         if call == 0:                                         # rough: independent normal offsets
@@ -51,6 +50,24 @@ def test_deform_apply_and_chain_match_oracle(name, g, R):
         assert np.max(np.abs(h - ho)) < max(1e-13, 4 * kappa) * np.max(np.abs(ho)), call
     # the moved mesh is a valid mesh
     dvm.Mesh(g.topology, g.ni, g.nj, g.n_wake, x)
+
+
+@pytest.mark.parametrize("name,g,R", _grids(), ids=[x[0] for x in _grids()])
+def test_deform_apply_and_chain_match_oracle(name, g, R):
+    _deform_parity(name, g, R)
+
+
+def test_deform_at_the_wall_node_limit():
+    """8192 wall nodes, the most the library takes.  The wall is a circle of
+    equally spaced nodes, so the RBF matrix is circulant and its condition
+    number is exactly that of the FFT of one row."""
+    g = I.ogrid(8192, 1, r_outer=2.0)
+    assert dvm.Mesh.from_grid(g).nw == 8192
+
+    def circulant_cond(M):
+        lam = np.abs(np.fft.fft(M[0]).real)
+        return lam.max() / lam.min()
+    _deform_parity("o8192x1", g, 1.5, circulant_cond)
 
 
 def _small_workload(Kn=1.0):

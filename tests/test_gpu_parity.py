@@ -155,6 +155,25 @@ def test_mixed_precision_parity(name):
     assert ef <= 2e-5 and eJ <= 2e-5 and eS <= 1e-3 and eM <= 1e-3
 
 
+def test_param_sensitivity_at_the_parameter_limit():
+    """64 shape parameters, the most the library takes, against the
+    oracle's wall-node derivative contracted with the same Jacobian (a dense
+    random one); 65 parameters are refused before any device work."""
+    wl = I.tiny_naca()
+    r = _run(wl, dvm.FP64, 37, 29)
+    s, o = r["s"], r["o"]
+    nw = wl.grid.wall_jac.shape[0]
+    jac = np.random.default_rng(64).standard_normal((nw, 2, dvm.MAX_PARAMS))
+    da = s.param_sensitivity(jac)
+    do = np.einsum("md,mdp->p", o.wall_sensitivity()["dJ_dnodes"], jac)
+    assert _rel(da, do) <= 1e-10
+    # fewer parameters give the leading entries of the same contraction
+    assert _rel(s.param_sensitivity(jac[..., :5]), do[:5]) <= 1e-10
+    with pytest.raises(dvm.DvmError) as ei:
+        s.param_sensitivity(np.zeros((nw, 2, dvm.MAX_PARAMS + 1)))
+    assert ei.value.code == dvm.DVM_EINVAL
+
+
 def test_c1_circle_full_size():
     """Circle O-grid 64x32, 16x16 velocities on [-5,5], Kn 1, Ma 0.5, FP64:
     the GPU converges the primal and the adjoint to a relative residual of

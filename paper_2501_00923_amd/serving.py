@@ -18,10 +18,9 @@ The scheduler talks to a ``Backend``; ``GpuBackend`` runs libdvm batches,
 """
 from __future__ import annotations
 
-import heapq
 import math
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Dict, List, Optional
 
 import numpy as np

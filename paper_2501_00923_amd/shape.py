@@ -4,7 +4,6 @@ RBF bulk-mesh deformation (Sec. 3.4, Step 2).  Argument marshalling only."""
 from __future__ import annotations
 
 import ctypes as C
-from typing import Optional
 
 import numpy as np
 

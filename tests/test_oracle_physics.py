@@ -13,7 +13,6 @@
 import math
 
 import numpy as np
-import pytest
 from scipy.special import i0e, i1e
 
 import oracle

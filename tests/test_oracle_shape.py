@@ -7,10 +7,8 @@ CST surface's own parameters by the fit, the shoelace formula and the
 analytic (beta-function) area of a CST profile, central differences, and the
 brute-force Jacobian of the deformation.
 """
-import math
 
 import numpy as np
-import pytest
 
 from oracle import shape as S
 from paper_2501_00923_amd import inputs as I

@@ -7,6 +7,7 @@ import ctypes as C
 
 import numpy as np
 
+from . import dvm as _dvm
 from .dvm import Mesh, _check, alloc_device, current_stream_handle, lib
 
 MAX_NB = 20
@@ -91,8 +92,10 @@ class Deformer:
         return out
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().dvm_deform_destroy(self._h)
+        # the library is loaded by then (create needed it); at interpreter
+        # shutdown the module globals may already be gone
+        if getattr(self, "_h", None) and _dvm._lib is not None:
+            _dvm._lib.dvm_deform_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -477,6 +477,47 @@ def cpu_baseline(wl, seconds):
                             "sample": f"{np1} primal + {na1} adjoint sweeps, one thread ({t1:.1f} s)"}}
 
 
+def deform_scale():
+    """RBF mesh motion (Sec. 3.4, Step 2) on O-grids from 192 to 8192 wall
+    nodes (the library's limit): set-up (host Cholesky of the RBF system)
+    and one motion and one transpose, host-inclusive, averaged over 5 calls
+    after 2 warm-up calls.  Kernel times come from a kernel trace of this
+    mode."""
+    import numpy as np
+    import torch
+
+    from paper_2501_00923_amd import dvm, inputs as I
+    from paper_2501_00923_amd.shape import Deformer
+
+    rows = []
+    for ni, nj, R in ((192, 128, 2.0), (2048, 128, 2.0), (8192, 64, 0.5), (8192, 64, 1.5)):
+        g = I.ogrid(ni, nj, r_outer=10.0)
+        mesh = dvm.Mesh.from_grid(g)
+        t = time.perf_counter()
+        D = Deformer(mesh, R)
+        t_setup = time.perf_counter() - t
+        wall = g.nodes[0, :ni] + 1e-4
+        gvec = np.ones((nj + 1, ni + 1, 2))
+        for _ in range(2):
+            D.apply(wall)
+            D.chain(gvec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            D.apply(wall)
+        t_apply = (time.perf_counter() - t) / 5
+        t = time.perf_counter()
+        for _ in range(5):
+            D.chain(gvec)
+        t_chain = (time.perf_counter() - t) / 5
+        row = {"wall_nodes": ni, "mesh_nodes": (ni + 1) * (nj + 1), "radius": R, "setup_s": t_setup,
+               "apply_ms": t_apply * 1e3, "chain_ms": t_chain * 1e3}
+        print(f"[deform] {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+        D.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -526,6 +567,8 @@ def main():
     ap.add_argument("--cst-fd-check", action="store_true",
                     help="drag sensitivity to the CST variables (adjoint, both forms) vs central differences, "
                          "on the --opt-grid / --opt-nv / --opt-kn / --opt-ma case")
+    ap.add_argument("--deform-scale", action="store_true",
+                    help="RBF mesh motion timings on O-grids from 192 to 8192 wall nodes")
     ap.add_argument("--cst-fd-h", type=float, default=1e-4)
     ap.add_argument("--cst-fd-tol", type=float, default=1e-13)
     ap.add_argument("--opt-order", type=int, default=1, choices=(1, 2),
@@ -567,6 +610,9 @@ def main():
     if args.fd_check:
         print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol, order=args.fd_order,
                                                limiter=not args.fd_no_limiter)}))
+        return
+    if args.deform_scale:
+        print(json.dumps({"deform_scale": deform_scale()}))
         return
     if args.cst_fd_check:
         nw_, nh_, nj_ = (int(x) for x in args.opt_grid.split(","))

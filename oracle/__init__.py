@@ -15,16 +15,17 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dvm_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of the same source (the sanitizer runs)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
+FLAGS = ["-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function"]
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no fast-math, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", *FLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -76,6 +77,7 @@ def lib():
         L.or_adjoint_dJdp.argtypes = [P, I]
         L.or_wall_sensitivity.argtypes = [P, dp, dp, dp, C.c_void_p]
         L.or_mesh_sensitivity.argtypes = [P, D, dp]
+        L.or_gauss_grad.argtypes = [P, I, dp]
         L.or_wall_JB.restype = D
         L.or_wall_JB.argtypes = [P, I, D, D, D, D, D]
         L.or_set_scheme.restype = I
@@ -311,6 +313,13 @@ class Problem:
         off)."""
         out = np.zeros((self.nj + 1, self.ni + 1, 2))
         lib().or_mesh_sensitivity(self._h, float(h), out)
+        return out
+
+    def gauss_grad(self, c: int):
+        """Green-Gauss gradient of eq. (gaussgrad) at cell c with the current
+        f: [velocity, component, direction]."""
+        out = np.zeros((self.nv, 2, 2))
+        lib().or_gauss_grad(self._h, int(c), out)
         return out
 
     def wall_JB(self, l, A, x, n):

@@ -1681,6 +1681,22 @@ static void gauss_grad(const or_problem *p, const wall_ctx *w, int c, int k, dou
     for (int a = 0; a < 2; a++) for (int b = 0; b < 2; b++) g[a][b] /= V;
 }
 
+/* The Green-Gauss gradient of eq. (gaussgrad) at cell c for every velocity,
+ * out[k][component][direction], with the current f and wall fluxes (access
+ * for the tests that pin it on fields whose upwind differences have closed
+ * forms). */
+void or_gauss_grad(or_problem *p, int c, double *out)
+{
+    wall_ctx wc = wall_ctx_make(p);
+    for (int k = 0; k < p->nv; k++) {
+        double g[2][2];
+        gauss_grad(p, &wc, c, k, g);
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) out[4 * k + 2 * a + b] = g[a][b];
+    }
+    wall_ctx_free(&wc);
+}
+
 /* Element derivatives dL/dA_l, dL/dx_l, dL/dn_l (eqs. sens_J_itf, sens_B_itf)
  * and their transform to the wall nodes (eq. sens_nod).  Wall node m is
  * x_{l,1} of element l = m and x_{l,2} of element m - 1 (closed loop). */

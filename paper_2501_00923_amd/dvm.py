@@ -14,14 +14,15 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdvm.so")
+# DVM_LIB names another build of the same sources (the host-sanitizer runs)
+LIB_PATH = os.environ.get("DVM_LIB") or os.path.join(_HERE, "libdvm.so")
 
 DVM_OK, DVM_EINVAL, DVM_ENOMEM, DVM_EHIP, DVM_ENOTCONV, DVM_ENAN, DVM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 TOPO_O, TOPO_C = 0, 1
 FP64, MIXED = 0, 1
 OBJ_DRAG, OBJ_HEAT = 0, 1
 VG_MIDPOINT, VG_NEWTON_COTES, VG_SINH = 0, 1, 2
-STATE_F, STATE_PHI = 0, 1
+STATE_F, STATE_PHI, STATE_PHI_ROWS = 0, 1, 2
 LIMITER_NONE, LIMITER_VENKAT = 0, 1
 MAX_PARAMS = 64
 

@@ -67,7 +67,7 @@ enum { DVM_FP64 = 0, DVM_MIXED = 1 };   /* MIXED: f, phi and per-pair arithmetic
                                            wall fluxes, J and sensitivities in FP64 */
 enum { DVM_OBJ_DRAG = 0, DVM_OBJ_HEAT = 1 };
 enum { DVM_VG_MIDPOINT = 0, DVM_VG_NEWTON_COTES = 1, DVM_VG_SINH = 2 };
-enum { DVM_STATE_F = 0, DVM_STATE_PHI = 1 };
+enum { DVM_STATE_F = 0, DVM_STATE_PHI = 1, DVM_STATE_PHI_ROWS = 2 };
 enum { DVM_LIMITER_NONE = 0, DVM_LIMITER_VENKAT = 1 };   /* second-order slope limiter */
 #define DVM_MAX_PARAMS 64
 
@@ -218,7 +218,12 @@ int dvm_mesh_sensitivity(dvm_solver *s, double *dJ_dx);
  * wall fluxes (bitwise as the sweep computes them) and starts a primal
  * phase.  DVM_STATE_PHI: phi followed by its FP64 adjoint moments ([nc][8])
  * and wall multipliers ([nw]); needs an adjoint phase.  Resuming from a
- * snapshot reproduces the iterates bitwise.  Both synchronise. */
+ * snapshot reproduces the iterates bitwise.  DVM_STATE_PHI_ROWS: phi alone
+ * ([nc][nv][2], storage precision); loading it computes its adjoint moments
+ * (eq. adjoint_macdefines, with the frozen f) and wall multipliers (eq.
+ * formula_adjointbgk) on the device, with the arithmetic and summation order
+ * of the adjoint sweep, so any phi (e.g. one from another solver) can start
+ * an adjoint iteration; needs an adjoint phase.  Both synchronise. */
 size_t dvm_state_bytes(const dvm_solver *s, int which);
 int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes);
 int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes);

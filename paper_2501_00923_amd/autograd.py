@@ -16,6 +16,7 @@ snapshots of f during the primal solve (resume / inspection).
 """
 from __future__ import annotations
 
+import warnings
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional
 
@@ -34,6 +35,20 @@ class SolveOptions:
     adjoint_max_iter: int = 20000
     adjoint_tol: float = 1e-10
     fixed_iters: bool = False        # run exactly max_iter / adjoint_max_iter sweeps
+    on_notconv: str = "warn"         # a solve left above its tolerance: "warn", "raise" or "ignore"
+
+
+class NotConvergedWarning(RuntimeWarning):
+    """A primal or adjoint solve stopped at its sweep cap above tolerance."""
+
+
+def _unconverged(o: SolveOptions, what: str, iters: int, resid: float, tol: float):
+    if o.fixed_iters or resid < tol or o.on_notconv == "ignore":
+        return
+    msg = f"{what} solve not converged: residual {resid:.3e} above {tol:.1e} after {iters} sweeps"
+    if o.on_notconv == "raise":
+        raise dvm.NotConverged(dvm.DVM_ENOTCONV, msg)
+    warnings.warn(msg, NotConvergedWarning, stacklevel=3)
 
 
 @dataclass
@@ -98,9 +113,11 @@ class _DragFn(torch.autograd.Function):
                             order=case.order, limiter=case.limiter, correction_every=case.correction_every)
         solver.primal_init()
         _primal(case, solver, rec)
+        _unconverged(case.options, "primal", rec.iters, rec.resid, case.options.tol)
         J, Cd = solver.objective()
         rec.Cd = Cd
         ctx.case, ctx.rec, ctx.wall_jac, ctx.node_jac = case, rec, grid.wall_jac, grid.node_jac
+        ctx.alpha_device, ctx.alpha_dtype = alpha.device, alpha.dtype
         if case.offload:
             ctx.f_host = solver.state_save(dvm.STATE_F)
             solver.buffer = None          # release the device workspace
@@ -121,12 +138,14 @@ class _DragFn(torch.autograd.Function):
         else:
             it, r = solver.adjoint_iterate(o.adjoint_max_iter, o.adjoint_tol, o.check_every, raise_notconv=False)
         ctx.rec.adjoint_iters, ctx.rec.adjoint_resid = it, r
+        _unconverged(o, "adjoint", it, r, o.adjoint_tol)
         if case.exact:
             dJ = np.einsum("jid,jidp->p", solver.mesh_sensitivity(), ctx.node_jac)
         else:
             dJ = solver.param_sensitivity(ctx.wall_jac)
         ctx.solver = None
-        return torch.from_numpy(dJ) * gJ.detach().cpu().double(), None, None
+        grad = torch.from_numpy(dJ) * gJ.detach().cpu().double()
+        return grad.to(device=ctx.alpha_device, dtype=ctx.alpha_dtype), None, None
 
 
 def drag(alpha: torch.Tensor, case: ShapeCase, record: Optional[ForwardRecord] = None) -> torch.Tensor:

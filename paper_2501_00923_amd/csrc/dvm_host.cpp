@@ -1021,6 +1021,7 @@ size_t dvm_state_bytes(const dvm_solver *s, int which)
     if (which == DVM_STATE_F) return row;
     if (which == DVM_STATE_PHI && s->want_adjoint)
         return row + (size_t)8 * s->nc * sizeof(double) + (size_t)s->nw * sizeof(double);
+    if (which == DVM_STATE_PHI_ROWS && s->want_adjoint) return row;
     return 0;
 }
 
@@ -1030,7 +1031,7 @@ int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes)
     const size_t need = dvm_state_bytes(s, which);
     if (!need || !host_dst || bytes < need) return fail(DVM_EINVAL, "bad state kind or buffer size");
     if (which == DVM_STATE_F && s->phase < 0) return fail(DVM_ESTATE, "no primal state");
-    if (which == DVM_STATE_PHI && s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
+    if (which != DVM_STATE_F && s->phase != 1) return fail(DVM_ESTATE, "no adjoint state");
     char *dst = static_cast<char *>(host_dst);
     const size_t rowb = (size_t)s->nv * 2 * elt_bytes(*s), all = rowb * s->nc, awb = 8 * sizeof(double);
     try {
@@ -1038,6 +1039,8 @@ int dvm_state_save(dvm_solver *s, int which, void *host_dst, size_t bytes)
         if (which == DVM_STATE_F) {
             const int par = s->phase == 1 ? s->frozen_fpar : s->fpar;
             HIP_OK(hipMemcpyAsync(tmp.data(), s->dev.f[par], all, hipMemcpyDeviceToHost, s->stream));
+        } else if (which == DVM_STATE_PHI_ROWS) {
+            HIP_OK(hipMemcpyAsync(tmp.data(), s->dev.phi[s->ppar], all, hipMemcpyDeviceToHost, s->stream));
         } else {
             HIP_OK(hipMemcpyAsync(tmp.data(), s->dev.phi[s->ppar], all, hipMemcpyDeviceToHost, s->stream));
             HIP_OK(hipMemcpyAsync(tmp.data() + all, s->dev.aW[s->ppar], awb * s->nc, hipMemcpyDeviceToHost, s->stream));
@@ -1058,7 +1061,7 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
     if (int e = check_bound(s)) return e;
     const size_t need = dvm_state_bytes(s, which);
     if (!need || !host_src || bytes < need) return fail(DVM_EINVAL, "bad state kind or buffer size");
-    if (which == DVM_STATE_PHI && s->phase != 1)
+    if (which != DVM_STATE_F && s->phase != 1)
         return fail(DVM_ESTATE, "no adjoint phase to load into (call dvm_adjoint_init)");
     const char *src = static_cast<const char *>(host_src);
     const size_t rowb = (size_t)s->nv * 2 * elt_bytes(*s), all = rowb * s->nc, awb = 8 * sizeof(double);
@@ -1072,6 +1075,10 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
             s->phase = 0;
             s->iters[0] = s->iters[1] = 0;
             s->corr_ok[0] = 0;
+        } else if (which == DVM_STATE_PHI_ROWS) {
+            HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], tmp.data(), all, hipMemcpyHostToDevice, s->stream));
+            HIP_OK(dvm::launch_adjoint_moments(s->dev, s->ppar, s->stream));
+            s->corr_ok[1] = 0;
         } else {
             rows_to_dev(*s, src + all, tmp.data() + all, awb);
             HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], tmp.data(), all, hipMemcpyHostToDevice, s->stream));

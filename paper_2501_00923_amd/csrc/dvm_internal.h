@@ -91,6 +91,8 @@ hipError_t launch_residual(const DevSolve &d, int adjoint, hipStream_t st);
 hipError_t launch_objective(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st);
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
+// adjoint moments (What, rho_tau) and wall multipliers of phi[par] (a loaded phi)
+hipError_t launch_adjoint_moments(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
 hipError_t launch_mesh_sens(const DevSolve &d, int fpar, int ppar, hipStream_t st);
 

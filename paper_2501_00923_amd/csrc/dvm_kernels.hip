@@ -381,6 +381,59 @@ __device__ __forceinline__ void moments_wave(const DevSolve &d, int c, int par)
     }
 }
 
+// Per-cell constants of the adjoint moments: the frozen velocity u, theta/2,
+// theta_w/2, the wall face vector and wall element (-1: none), objective.
+struct AdjCell {
+    double u1, u2, hth, thw2, S0x, S0y;
+    int wl, obj;
+};
+
+// One velocity's share of the FP64 adjoint moments of phi (eqs.
+// adjoint_macdefines, formula_adjointbgk): phi . dg/dP for P = (rho, u1, u2,
+// theta) summed as A0..A4, the rho_tau sum R and the wall multiplier sum Pw
+// (incoming velocities of the wall face).  g1, g2: the frozen Maxwellian at
+// this velocity; gMk: g_M1(1, 0, theta_w) there.  Shared by the adjoint
+// sweep's epilogue and k_adjoint_moments, so both give the same bits.
+__device__ __forceinline__ void adjoint_terms(double &A0, double &A1, double &A2, double &A3, double &A4, double &R,
+                                              double &Pw, const AdjCell &q, double v1d, double v2d, double wt,
+                                              double g1, double g2, double p1, double p2, double fs1, double fs2,
+                                              double gMk)
+{
+    const double qq = fma(q.hth, p2, p1);
+    const double c1 = v1d - q.u1, c2 = v2d - q.u2;
+    const double wg = wt * g1, wq = wg * qq;
+    A0 += wq;
+    A1 = fma(wq, c1, A1);
+    A2 = fma(wq, c2, A2);
+    A3 = fma(wq, fma(c1, c1, c2 * c2), A3);
+    A4 = fma(wg, p2, A4);
+    R = fma(wt, fma(p1, g1 - fs1, p2 * (g2 - fs2)), R);
+    if (q.wl >= 0) {
+        const double s0 = v1d * q.S0x + v2d * q.S0y;
+        if (s0 <= 0) Pw += wt * s0 * gMk * ((p1 + mJ_of(q.obj, v1d, v2d)) + q.thw2 * p2);
+    }
+}
+
+// The wave-reduced sums acc[0..6] of adjoint_terms -> What (4) and rho_tau
+// of the cell (ao[0..4]) and the wall multiplier Phi_l of its wall element.
+__device__ __forceinline__ void adjoint_store(const DevSolve &d, const double *ac, int wl, const double *acc,
+                                              double *ao, double *Phi)
+{
+    const double rho = ac[0], u1 = ac[1], u2 = ac[2], th = ac[3], itau = ac[4], E = ac[10];
+    // phi . dg/dP with P = (rho, u1, u2, theta)
+    const double P0 = acc[0] / rho;
+    const double P1 = acc[1] / th, P2 = acc[2] / th;
+    const double P3 = acc[3] / (2.0 * th * th) - acc[0] / th + 0.5 * acc[4];
+    const double ir = 1.0 / rho;
+    // What_m = sum_q P_q dP_q/dW_m
+    ao[0] = P0 - P1 * u1 * ir - P2 * u2 * ir + P3 * (2.0 / 3.0) * (u1 * u1 + u2 * u2 - E) * ir;
+    ao[1] = P1 * ir - P3 * (2.0 / 3.0) * u1 * ir;
+    ao[2] = P2 * ir - P3 * (2.0 / 3.0) * u2 * ir;
+    ao[3] = P3 * (2.0 / 3.0) * ir;
+    ao[4] = acc[5] * itau;
+    if (wl >= 0) Phi[wl] = -acc[6] / (d.wall_A[wl] * d.D[wl]);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint sweep of one patch: eq. (numerad_gov) with the wall and far-field
 // conditions of eq. (formula_adjointbgk), Jacobi point-implicit:
@@ -406,7 +459,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
     const T2 *__restrict__ eterm = static_cast<const T2 *>(d.corr);
 
     const double *ac = d.acoef + 16 * c;
-    const double rho = uni(ac[0]), u1 = uni(ac[1]), u2 = uni(ac[2]), th = uni(ac[3]), itau = uni(ac[4]);
+    const double u1 = uni(ac[1]), u2 = uni(ac[2]), th = uni(ac[3]), itau = uni(ac[4]);
     const double gcoef = ac[5];
     const double dt0 = ac[6], dt1 = ac[7], dt2 = ac[8], dt3 = ac[9];
     const double Vv = d.vol[c];
@@ -482,25 +535,15 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
         r.y = (a2 + VT * Ct3) * rden;
         return r;
     };
+    const AdjCell cq = {u1, u2, hth, thw2, S0x, S0y, wl, obj};
     auto accumulate = [&](int a, int b, int k, T2 r, T2 fs, T2 old) {
         const double v1d = sm.vx[a], v2d = sm.vy[b];
         const double wt = sm.wx[a] * sm.wy[b];
         const double p1 = (double)r.x, p2 = (double)r.y;
         const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
         const double g2 = (double)(th2 * (T)g1);
-        const double qq = fma(hth, p2, p1);
-        const double c1 = v1d - u1, c2 = v2d - u2;
-        const double wg = wt * g1, wq = wg * qq;
-        A0 += wq;
-        A1 = fma(wq, c1, A1);
-        A2 = fma(wq, c2, A2);
-        A3 = fma(wq, fma(c1, c1, c2 * c2), A3);
-        A4 = fma(wg, p2, A4);
-        R = fma(wt, fma(p1, g1 - (double)fs.x, p2 * (g2 - (double)fs.y)), R);
-        if (wl >= 0) {
-            const double s0 = v1d * S0x + v2d * S0y;
-            if (s0 <= 0) Pw += wt * s0 * (double)gM[k] * ((p1 + mJ_of(obj, v1d, v2d)) + thw2 * p2);
-        }
+        adjoint_terms(A0, A1, A2, A3, A4, R, Pw, cq, v1d, v2d, wt, g1, g2, p1, p2, (double)fs.x, (double)fs.y,
+                      wl >= 0 ? (double)gM[k] : 0.0);
         const double e1 = p1 - (double)old.x, e2 = p2 - (double)old.y;
         dn = fma(wt, fma(e1, e1, e2 * e2), dn);
         dd = fma(wt, fma(p1, p1, p2 * p2), dd);
@@ -630,23 +673,83 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
     double acc[9] = {A0, A1, A2, A3, A4, R, Pw, dn, dd};
     wave_sum<9>(acc);
     if (act && lane == 0) {
-        // phi . dg/dP with P = (rho, u1, u2, theta)
-        const double P0 = acc[0] / rho;
-        const double P1 = acc[1] / th, P2 = acc[2] / th;
-        const double P3 = acc[3] / (2.0 * th * th) - acc[0] / th + 0.5 * acc[4];
-        const double E = ac[10];
-        const double ir = 1.0 / rho;
-        double *ao = d.aW[par ^ 1] + 8 * c;
-        // What_m = sum_q P_q dP_q/dW_m
-        ao[0] = P0 - P1 * u1 * ir - P2 * u2 * ir + P3 * (2.0 / 3.0) * (u1 * u1 + u2 * u2 - E) * ir;
-        ao[1] = P1 * ir - P3 * (2.0 / 3.0) * u1 * ir;
-        ao[2] = P2 * ir - P3 * (2.0 / 3.0) * u2 * ir;
-        ao[3] = P3 * (2.0 / 3.0) * ir;
-        ao[4] = acc[5] * itau;
-        if (wl >= 0) d.Phi[par ^ 1][wl] = -acc[6] / (d.wall_A[wl] * d.D[wl]);
+        adjoint_store(d, ac, wl, acc, d.aW[par ^ 1] + 8 * c, d.Phi[par ^ 1]);
         d.red[2 * c] = acc[7];
         d.red[2 * c + 1] = acc[8];
     }
+}
+
+// Adjoint moments What, rho_tau and wall multipliers Phi_l of phi[par] with
+// no update (a loaded phi): the lane <-> velocity map, expressions and
+// summation order of the adjoint sweep's epilogue, so the next sweep sees
+// what a sweep that had produced this phi would have left.
+template <typename T>
+__device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, int par)
+{
+    using T2 = typename Vec2<T>::type;
+    __shared__ PatchLds<T, false> sm;
+    const int w = uni((int)(threadIdx.x / kWave)), lane = threadIdx.x % kWave;
+    const int c0 = uni(d.patch[p]), cnt = uni(d.patch[p + 1]) - c0;
+    const bool act = w < cnt;
+    const int c = c0 + (act ? w : 0);
+    const int nv = d.nv, n1 = d.n1;
+    const T2 *__restrict__ pin = static_cast<const T2 *>(d.phi[par]);
+    const T2 *__restrict__ fst = static_cast<const T2 *>(d.fstar);
+    const T *__restrict__ gM = static_cast<const T *>(d.gM);
+    const double *ac = d.acoef + 16 * c;
+    const double u1 = uni(ac[1]), u2 = uni(ac[2]), th = uni(ac[3]);
+    patch_tables<T, false>(d, sm, w, lane, u1, u2, 0.5 / th);
+    const int l0 = uni(d.nbr[4 * c]);
+    const int wl = l0 <= -2 ? -2 - l0 : -1;
+    double S0x = 0, S0y = 0;
+    if (wl >= 0) {
+        S0x = uni(d.S[8 * c]);
+        S0y = uni(d.S[8 * c + 1]);
+    }
+    const T gc = uni((T)ac[5]), th2 = uni((T)(0.5 * th));
+    const AdjCell cq = {u1, u2, 0.5 * th, 0.5 * d.theta_w, S0x, S0y, wl, d.objective};
+    const size_t row = (size_t)c * nv;
+    __syncthreads();
+    double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, R = 0, Pw = 0;
+    auto accumulate = [&](int a, int b, int k, T2 r, T2 fs) {
+        const double v1d = sm.vx[a], v2d = sm.vy[b];
+        const double wt = sm.wx[a] * sm.wy[b];
+        const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
+        const double g2 = (double)(th2 * (T)g1);
+        adjoint_terms(A0, A1, A2, A3, A4, R, Pw, cq, v1d, v2d, wt, g1, g2, (double)r.x, (double)r.y, (double)fs.x,
+                      (double)fs.y, wl >= 0 ? (double)gM[k] : 0.0);
+    };
+    if (act) {
+        if (pair_velocities<T>(n1)) {
+            int a = (2 * lane) % n1, b = (2 * lane) / n1;
+            const int da = (2 * kWave) % n1, db = (2 * kWave) / n1;
+            for (int k = 2 * lane; k < nv; k += 2 * kWave) {
+                accumulate(a, b, k, pin[row + k], fst[row + k]);
+                accumulate(a + 1, b, k + 1, pin[row + k + 1], fst[row + k + 1]);
+                a += da;
+                b += db;
+                if (a >= n1) {
+                    a -= n1;
+                    b++;
+                }
+            }
+        } else {
+            int a = lane % n1, b = lane / n1;
+            const int da = kWave % n1, db = kWave / n1;
+            for (int k = lane; k < nv; k += kWave) {
+                accumulate(a, b, k, pin[row + k], fst[row + k]);
+                a += da;
+                b += db;
+                if (a >= n1) {
+                    a -= n1;
+                    b++;
+                }
+            }
+        }
+    }
+    double acc[7] = {A0, A1, A2, A3, A4, R, Pw};
+    wave_sum<7>(acc);
+    if (act && lane == 0) adjoint_store(d, ac, wl, acc, d.aW[par] + 8 * c, d.Phi[par]);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,6 +779,14 @@ __global__ __launch_bounds__(kPatchBlock) void k_adjoint_sweep(DevSolve d, int p
     const int p = xcd_item(d.np, blockIdx.x);
     if (p < 0) return;
     adjoint_patch<T, kAdjointExchange<T>, SO>(d, p, par);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPatchBlock) void k_adjoint_moments(DevSolve d, int par)
+{
+    const int p = xcd_item(d.np, blockIdx.x);
+    if (p < 0) return;
+    adjoint_moments_patch<T>(d, p, par);
 }
 
 // one sweep of the primal-phase (or adjoint-phase) members of a batch that
@@ -909,6 +1020,13 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
         if (hipError_t e = hipGetLastError()) return e;
     }
     DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_wall_phi0<T>, dim3(d.nw), dim3(kBlock), 0, st, d, 0));
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_moments(const DevSolve &d, int par, hipStream_t st)
+{
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_adjoint_moments<T>, dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0, st, d,
+                                             par));
     return hipGetLastError();
 }
 

@@ -352,7 +352,14 @@ class Solver:
         raw = self.state_save(which)
         dt = np.float32 if self.precision == MIXED else np.float64
         n = self.nc * self.nv * 2
-        return np.frombuffer(raw.tobytes()[: n * np.dtype(dt).itemsize], dtype=dt).reshape(self.nc, self.nv, 2).astype(np.float64)
+        rows = np.frombuffer(raw, dtype=dt, count=n).reshape(self.nc, self.nv, 2)
+        return rows.astype(np.float64) if dt != np.float64 else rows
+
+    def state_load_array(self, which: int, rows: np.ndarray):
+        """Load f (STATE_F) or phi alone (STATE_PHI_ROWS) from a [nc][nv][2]
+        array, converted to the storage precision."""
+        dt = np.float32 if self.precision == MIXED else np.float64
+        self.state_load(which, np.ascontiguousarray(rows, dtype=dt))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -460,3 +460,27 @@ def poisson_stream(n: int, rate: float, seed: int = 0, mesh_choices=None,
         w, adj = serve_request(rid, rng, mesh_choices, vgrid_choices)
         out.append(Request(rid, tnow, w, adj))
     return out
+
+
+# --------------------------------------------------------------------------
+# Seeded state perturbations (for parity checks from a non-trivial state)
+# --------------------------------------------------------------------------
+
+def perturbation(shape, seed: int, amp: float = 0.2) -> np.ndarray:
+    """Seeded multiplicative noise 1 + amp * U(-1, 1) of the given shape
+    (float64): applied to a positive distribution it stays positive for
+    amp < 1."""
+    rng = np.random.default_rng(seed)
+    out = rng.random(shape)
+    out *= 2.0 * amp
+    out += 1.0 - amp
+    return out
+
+
+def noise_field(shape, seed: int, amp: float = 1.0) -> np.ndarray:
+    """Seeded additive noise amp * U(-1, 1) of the given shape (float64)."""
+    rng = np.random.default_rng(seed)
+    out = rng.random(shape)
+    out *= 2.0 * amp
+    out -= amp
+    return out

@@ -177,21 +177,54 @@ def serve(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_co
     backend.sync()
     wall = now()
     res = [results[r.rid] for r in order]
-    lat = np.array([x.latency for x in res if x.status in ("ok", "notconv")]) * 1e3
+
+    def latency_stats(keep):
+        lat = np.array([x.latency for x in res if keep(x)]) * 1e3
+        return {"count": int(len(lat)),
+                "solves_per_s": len(lat) / wall if wall > 0 else float("nan"),
+                "p50_ms": float(np.percentile(lat, 50)) if len(lat) else float("nan"),
+                "p99_ms": float(np.percentile(lat, 99)) if len(lat) else float("nan"),
+                "mean_ms": float(lat.mean()) if len(lat) else float("nan")}
+
+    finished = latency_stats(lambda x: x.status in ("ok", "notconv"))
     return {
         "results": res,
         "wall_s": wall,
-        "solves_per_s": len(lat) / wall if wall > 0 else float("nan"),
-        "p50_ms": float(np.percentile(lat, 50)) if len(lat) else float("nan"),
-        "p99_ms": float(np.percentile(lat, 99)) if len(lat) else float("nan"),
-        "mean_ms": float(lat.mean()) if len(lat) else float("nan"),
-        "completed": int(len(lat)),
+        # every finished solve (converged or stopped at the sweep cap)
+        "solves_per_s": finished["solves_per_s"],
+        "p50_ms": finished["p50_ms"],
+        "p99_ms": finished["p99_ms"],
+        "mean_ms": finished["mean_ms"],
+        "completed": finished["count"],
+        # the solves that reached their tolerances, and those stopped at the cap
+        "converged": latency_stats(lambda x: x.status == "ok"),
+        "capped": latency_stats(lambda x: x.status == "notconv"),
+        "capped_by_kn": capped_by_kn(order, res),
         "failed": sum(1 for x in res if x.status == "failed"),
         "notconv": sum(1 for x in res if x.status == "notconv"),
         "sweep_launches": launches,
         "peak_bytes": peak_used,
         "peak_resident": peak_resident,
     }
+
+
+KN_DECADES = ((1e-3, 1e-2), (1e-2, 1e-1), (1e-1, 1.0), (1.0, 10.0 + 1e-9))
+
+
+def capped_by_kn(requests: List, results: List[SolveResult]) -> Dict:
+    """Requests and sweep-capped solves per decade of Kn (requests that carry
+    a workload with a flow state; others are not counted)."""
+    out = {}
+    for lo, hi in KN_DECADES:
+        n = capped = 0
+        for req, r in zip(requests, results):
+            kn = getattr(getattr(getattr(req, "workload", None), "flow", None), "Kn", None)
+            if kn is None or not (lo <= kn < hi):
+                continue
+            n += 1
+            capped += r.status == "notconv"
+        out[f"[{lo:g},{min(hi, 10.0):g}]"] = {"requests": n, "capped": capped}
+    return out
 
 
 def serve_one_at_a_time(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_counter,

@@ -171,3 +171,26 @@ def test_server_admission_respects_budget():
     out = S.serve(reqs, be, S.ServeConfig(memory_budget=budget, sweeps_per_check=10, tol=1e-4, adjoint_tol=1e-4,
                                           max_iter=200), realtime=False)
     assert out["peak_bytes"] <= budget and out["completed"] == len(reqs)
+
+
+def test_autograd_device_alpha_and_unconverged_solves():
+    """A CUDA alpha gets its gradient on its own device and dtype (equal to
+    the host one); a solve left above its tolerance warns, or raises when
+    asked to."""
+    case, a0 = AG.circle_fourier_case(16, 8, 8, 5.0, Kn=1.0, Ma=0.5, r_outer=5.0, stretch=1.2,
+                                      options=AG.SolveOptions(max_iter=200, adjoint_max_iter=200, fixed_iters=True))
+    a_host = torch.tensor(a0 + 0.01, requires_grad=True)
+    AG.drag(a_host, case).backward()
+    a_dev = torch.tensor(a0 + 0.01, device="cuda", requires_grad=True)
+    AG.drag(a_dev, case).backward()
+    assert a_dev.grad.device == a_dev.device and a_dev.grad.dtype == a_dev.dtype
+    assert np.array_equal(a_dev.grad.cpu().numpy(), a_host.grad.numpy())
+    case.options = AG.SolveOptions(max_iter=40, adjoint_max_iter=40, tol=1e-12, adjoint_tol=1e-12, check_every=20)
+    a = torch.tensor(a0, requires_grad=True)
+    with pytest.warns(AG.NotConvergedWarning):
+        J = AG.drag(a, case)
+    with pytest.warns(AG.NotConvergedWarning):
+        J.backward()
+    case.options.on_notconv = "raise"
+    with pytest.raises(dvm.NotConverged):
+        AG.drag(torch.tensor(a0, requires_grad=True), case)

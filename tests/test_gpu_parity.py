@@ -14,7 +14,6 @@ largest velocity grid (128 x 128), both topologies (wake cut), tau =
 infinity, the heat objective and a hot wall.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
@@ -29,33 +28,9 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2501_00923_amd import dvm  # noqa: E402
+from _parity import _rel, _say, check_resid, check_sens  # noqa: E402
 
 NTHREADS = 16
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def _rel(a, b):
-    scale = np.max(np.abs(b))
-    return np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0)
-
-
-def _sens_scale(go):
-    """Common scale of the wall sensitivities: an element's S_x can be pure
-    rounding noise next to O(1) S_A (e.g. in free-molecular flow), so each
-    output is compared against the largest of them."""
-    return max(np.max(np.abs(go[k])) for k in ("S_A", "S_x", "S_n", "dJ_dnodes"))
-
-
-def _check_sens(gs, go, tol):
-    sc = _sens_scale(go)
-    for key in ("S_A", "S_x", "S_n", "dJ_dnodes"):
-        err = np.max(np.abs(gs[key] - go[key])) / sc
-        assert err <= tol, (key, err)
-    return max(np.max(np.abs(gs[k] - go[k])) / sc for k in ("S_A", "S_x", "S_n", "dJ_dnodes"))
 
 
 def _case(name):
@@ -101,16 +76,17 @@ def _run(wl, precision, n_primal, n_adjoint, n_params_jac=None):
     _say(f"[gpu] {wl.name} precision={precision} primal={n_primal} adjoint={n_adjoint}")
     s = dvm.Solver.from_workload(wl, precision=precision)
     s.primal_init()
-    s.primal_iterate(n_primal)
+    _, rps = s.primal_iterate(n_primal)
     o = oracle.Problem.from_workload(wl, nthreads=NTHREADS)
     o.primal_init()
-    o.primal_iterate(n_primal)
-    res = dict(s=s, o=o)
+    rpo = o.primal_iterate(n_primal)
+    res = dict(s=s, o=o, rp=(rps, rpo))
     if n_adjoint is not None:
         s.adjoint_init()
-        s.adjoint_iterate(n_adjoint)
+        _, ras = s.adjoint_iterate(n_adjoint)
         o.adjoint_init()
-        o.adjoint_iterate(n_adjoint)
+        rao = o.adjoint_iterate(n_adjoint)
+        res["ra"] = (ras, rao)
     return res
 
 
@@ -119,6 +95,8 @@ def test_fp64_primal_adjoint_sensitivity_parity(name):
     wl = _case(name)
     r = _run(wl, dvm.FP64, 37, 29)
     s, o = r["s"], r["o"]
+    check_resid(*r["rp"], label=f"{name} primal")
+    check_resid(*r["ra"], label=f"{name} adjoint")
     assert _rel(s.state_array(dvm.STATE_F), o.f) <= 1e-11
     assert _rel(s.moments(), o.W) <= 1e-11
     J, Cd = s.objective()
@@ -128,7 +106,7 @@ def test_fp64_primal_adjoint_sensitivity_parity(name):
         assert abs(Cd - Jo / o.cd_scale()) <= 1e-10 * abs(Jo / o.cd_scale()) + 1e-14
     assert _rel(s.state_array(dvm.STATE_PHI), o.phi) <= 1e-11
     gs, go = s.wall_sensitivity(), o.wall_sensitivity()
-    _check_sens(gs, go, 1e-10)
+    check_sens(gs, go, 1e-10, name)
     jac = wl.grid.wall_jac
     if jac.shape[-1]:
         da = s.param_sensitivity(jac)
@@ -149,7 +127,7 @@ def test_mixed_precision_parity(name):
     Jo = o.objective()
     eJ = abs(J - Jo) / abs(Jo)
     gs, go = s.wall_sensitivity(), o.wall_sensitivity()
-    eS = _check_sens(gs, go, 1e-3)
+    eS = check_sens(gs, go, 1e-3, f"{name} mixed")
     eM = _rel(s.mesh_sensitivity(), o.mesh_sensitivity())
     _say(f"[mixed] {name}: f {ef:.2e}  J {eJ:.2e}  sens {eS:.2e}  mesh sens {eM:.2e}")
     assert ef <= 2e-5 and eJ <= 2e-5 and eS <= 1e-3 and eM <= 1e-3
@@ -191,33 +169,16 @@ def test_c1_circle_full_size():
     assert rp < 1e-8 and ra < 1e-8
     o = oracle.Problem.from_workload(wl, nthreads=NTHREADS)
     o.primal_init()
-    o.primal_iterate(itp)
+    rpo = o.primal_iterate(itp)
     Jo = o.objective()
     o.adjoint_init()
-    o.adjoint_iterate(ita)
+    rao = o.adjoint_iterate(ita)
     go = np.einsum("md,mdp->p", o.wall_sensitivity()["dJ_dnodes"], wl.grid.wall_jac)
+    # the stopping test: the oracle's residual after the same sweeps is the
+    # GPU's (so both stop at the same sweep)
+    check_resid(rp, rpo, "c1 primal")
+    check_resid(ra, rao, "c1 adjoint")
+    assert rpo < 1e-8 and rao < 1e-8
     assert abs(J - Jo) <= 1e-10 * abs(Jo)
     assert abs(Cd - Jo / o.cd_scale()) <= 1e-10 * abs(Cd)
     assert _rel(g, go) <= 1e-10
-
-
-def test_c2_naca_full_size_sampled():
-    """NACA0012 C-grid 256x128, 48x48 Newton-Cotes grid, Kn 0.1, Ma 0.8, FP64
-    (the benchmark workload): 3 primal + 3 adjoint sweeps on both sides;
-    J, every cell's moments, sampled f / phi rows and all sensitivities,
-    the exact mesh sensitivity in every node included."""
-    wl = I.c2_naca()
-    r = _run(wl, dvm.FP64, 3, 3)
-    s, o = r["s"], r["o"]
-    J, _ = s.objective()
-    assert abs(J - o.objective()) <= 1e-10 * abs(o.objective())
-    assert _rel(s.moments(), o.W) <= 1e-11
-    rng = np.random.default_rng(0)
-    cells = np.unique(np.concatenate([rng.integers(0, s.nc, 64), o.mesh()["wall_cell"][:8],
-                                      [0, s.nc - 1, 255, 256]]))
-    fs = s.state_array(dvm.STATE_F)[cells]
-    ps = s.state_array(dvm.STATE_PHI)[cells]
-    assert _rel(fs, o.f[cells]) <= 1e-11
-    assert _rel(ps, o.phi[cells]) <= 1e-11
-    _check_sens(s.wall_sensitivity(), o.wall_sensitivity(), 1e-10)
-    assert _rel(s.mesh_sensitivity(), o.mesh_sensitivity()) <= 1e-10

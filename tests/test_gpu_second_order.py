@@ -13,7 +13,6 @@ with ragged tails, partial patches and tiles, the wake cut, one cell row
 objective on a hot wall, the largest velocity grid, limiter on and off.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
@@ -28,19 +27,10 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2501_00923_amd import dvm  # noqa: E402
+from _parity import _rel, _say, check_resid, check_sens  # noqa: E402
 
 NTHREADS = 16
 K = 5
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def _rel(a, b):
-    scale = np.max(np.abs(b))
-    return np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0)
 
 
 def _case(name):
@@ -73,31 +63,27 @@ def _case(name):
     raise KeyError(name)
 
 
-def _sens_err(gs, go):
-    sc = max(np.max(np.abs(go[k])) for k in ("S_A", "S_x", "S_n", "dJ_dnodes"))
-    return max(np.max(np.abs(gs[k] - go[k])) for k in ("S_A", "S_x", "S_n", "dJ_dnodes")) / sc
-
-
 def _run(wl, precision, n_primal, n_adjoint, limiter=True, k=K):
     _say(f"[gpu-so] {wl.name} precision={precision} limiter={limiter} K={k} primal={n_primal} adjoint={n_adjoint}")
     s = dvm.Solver.from_workload(wl, precision=precision, order=2,
                                  limiter=dvm.LIMITER_VENKAT if limiter else dvm.LIMITER_NONE, correction_every=k)
     s.primal_init()
-    s.primal_iterate(n_primal)
+    _, rps = s.primal_iterate(n_primal)
     o = oracle.Problem.from_workload(wl, nthreads=NTHREADS)
     o.set_scheme(2, limiter, k)
     o.primal_init()
-    o.primal_iterate(n_primal)
+    rpo = o.primal_iterate(n_primal)
     J, _ = s.objective()
     Jo = o.objective()
-    res = dict(s=s, o=o, J=J, Jo=Jo, f=s.state_array(dvm.STATE_F), W=s.moments())
+    res = dict(s=s, o=o, J=J, Jo=Jo, f=s.state_array(dvm.STATE_F), W=s.moments(), rp=(rps, rpo))
     if n_adjoint:
         s.adjoint_init()
-        s.adjoint_iterate(n_adjoint)
+        _, ras = s.adjoint_iterate(n_adjoint)
         o.adjoint_init()
-        o.adjoint_iterate(n_adjoint)
+        rao = o.adjoint_iterate(n_adjoint)
+        res["ra"] = (ras, rao)
         res["phi"] = s.state_array(dvm.STATE_PHI)
-        res["sens"] = _sens_err(s.wall_sensitivity(), o.wall_sensitivity())
+        res["gs"], res["go"] = s.wall_sensitivity(), o.wall_sensitivity()
         res["msens"] = _rel(s.mesh_sensitivity(), o.mesh_sensitivity())
     return res
 
@@ -114,9 +100,11 @@ def test_fp64_second_order_parity(name, limiter):
     o = r["o"]
     ef, eW, ep = _rel(r["f"], o.f), _rel(r["W"], o.W), _rel(r["phi"], o.phi)
     eJ = abs(r["J"] - r["Jo"]) / max(abs(r["Jo"]), 1e-300)
-    _say(f"[fp64-so] {name}: f {ef:.1e} W {eW:.1e} J {eJ:.1e} phi {ep:.1e} sens {r['sens']:.1e} "
-         f"mesh sens {r['msens']:.1e}")
-    assert ef <= 1e-11 and eW <= 1e-11 and ep <= 1e-11 and r["sens"] <= 1e-10 and r["msens"] <= 1e-10
+    _say(f"[fp64-so] {name}: f {ef:.1e} W {eW:.1e} J {eJ:.1e} phi {ep:.1e} mesh sens {r['msens']:.1e}")
+    check_resid(*r["rp"], label=f"{name} order-2 primal")
+    check_resid(*r["ra"], label=f"{name} order-2 adjoint")
+    check_sens(r["gs"], r["go"], 1e-10, f"{name} order 2")
+    assert ef <= 1e-11 and eW <= 1e-11 and ep <= 1e-11 and r["msens"] <= 1e-10
     assert abs(r["J"] - r["Jo"]) <= 1e-10 * abs(r["Jo"]) + 1e-14
 
 
@@ -127,27 +115,9 @@ def test_mixed_second_order_parity(name):
     o = r["o"]
     ef, ep = _rel(r["f"], o.f), _rel(r["phi"], o.phi)
     eJ = abs(r["J"] - r["Jo"]) / abs(r["Jo"])
-    _say(f"[mixed-so] {name}: f {ef:.2e} J {eJ:.2e} phi {ep:.2e} sens {r['sens']:.2e} mesh sens {r['msens']:.2e}")
-    assert ef <= 5e-5 and eJ <= 5e-5 and ep <= 5e-5 and r["sens"] <= 1e-3 and r["msens"] <= 1e-3
-
-
-def test_c2_naca_second_order_sampled():
-    """NACA0012 C-grid 256x128, 48x48 Newton-Cotes grid, Kn 0.1, Ma 0.8, FP64,
-    order 2 with the limiter: 7 primal sweeps (corrections at 0 and 5) and 6
-    adjoint sweeps on both sides; J, every cell's moments, sampled rows,
-    the wall sensitivities and the exact mesh sensitivity in every node."""
-    wl = I.c2_naca()
-    r = _run(wl, dvm.FP64, 7, 6)
-    o, s = r["o"], r["s"]
-    assert abs(r["J"] - r["Jo"]) <= 1e-10 * abs(r["Jo"])
-    assert _rel(r["W"], o.W) <= 1e-11
-    rng = np.random.default_rng(0)
-    cells = np.unique(np.concatenate([rng.integers(0, s.nc, 64), o.mesh()["wall_cell"][:8],
-                                      [0, s.nc - 1, 255, 256]]))
-    assert _rel(r["f"][cells], o.f[cells]) <= 1e-11
-    assert _rel(r["phi"][cells], o.phi[cells]) <= 1e-11
-    assert r["sens"] <= 1e-10
-    assert r["msens"] <= 1e-10
+    _say(f"[mixed-so] {name}: f {ef:.2e} J {eJ:.2e} phi {ep:.2e} mesh sens {r['msens']:.2e}")
+    check_sens(r["gs"], r["go"], 1e-3, f"{name} order 2 mixed")
+    assert ef <= 5e-5 and eJ <= 5e-5 and ep <= 5e-5 and r["msens"] <= 1e-3
 
 
 def test_second_order_checkpoint_continues_bitwise():
@@ -209,11 +179,13 @@ def test_c1_circle_second_order_converged():
     o = oracle.Problem.from_workload(wl, nthreads=NTHREADS)
     o.set_scheme(2, True, 10)
     o.primal_init()
-    o.primal_iterate(itp)
+    rpo = o.primal_iterate(itp)
     Jo = o.objective()
     o.adjoint_init()
-    o.adjoint_iterate(ita)
+    rao = o.adjoint_iterate(ita)
     go = np.einsum("md,mdp->p", o.wall_sensitivity()["dJ_dnodes"], wl.grid.wall_jac)
+    check_resid(rp, rpo, "c1 order-2 primal")
+    check_resid(ra, rao, "c1 order-2 adjoint")
     assert abs(J - Jo) <= 1e-10 * abs(Jo)
     assert abs(Cd - Jo / o.cd_scale()) <= 1e-10 * abs(Cd)
     assert _rel(g, go) <= 1e-10

@@ -91,3 +91,24 @@ def test_poisson_stream_is_seeded():
     assert [r.workload.flow.Kn for r in a] == [r.workload.flow.Kn for r in b]
     assert all(np.array_equal(x.workload.grid.nodes, y.workload.grid.nodes) for x, y in zip(a, b))
     assert all(1e-3 <= r.workload.flow.Kn <= 10 and 0.3 <= r.workload.flow.Ma <= 2.0 for r in a)
+
+
+def test_converged_and_capped_solves_are_reported_apart():
+    """Solves stopped at the sweep cap are counted apart from converged ones
+    (solves/s and latency of each, and the cap rate per decade of Kn)."""
+    reqs = _stream(40, rate=400.0, seed=5)
+    for r in reqs:
+        r.workload.flow = SimpleNamespace(Kn=10.0 ** (-3 + 4 * (r.rid % 8) / 8))
+    fb = S.FakeBackend(cost_per_pair=2e-12)
+    cfg = S.ServeConfig(memory_budget=10 ** 12, sweeps_per_check=10, tol=1e-6, adjoint_tol=1e-6, max_iter=60)
+    out = S.serve(reqs, fb, cfg, clock=fb.clock, sleep=fb.sleep)
+    conv = [r for r in out["results"] if r.status == "ok"]
+    capped = [r for r in out["results"] if r.status == "notconv"]
+    assert conv and capped
+    assert out["converged"]["count"] == len(conv) and out["capped"]["count"] == len(capped)
+    assert out["completed"] == len(conv) + len(capped)
+    assert out["converged"]["p50_ms"] == pytest.approx(1e3 * np.percentile([r.latency for r in conv], 50))
+    assert out["converged"]["solves_per_s"] == pytest.approx(len(conv) / out["wall_s"])
+    by_kn = out["capped_by_kn"]
+    assert sum(v["requests"] for v in by_kn.values()) == len(reqs)
+    assert sum(v["capped"] for v in by_kn.values()) == len(capped)

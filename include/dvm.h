@@ -262,6 +262,20 @@ typedef struct dvm_batch dvm_batch;
 size_t dvm_batch_work_bytes(int n, int64_t total_cells);
 int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t work_bytes,
                      void *hip_stream, dvm_batch **out);
+/* Allocation-free variant of dvm_batch_create, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same batch, whose launch tables
+ * live in a fixed device array the library holds on each GPU it runs on
+ * (8 MiB, until the process ends) instead of a caller-owned work buffer;
+ * they are built there by a kernel on hip_stream, with no device or host
+ * allocation.  At most 64 members, and tables of at most 8 MiB (about 2 M
+ * patches, i.e. some 8 M cells over all members); larger batches give
+ * DVM_EINVAL.  One such batch may exist per device at a time: a second
+ * create on the same device gives DVM_ESTATE until dvm_batch_destroy of the
+ * first.  All calls on one device share the array, so concurrent use from
+ * several host threads on one device races.  run, residual and destroy as
+ * for dvm_batch_create; results are bitwise those of dvm_batch_create. */
+int dvm_batch_create_static(dvm_solver *const *solvers, int n, void *hip_stream, dvm_batch **out);
 int dvm_batch_run(dvm_batch *b, int iters);
 /* Residual (as in *_iterate) of each member's last sweep into resid[n].
  * Synchronises the batch's stream. */

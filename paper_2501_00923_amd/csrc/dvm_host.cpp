@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/dvm.h"
@@ -581,7 +582,11 @@ std::vector<T> convert(const std::vector<double> &v)
 // batch
 // ---------------------------------------------------------------------------
 struct dvm_batch {
-    std::vector<dvm_solver *> members;
+    std::vector<dvm_solver *> owned;     // member list of a dvm_batch_create batch
+    dvm_solver *fixed[dvm::kStaticBatchMaxMembers] = {};   // member list of an allocation-free batch
+    dvm_solver **members = nullptr;
+    int n = 0;
+    int static_dev = -1;                 // >= 0: the allocation-free batch of this device
     char *work = nullptr;
     hipStream_t stream = nullptr;
     int nblocks = 0, mixed = 0;
@@ -1141,6 +1146,8 @@ void dvm_solver_destroy(dvm_solver *s) { delete s; }
 
 // ---- batch ----------------------------------------------------------------
 
+static int batch_group(const dvm_solver *s) { return 2 * s->phase + (s->order == 2 ? 1 : 0); }
+
 static void batch_layout(int n, int64_t nblocks, dvm_batch *b, size_t *total)
 {
     size_t cur = 0;
@@ -1176,12 +1183,11 @@ size_t dvm_batch_work_bytes(int n, int64_t total_cells)
     return t;
 }
 
-int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t work_bytes, void *hip_stream,
-                     dvm_batch **out)
+// Members of one precision, each bound, in a phase and listed once; the
+// workgroups of the four launch groups (primal first- and second-order
+// members, adjoint first- and second-order members).
+static int batch_check(dvm_solver *const *solvers, int n, int *mixed_out, int64_t per_group[4])
 {
-    if (!out || !solvers || n <= 0 || !work_dev) return fail(DVM_EINVAL, "null argument or empty batch");
-    *out = nullptr;
-    if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(DVM_EINVAL, "work buffer not 256-byte aligned");
     int mixed = -1;
     for (int i = 0; i < n; i++) {
         const dvm_solver *s = solvers[i];
@@ -1200,11 +1206,24 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
     // share of every member's work, whatever the mix of mesh and
     // velocity-grid sizes, and its L2 sees contiguous tiles as in a
     // single-solve sweep.
-    auto group = [](const dvm_solver *s) { return 2 * s->phase + (s->order == 2 ? 1 : 0); };
-    int64_t per_group[4] = {0, 0, 0, 0};
-    for (int i = 0; i < n; i++) per_group[group(solvers[i])] += (solvers[i]->np + 7) / 8;
+    for (int g = 0; g < 4; g++) per_group[g] = 0;
+    for (int i = 0; i < n; i++) per_group[batch_group(solvers[i])] += (solvers[i]->np + 7) / 8;
+    if (8 * (per_group[0] + per_group[1] + per_group[2] + per_group[3]) > INT32_MAX)
+        return fail(DVM_EINVAL, "batch too large");
+    *mixed_out = mixed;
+    return DVM_OK;
+}
+
+int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t work_bytes, void *hip_stream,
+                     dvm_batch **out)
+{
+    if (!out || !solvers || n <= 0 || !work_dev) return fail(DVM_EINVAL, "null argument or empty batch");
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(DVM_EINVAL, "work buffer not 256-byte aligned");
+    int mixed = -1;
+    int64_t per_group[4];
+    if (int e = batch_check(solvers, n, &mixed, per_group)) return e;
     const int64_t nblocks = 8 * (per_group[0] + per_group[1] + per_group[2] + per_group[3]);
-    if (nblocks > INT32_MAX) return fail(DVM_EINVAL, "batch too large");
     size_t need;
     try {
         auto *b = new dvm_batch;
@@ -1213,7 +1232,9 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
             delete b;
             return fail(DVM_ENOMEM, "batch work buffer of %zu bytes < %zu bytes", work_bytes, need);
         }
-        b->members.assign(solvers, solvers + n);
+        b->owned.assign(solvers, solvers + n);
+        b->members = b->owned.data();
+        b->n = n;
         b->work = static_cast<char *>(work_dev);
         b->stream = static_cast<hipStream_t>(hip_stream);
         b->nblocks = (int)nblocks;
@@ -1232,7 +1253,7 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
             std::vector<int64_t> pos(8, 0);   // next slot of each XCD
             for (int i = 0; i < n; i++) {
                 const dvm_solver *s = solvers[i];
-                if (group(s) != gr) continue;
+                if (batch_group(s) != gr) continue;
                 const int64_t per = (s->np + 7) / 8;
                 for (int x = 0; x < 8; x++) {
                     const int64_t p0 = x * per, p1 = std::min<int64_t>(s->np, p0 + per);
@@ -1268,6 +1289,74 @@ int dvm_batch_create(dvm_solver *const *solvers, int n, void *work_dev, size_t w
     }
 }
 
+// The allocation-free batch: at most one per device at a time, its handle
+// and member list in static host storage, its tables in the device's fixed
+// scratch array (built there by a kernel).
+namespace {
+constexpr int kStaticDevices = 64;
+dvm_batch g_static_batch[kStaticDevices];
+bool g_static_live[kStaticDevices] = {};
+std::mutex g_static_mu;
+}  // namespace
+
+int dvm_batch_create_static(dvm_solver *const *solvers, int n, void *hip_stream, dvm_batch **out)
+{
+    if (!out || !solvers || n <= 0) return fail(DVM_EINVAL, "null argument or empty batch");
+    *out = nullptr;
+    if (n > dvm::kStaticBatchMaxMembers)
+        return fail(DVM_EINVAL, "%d members: the allocation-free batch takes at most %d", n,
+                    dvm::kStaticBatchMaxMembers);
+    int mixed = -1;
+    int64_t per_group[4];
+    if (int e = batch_check(solvers, n, &mixed, per_group)) return e;
+    const int64_t nblocks = 8 * (per_group[0] + per_group[1] + per_group[2] + per_group[3]);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticDevices) return fail(DVM_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_live[dev])
+        return fail(DVM_ESTATE, "an allocation-free batch already exists on device %d (destroy it first)", dev);
+    dvm_batch *b = &g_static_batch[dev];
+    size_t need;
+    batch_layout(n, nblocks, b, &need);
+    if (need > dvm::kStaticBatchBytes)
+        return fail(DVM_EINVAL, "the batch's tables need %zu bytes; the allocation-free batch holds %zu", need,
+                    dvm::kStaticBatchBytes);
+    char *w = nullptr;
+    HIP_OK(dvm::static_batch_scratch(&w));
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int32_t par[dvm::kStaticBatchMaxMembers], phase[dvm::kStaticBatchMaxMembers];
+    for (int i = 0; i < n; i++) {
+        phase[i] = solvers[i]->phase;
+        par[i] = phase[i] == 0 ? solvers[i]->fpar : solvers[i]->ppar;
+        HIP_OK(hipMemcpyAsync(w + b->off_tab + i * sizeof(dvm::DevSolve), &solvers[i]->dev, sizeof(dvm::DevSolve),
+                              hipMemcpyHostToDevice, st));
+    }
+    HIP_OK(hipMemcpyAsync(w + b->off_par, par, n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(w + b->off_phase, phase, n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    int nbg[4];
+    for (int g = 0; g < 4; g++) nbg[g] = (int)(8 * per_group[g]);
+    HIP_OK(dvm::launch_batch_tables(reinterpret_cast<const dvm::DevSolve *>(w + b->off_tab),
+                                    reinterpret_cast<const int32_t *>(w + b->off_phase), n, nbg,
+                                    reinterpret_cast<int32_t *>(w + b->off_bs), reinterpret_cast<int32_t *>(w + b->off_bc),
+                                    st));
+    HIP_OK(hipStreamSynchronize(st));   // par, phase and the solver structs must outlive their copies
+    for (int i = 0; i < n; i++) b->fixed[i] = solvers[i];
+    b->members = b->fixed;
+    b->n = n;
+    b->static_dev = dev;
+    b->work = w;
+    b->stream = st;
+    b->nblocks = (int)nblocks;
+    for (int g = 0; g < 4; g++) b->nb_group[g] = nbg[g];
+    b->mixed = mixed;
+    b->step = 0;
+    for (int i = 0; i < n; i++) solvers[i]->in_batch = 1;
+    g_static_live[dev] = true;
+    *out = b;
+    return DVM_OK;
+}
+
 int dvm_batch_run(dvm_batch *b, int iters)
 {
     if (!b) return fail(DVM_EINVAL, "null batch");
@@ -1280,7 +1369,8 @@ int dvm_batch_run(dvm_batch *b, int iters)
     for (int it = 0; it < iters; it++) {
         // second-order members: the held correction of the current state,
         // on the same cadence as a single solve's
-        for (dvm_solver *s : b->members) {
+        for (int m = 0; m < b->n; m++) {
+            dvm_solver *s = b->members[m];
             if (s->order != 2) continue;
             const int ph = s->phase;
             if (!s->corr_ok[ph] || s->since[ph] == s->kcorr) {
@@ -1302,7 +1392,8 @@ int dvm_batch_run(dvm_batch *b, int iters)
         }
     }
     b->step += iters;
-    for (dvm_solver *s : b->members) {
+    for (int m = 0; m < b->n; m++) {
+        dvm_solver *s = b->members[m];
         if (s->phase == 0)
             s->fpar ^= (iters & 1);
         else
@@ -1315,12 +1406,21 @@ int dvm_batch_run(dvm_batch *b, int iters)
 int dvm_batch_residual(dvm_batch *b, double *resid)
 {
     if (!b || !resid) return fail(DVM_EINVAL, "null argument");
-    const int n = (int)b->members.size();
+    const int n = b->n;
     double *out = reinterpret_cast<double *>(b->work + b->off_out);
     HIP_OK(dvm::launch_batch_residual(reinterpret_cast<const dvm::DevSolve *>(b->work + b->off_tab), n, out,
                                       b->stream));
-    std::vector<double> v(2 * (size_t)n);
-    HIP_OK(hipMemcpyAsync(v.data(), out, v.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    double small[2 * dvm::kStaticBatchMaxMembers];
+    std::vector<double> big;
+    if (n > dvm::kStaticBatchMaxMembers) {
+        try {
+            big.resize(2 * (size_t)n);
+        } catch (const std::bad_alloc &) {
+            return fail(DVM_ENOMEM, "out of host memory");
+        }
+    }
+    double *v = n > dvm::kStaticBatchMaxMembers ? big.data() : small;
+    HIP_OK(hipMemcpyAsync(v, out, 2 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIP_OK(hipStreamSynchronize(b->stream));
     for (int i = 0; i < n; i++) resid[i] = rel_norm(v[2 * i], v[2 * i + 1]);
     return DVM_OK;
@@ -1329,7 +1429,14 @@ int dvm_batch_residual(dvm_batch *b, double *resid)
 void dvm_batch_destroy(dvm_batch *b)
 {
     if (!b) return;
-    for (dvm_solver *s : b->members) s->in_batch = 0;
+    for (int m = 0; m < b->n; m++) b->members[m]->in_batch = 0;
+    if (b->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_live[b->static_dev] = false;
+        b->n = 0;
+        b->members = nullptr;
+        return;
+    }
     delete b;
 }
 

@@ -114,6 +114,20 @@ hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int
                         const int32_t *par0, int step, int nblocks, int mixed, int adjoint, int so, hipStream_t st);
 hipError_t launch_batch_residual(const DevSolve *tab, int n, double *out, hipStream_t st);
 
+// The allocation-free batch (dvm_batch_create_static) keeps its launch
+// tables in one fixed device array per GPU, of kStaticBatchBytes, for at
+// most kStaticBatchMaxMembers members.  static_batch_scratch gives the
+// current device's copy of the array (its address is looked up once per
+// device); launch_batch_tables writes the per-workgroup (member, patch) map
+// of the four groups (group g = 2 * phase + (order == 2), nb_group[g]
+// workgroups each, in that order) from the member table and phases, in the
+// layout dvm_batch_create builds on the host.
+constexpr size_t kStaticBatchBytes = size_t(8) << 20;
+constexpr int kStaticBatchMaxMembers = 64;
+hipError_t static_batch_scratch(char **out);
+hipError_t launch_batch_tables(const DevSolve *tab, const int32_t *phase, int n, const int *nb_group,
+                               int32_t *blk_solve, int32_t *blk_patch, hipStream_t st);
+
 
 // radial-basis-function mesh motion (Wendland C0, support 1/inv_r):
 // apply: out[n] = wall[widx[n]] for wall nodes, else x0[n] + sum_w gamma[w]

@@ -23,6 +23,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "dvm_device.h"
 
@@ -815,6 +816,69 @@ __global__ __launch_bounds__(kPatchBlock) void k_batch_adjoint(const DevSolve *_
     adjoint_patch<T, kAdjointExchange<T>, SO>(tab[s], blk_patch[blockIdx.x], (par0[s] + step) & 1);
 }
 
+// Block tables of a batch on the device (the allocation-free batch): block
+// b of group g runs on XCD x = b % 8 and is the (b / 8)-th slot of that
+// XCD's column, which holds, member after member of the group in table
+// order, the x-th eighth of each member's patches (ceil(np / 8) of them, the
+// last eighth possibly shorter); slots past the last member are padding (-1).
+// The same map as the host-built one of dvm_batch_create.
+struct BatchGroups {
+    int nb[4];
+};
+
+__global__ __launch_bounds__(kBlock) void k_batch_tables(const DevSolve *__restrict__ tab,
+                                                         const int32_t *__restrict__ phase, int n, BatchGroups grp,
+                                                         int32_t *__restrict__ blk_solve,
+                                                         int32_t *__restrict__ blk_patch)
+{
+    const int total = grp.nb[0] + grp.nb[1] + grp.nb[2] + grp.nb[3];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= total) return;
+    int g = 0, local = b;
+    while (local >= grp.nb[g]) {
+        local -= grp.nb[g];
+        g++;
+    }
+    const int x = local & 7;
+    int slot = local >> 3, solve = -1, patch = 0;
+    for (int i = 0; i < n; i++) {
+        if (2 * phase[i] + (tab[i].order == 2 ? 1 : 0) != g) continue;
+        const int np = tab[i].np, per = (np + 7) / 8;
+        const int p0 = x * per, cnt = max(0, min(np, p0 + per) - p0);
+        if (slot < cnt) {
+            solve = i;
+            patch = p0 + slot;
+            break;
+        }
+        slot -= cnt;
+    }
+    blk_solve[b] = solve;
+    blk_patch[b] = solve >= 0 ? patch : 0;
+}
+
+// The fixed device array of the allocation-free batch (one per GPU the
+// library runs on; held until the process ends).  Host code reaches it only
+// through the address static_batch_scratch looks up for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticBatchBytes];
+
+hipError_t static_batch_scratch(char **out)
+{
+    constexpr int kMaxDevices = 64;
+    static char *addr[kMaxDevices] = {};
+    static std::mutex mu;
+    int dev = 0;
+    if (hipError_t e = hipGetDevice(&dev)) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) return e;
+        addr[dev] = static_cast<char *>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
 // f = far-field Maxwellian everywhere (storage type)
 template <typename T>
 __global__ void k_fill_fd(DevSolve d, int par)
@@ -1057,6 +1121,21 @@ hipError_t launch_batch(const DevSolve *tab, const int32_t *blk_solve, const int
     else
         DVM_DISPATCH(mixed, hipLaunchKernelGGL((k_batch_primal<T, false>), dim3(nblocks), dim3(kPatchBlock), 0, st,
                                                tab, blk_solve, blk_patch, par0, step));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tables(const DevSolve *tab, const int32_t *phase, int n, const int *nb_group,
+                               int32_t *blk_solve, int32_t *blk_patch, hipStream_t st)
+{
+    BatchGroups grp;
+    int total = 0;
+    for (int g = 0; g < 4; g++) {
+        grp.nb[g] = nb_group[g];
+        total += nb_group[g];
+    }
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_tables, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, st, tab, phase, n, grp,
+                       blk_solve, blk_patch);
     return hipGetLastError();
 }
 

@@ -38,7 +38,8 @@ EXPORTED = [
     "dvm_adjoint_init", "dvm_adjoint_iterate", "dvm_adjoint_sweeps",
     "dvm_wall_sensitivity", "dvm_param_sensitivity", "dvm_mesh_sensitivity",
     "dvm_state_bytes", "dvm_state_save", "dvm_state_load", "dvm_state_copy",
-    "dvm_batch_work_bytes", "dvm_batch_create", "dvm_batch_run", "dvm_batch_residual", "dvm_batch_destroy",
+    "dvm_batch_work_bytes", "dvm_batch_create", "dvm_batch_create_static", "dvm_batch_run", "dvm_batch_residual",
+    "dvm_batch_destroy",
     "dvm_solver_iterations", "dvm_solver_phase", "dvm_last_error", "dvm_solver_destroy",
     "dvm_cst_eval", "dvm_cst_fit", "dvm_volume_constraint",
     "dvm_deform_create", "dvm_deform_workspace_bytes", "dvm_deform_bind", "dvm_deform_apply",
@@ -107,6 +108,7 @@ def lib():
         "dvm_state_copy": (i32, [vp, vp, i32]),
         "dvm_batch_work_bytes": (sz, [i32, i64]),
         "dvm_batch_create": (i32, [vp, i32, vp, sz, vp, pvp]),
+        "dvm_batch_create_static": (i32, [vp, i32, vp, pvp]),
         "dvm_batch_run": (i32, [vp, i32]),
         "dvm_batch_residual": (i32, [vp, vp]),
         "dvm_batch_destroy": (None, [vp]),
@@ -368,19 +370,26 @@ class Solver:
 
 
 class Batch:
-    """A group of bound solvers advanced together (one launch per sweep)."""
+    """A group of bound solvers advanced together (one launch per sweep).
+    static=True: the allocation-free form (dvm_batch_create_static), whose
+    launch tables live in the library's fixed per-device array."""
 
-    def __init__(self, solvers: Sequence[Solver], stream=None, work=None):
+    def __init__(self, solvers: Sequence[Solver], stream=None, work=None, static: bool = False):
         self.solvers = list(solvers)
         n = len(self.solvers)
-        total = sum(s.nc for s in self.solvers)
-        need = int(lib().dvm_batch_work_bytes(n, total))
-        self.work = alloc_device(need) if work is None else work
         arr = (C.c_void_p * n)(*[s._h.value for s in self.solvers])
         self._arr = arr
         st = current_stream_handle() if stream is None else C.c_void_p(int(stream))
         h = C.c_void_p()
-        _check(lib().dvm_batch_create(arr, n, C.c_void_p(self.work.data_ptr()), self.work.numel(), st, C.byref(h)))
+        if static:
+            self.work = None
+            _check(lib().dvm_batch_create_static(arr, n, st, C.byref(h)))
+        else:
+            total = sum(s.nc for s in self.solvers)
+            need = int(lib().dvm_batch_work_bytes(n, total))
+            self.work = alloc_device(need) if work is None else work
+            _check(lib().dvm_batch_create(arr, n, C.c_void_p(self.work.data_ptr()), self.work.numel(), st,
+                                          C.byref(h)))
         self._h = h
 
     def run(self, iters: int):

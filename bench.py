@@ -113,6 +113,69 @@ def run_gpu(wl, precision, sweeps, steps, warmup, order=1, correction_every=40):
     return out
 
 
+def batch_roofline(n_members, seed, sweeps=20, warmup=3):
+    """Achieved HBM rate of the batched sweep kernels on a serving mix: the
+    first `n_members` requests of the seeded serving stream (circle / NACA,
+    meshes 64x32 .. 256x128, 16^2 .. 64^2 velocities), FP32 state.  Three
+    batches are timed with HIP events on their stream: every member in its
+    primal phase (k_batch_primal alone), the members that ask for the
+    adjoint in their adjoint phase (k_batch_adjoint alone), and the serving
+    mix (those in the adjoint phase, the others primal: both kernels per
+    sweep).  Algorithmic bytes per sweep: 16 B per primal and 24 B per
+    adjoint (cell, velocity) pair of the members."""
+    import torch
+
+    from paper_2501_00923_amd import dvm
+    from paper_2501_00923_amd import inputs as I
+
+    reqs = I.poisson_stream(n_members, 1.0, seed=seed)
+
+    def members(adjoint_of):
+        out = []
+        for r in reqs:
+            if adjoint_of == "only" and not r.want_adjoint:
+                continue
+            s = dvm.Solver.from_workload(r.workload, precision=dvm.MIXED, want_adjoint=r.want_adjoint)
+            s.primal_init()
+            if r.want_adjoint and adjoint_of in ("only", "mix"):
+                s.adjoint_init()
+            out.append(s)
+        return out
+
+    def timed(sol):
+        b = dvm.Batch(sol)
+        b.run(warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        b.run(sweeps)
+        e1.record()
+        torch.cuda.synchronize()
+        b.close()
+        ms = e0.elapsed_time(e1) / sweeps
+        nbytes = sum(s.nc * s.nv * (24 if s.phase == 1 else 16) for s in sol)
+        pairs = sum(s.nc * s.nv for s in sol)
+        return {"members": len(sol), "pairs": pairs, "ms_per_sweep": ms, "algorithmic_bytes_per_sweep": nbytes,
+                "achieved": nbytes / (ms * 1e-3) / 1e9, "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "updates_per_s": pairs / (ms * 1e-3)}
+
+    out = {}
+    for key, kind, kern in (("primal", "none", "k_batch_primal<float, false>"),
+                            ("adjoint", "only", "k_batch_adjoint<float, false>"),
+                            ("mix", "mix", "both")):
+        sol = members(kind)
+        out[key] = timed(sol)
+        out[key]["kernel"] = kern
+        print(f"[bench] batch {key}: {out[key]['members']} members, {out[key]['ms_per_sweep']:.3f} ms/sweep, "
+              f"{out[key]['achieved']:.0f} GB/s ({out[key]['frac']:.3f} of peak)", file=sys.stderr, flush=True)
+        del sol
+        torch.cuda.empty_cache()
+    out["unit"] = "GB/s"
+    out["peak"] = HBM_PEAK_GBS
+    out["workload"] = f"first {n_members} requests of the serving stream (seed {seed}), FP32 state"
+    return out
+
+
 def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every):
     """Solve server on a seeded request stream (circle / NACA shapes, meshes
     {64x32, 128x64, 256x128}, velocity grids {16^2, 32^2, 64^2} on [-6, 6],
@@ -415,31 +478,48 @@ def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius, order=1, limite
 
 
 def stream_reference(nbytes_total):
-    """Device streaming rates of plain torch elementwise kernels moving about
-    `nbytes_total` bytes per launch in FP64, with the read/write mixes of the
-    sweeps: 2 reads + 1 write (c = a + b: the FP64 adjoint reads phi and f,
-    writes phi) and 1 read + 1 write (c = a: the primal reads f, writes f).
-    GB/s of algorithmic bytes, HIP events over 20 launches after 3 warm-ups."""
+    """Plain HIP streams (csrc/dvm_stream.hip) with the read/write mixes of
+    the sweeps, moving `nbytes_total` bytes per launch: 1 read + 1 write
+    (c = a: the primal), 2 reads + 1 write (c = a + b: the adjoint), and a
+    pure write and a pure read stream; 16-byte loads per lane and
+    non-temporal stores as in the sweeps.  GB/s of bytes moved, HIP events
+    over 20 launches after 3 warm-ups, best over grid-stride launches of
+    2048 to 16384 workgroups of 256 threads and a one-pass launch, with and
+    without non-temporal stores."""
+    import ctypes as C
+
     import torch
 
+    from paper_2501_00923_amd import build as B
+
+    lib = C.CDLL(B.STREAM_LIB)
+    lib.dvm_stream_time.restype = C.c_int
+    lib.dvm_stream_time.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int,
+                                    C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_float)]
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     out = {}
-    for name, nin in (("read2_write1", 2), ("read1_write1", 1)):
-        n = int(nbytes_total // (8 * (nin + 1)))
-        a = torch.ones(n, dtype=torch.float64, device="cuda")
-        b = torch.ones(n, dtype=torch.float64, device="cuda") if nin == 2 else None
-        c = torch.empty_like(a)
-        run = (lambda: torch.add(a, b, out=c)) if nin == 2 else (lambda: c.copy_(a))
-        for _ in range(3):
-            run()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(20):
-            run()
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) / 20 * 1e-3
-        out[name] = {"GB_per_s": 8 * n * (nin + 1) / t / 1e9, "bytes_per_launch": 8 * n * (nin + 1)}
+    for name, kind, narr in (("read1_write1", 0, 2), ("read2_write1", 1, 3), ("write_only", 2, 1),
+                             ("read_only", 3, 1)):
+        nb = (int(nbytes_total // narr) // 4096) * 4096
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.ones(nb // 4, dtype=torch.float32, device="cuda") if kind == 1 else a
+        c = torch.empty(nb // 4, dtype=torch.float32, device="cuda") if kind != 3 else \
+            torch.empty(16384, dtype=torch.float32, device="cuda")
+        best = None
+        for blocks in (2048, 4096, 8192, 16384, 0):
+            for nt in (1, 0):
+                if kind == 3 and (blocks == 0 or nt == 0):
+                    continue
+                ms = C.c_float()
+                rc = lib.dvm_stream_time(kind, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                         C.c_void_p(c.data_ptr()), nb, blocks, nt, 3, 20, st, C.byref(ms))
+                if rc != 0:
+                    raise RuntimeError(f"stream reference kernel failed ({rc})")
+                gbs = nb * narr / (ms.value * 1e-3) / 1e9
+                if best is None or gbs > best["GB_per_s"]:
+                    best = {"GB_per_s": gbs, "bytes_per_launch": nb * narr,
+                            "workgroups": blocks or "one pass", "nontemporal_stores": bool(nt)}
+        out[name] = best
         del a, b, c
     torch.cuda.empty_cache()
     return out
@@ -550,6 +630,10 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=64,
                     help="requests in the solve-server leg (0 skips it; 512 is the full stream)")
     ap.add_argument("--serving-cap", type=int, default=1000, help="sweep cap per phase per request")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 256x128 C-grid with 64x64 sinh velocities (134 M pairs) leg")
+    ap.add_argument("--batch-members", type=int, default=24,
+                    help="requests of the serving stream in the batched-sweep roofline (0 skips it)")
     ap.add_argument("--serving-tol", type=float, default=1e-5)
     ap.add_argument("--serving-seed", type=int, default=0)
     ap.add_argument("--precision-sweep", action="store_true",
@@ -738,6 +822,29 @@ def main():
                                "J_rel_err_vs_fp64": abs(r2m["J"] - r2["J"]) / abs(r2["J"]),
                                "dtype": "f32 state / f64 moments and limiter"}
             print(f"[bench] second order mixed {r2m['updates_per_s']:.3e} upd/s", file=sys.stderr, flush=True)
+    c3 = None
+    if not args.no_c3:
+        wl3 = I.c3_naca_sinh(0.1)
+        print(f"[bench] {wl3.name}: FP64 and mixed", file=sys.stderr, flush=True)
+        r3 = run_gpu(wl3, dvm.FP64, args.sweeps, max(2, args.steps // 2), args.warmup)
+        r3m = run_gpu(wl3, dvm.MIXED, args.sweeps, max(2, args.steps // 2), args.warmup)
+        p3 = r3["pairs"]
+        c3 = {"workload": wl3.name, "cells": wl3.grid.ni * wl3.grid.nj, "velocities": wl3.vgrid.n1 * wl3.vgrid.n2,
+              "pairs": p3, "fp64": {"value": r3["updates_per_s"], "ms_per_step": r3["ms_per_step"]},
+              "mixed": {"value": r3m["updates_per_s"], "ms_per_step": r3m["ms_per_step"],
+                        "J_rel_err_vs_fp64": abs(r3m["J"] - r3["J"]) / abs(r3["J"])}, "roofline": {}}
+        for prec, rr, mixed_ in (("fp64", r3, False), ("mixed", r3m, True)):
+            for kind in ("primal", "adjoint"):
+                t = rr[f"{kind}_sweep_ms"] * 1e-3
+                bb = bytes_per_update(kind, mixed_) * p3
+                c3["roofline"][f"{kind}_{prec}"] = {
+                    "kernel": f"k_{kind}_sweep<{'float' if mixed_ else 'double'}>", "avg_launch_ms": t * 1e3,
+                    "algorithmic_bytes_per_launch": bb, "achieved": bb / t / 1e9, "frac": bb / t / 1e9 / HBM_PEAK_GBS}
+        print(f"[bench] C3 fp64 {r3['updates_per_s']:.3e} upd/s, mixed {r3m['updates_per_s']:.3e} upd/s",
+              file=sys.stderr, flush=True)
+    batch_roof = None
+    if args.batch_members > 0:
+        batch_roof = batch_roofline(args.batch_members, args.serving_seed)
     serving = None
     if args.serving_requests > 0:
         print(f"[bench] serving leg: {args.serving_requests} requests", file=sys.stderr, flush=True)
@@ -768,7 +875,8 @@ def main():
                    "sweeps_per_step": {"primal": args.sweeps, "adjoint": args.sweeps},
                    "Kn": wl.flow.Kn, "Ma": wl.flow.Ma, "shape_params": int(wl.grid.wall_jac.shape[-1]),
                    "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "second_order": second, "serving": serving,
+        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "c3": c3, "batched_sweep_roofline": batch_roof,
+        "second_order": second, "serving": serving,
         "optimization": optimization, "J": r64["J"], "Cd": r64["Cd"],
     }
     print(json.dumps(line))

@@ -20,10 +20,15 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", "-ffp
          "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
+# the streaming reference kernels of the benchmark's roofline (not part of libdvm)
+STREAM_LIB = os.path.join(HERE, "libdvm_stream.so")
+STREAM_SOURCES = [os.path.join(CSRC, "dvm_stream.hip")]
+
+
+def _hipcc(out: str, sources, verbose: bool) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-o", tmp, *SOURCES]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *FLAGS, "-o", tmp, *sources]
     res = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
                      if "packed-fp32-ops" not in l and "not a recognized feature" not in l)
@@ -31,8 +36,13 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{msgs}")
     if verbose and msgs.strip():
         print(msgs, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(STREAM_LIB, STREAM_SOURCES, verbose)
+    return _hipcc(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

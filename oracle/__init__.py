@@ -78,6 +78,9 @@ def lib():
         L.or_wall_sensitivity.argtypes = [P, dp, dp, dp, C.c_void_p]
         L.or_mesh_sensitivity.argtypes = [P, D, dp]
         L.or_gauss_grad.argtypes = [P, I, dp]
+        L.or_set_equilibrium.restype = I
+        L.or_set_equilibrium.argtypes = [P, I]
+        L.or_eq_params.argtypes = [P, dp, dp, dp]
         L.or_wall_JB.restype = D
         L.or_wall_JB.argtypes = [P, I, D, D, D, D, D]
         L.or_set_scheme.restype = I
@@ -138,6 +141,7 @@ class Problem:
         self.nc, self.nw, self.nv, self.n1, self.n2 = (int(x) for x in s[:5])
         self.ni, self.nj = int(ni), int(nj)
         self.order = 1
+        self.equilibrium = 0
 
     def set_scheme(self, order: int = 2, limiter: bool = True, correction_every: int = 40):
         """Spatial order 1 (first-order upwind) or 2 (Green-Gauss slopes with an
@@ -146,6 +150,21 @@ class Problem:
         if lib().or_set_scheme(self._h, int(order), 1 if limiter else 0, int(correction_every)) != 0:
             raise ValueError("oracle: invalid scheme")
         self.order = int(order)
+
+    def set_equilibrium(self, kind: int):
+        """0: pointwise Maxwellian of the cell's primitive variables; 1: the
+        discrete-conservative equilibrium (moments on the grid equal W)."""
+        if lib().or_set_equilibrium(self._h, int(kind)) != 0:
+            raise ValueError("oracle: invalid equilibrium")
+        self.equilibrium = int(kind)
+
+    def eq_params(self, W):
+        """Equilibrium parameters (rho', u1', u2', theta') of a moment vector
+        W and their derivative d(.)/dW (4 x 4)."""
+        P = np.zeros(4)
+        M = np.zeros((4, 4))
+        lib().or_eq_params(self._h, np.ascontiguousarray(W, dtype=np.float64), P, M)
+        return P, M
 
     def so_slopes(self, f=None):
         """Limited slopes G[c, k, component, direction] and limiter factors

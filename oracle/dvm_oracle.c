@@ -127,6 +127,13 @@ typedef struct {
     double *psi;       /* [nc][nv][2] limiter of the frozen f (adjoint) */
     double *acorr;     /* [nc][nv][2] held adjoint reconstruction term */
     int acorr_ok, asince;
+
+    /* equilibrium: 0 pointwise Maxwellian of the cell's primitive variables,
+     * 1 discrete-conservative (see "discrete-conservative equilibrium") */
+    int equilibrium;
+    double *eqP;       /* [nc][4] (rho', u1', u2', theta') of the current W */
+    double *eqM;       /* [nc][4][4] d(rho', u1', u2', theta')/dW */
+    int eq_ok;         /* eqP, eqM hold the current W */
 } or_problem;
 
 /* ------------------------------------------------------------------ */
@@ -262,6 +269,205 @@ void or_dg_dW(double rho, double u1, double u2, double th, double v1, double v2,
     dg_dW(rho, u1, u2, th, E, v1, v2, a, b);
     memcpy(dg, a, sizeof(a));
     memcpy(dtt, b, sizeof(b));
+}
+
+/* ------------------------------------------------------------------ */
+/* discrete-conservative equilibrium                                   */
+/* ------------------------------------------------------------------ */
+/* A reading of the equilibrium on a discrete velocity grid, taken as an
+ * option (the pointwise Maxwellian of the cell's primitive variables stays
+ * the default): the equilibrium of a cell is the reduced Maxwellian
+ * g(P') whose moments on the grid equal the cell's moments,
+ *     sum_k w_k Psi_k g_k(P') = W,
+ * with P' = (rho', u1', u2', theta') found by Newton's method from the
+ * primitive variables of W (on a grid that integrates the Maxwellian
+ * exactly, P' = P(W)).  The discrete BGK collision term then conserves mass,
+ * momentum and energy, as the continuous one does (Sec. 2.1); tau keeps the
+ * cell's own rho and theta.  Newton runs a fixed number of steps (the
+ * quadrature error of a usable grid is at most a few percent, and each step
+ * squares the relative error). */
+#define OR_EQ_NEWTON 6
+
+/* moments m = sum_k w Psi g(P) and their Jacobian dm/dP at P */
+static void eq_moments_jac(const or_problem *p, const double P[4], double m[4], double J[4][4])
+{
+    const double rho = P[0], u1 = P[1], u2 = P[2], th = P[3];
+    for (int a = 0; a < 4; a++) { m[a] = 0; for (int b = 0; b < 4; b++) J[a][b] = 0; }
+    for (int k = 0; k < p->nv; k++) {
+        double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], w = p->w[k];
+        double g1 = maxwell1(rho, u1, u2, th, v1, v2), g2 = 0.5 * th * g1;
+        double c1 = v1 - u1, c2 = v2 - u2, cc = c1 * c1 + c2 * c2;
+        double d1[4] = { g1 / rho, g1 * c1 / th, g1 * c2 / th, g1 * (cc / (2 * th * th) - 1.0 / th) };
+        double d2[4] = { 0.5 * th * d1[0], 0.5 * th * d1[1], 0.5 * th * d1[2], 0.5 * th * d1[3] + 0.5 * g1 };
+        double psi[4] = { 1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2) };
+        for (int a = 0; a < 4; a++) {
+            m[a] += w * (psi[a] * g1 + (a == 3 ? g2 : 0.0));
+            for (int b = 0; b < 4; b++) J[a][b] += w * (psi[a] * d1[b] + (a == 3 ? d2[b] : 0.0));
+        }
+    }
+}
+
+/* x = A^{-1} b by Gaussian elimination with partial pivoting (A, b copied) */
+static void solve4(const double A_in[4][4], const double b_in[4], double x[4])
+{
+    double A[4][5];
+    for (int a = 0; a < 4; a++) { for (int b = 0; b < 4; b++) A[a][b] = A_in[a][b]; A[a][4] = b_in[a]; }
+    for (int col = 0; col < 4; col++) {
+        int piv = col;
+        for (int r = col + 1; r < 4; r++) if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (piv != col) for (int b = 0; b < 5; b++) { double t = A[col][b]; A[col][b] = A[piv][b]; A[piv][b] = t; }
+        for (int r = col + 1; r < 4; r++) {
+            double fct = A[r][col] / A[col][col];
+            for (int b = col; b < 5; b++) A[r][b] -= fct * A[col][b];
+        }
+    }
+    for (int r = 3; r >= 0; r--) {
+        double acc = A[r][4];
+        for (int b = r + 1; b < 4; b++) acc -= A[r][b] * x[b];
+        x[r] = acc / A[r][r];
+    }
+}
+
+/* equilibrium parameters P' of moments W; M (may be NULL) receives
+ * dP'/dW = (dm/dP')^{-1} at P' (pointwise: d(rho, u, theta)/dW) */
+static void eq_params(const or_problem *p, const double *W, double P[4], double M[4][4])
+{
+    prim(W, &P[0], &P[1], &P[2], &P[3]);
+    if (p->equilibrium == 1) {
+        for (int it = 0; it < OR_EQ_NEWTON; it++) {
+            double m[4], J[4][4], r[4], dP[4];
+            eq_moments_jac(p, P, m, J);
+            for (int a = 0; a < 4; a++) r[a] = W[a] - m[a];
+            solve4(J, r, dP);
+            for (int a = 0; a < 4; a++) P[a] += dP[a];
+        }
+    }
+    if (!M) return;
+    if (p->equilibrium == 1) {
+        double m[4], J[4][4];
+        eq_moments_jac(p, P, m, J);
+        for (int b = 0; b < 4; b++) {
+            double e[4] = { 0, 0, 0, 0 }, col[4];
+            e[b] = 1.0;
+            solve4(J, e, col);
+            for (int a = 0; a < 4; a++) M[a][b] = col[a];
+        }
+    } else {
+        const double rho = P[0], u1 = P[1], u2 = P[2], E = W[3] / W[0];
+        double J[4][4] = {
+            { 1.0, 0.0, 0.0, 0.0 },
+            { -u1 / rho, 1.0 / rho, 0.0, 0.0 },
+            { -u2 / rho, 0.0, 1.0 / rho, 0.0 },
+            { (2.0 / 3.0) * (u1 * u1 + u2 * u2 - E) / rho, -(2.0 / 3.0) * u1 / rho,
+              -(2.0 / 3.0) * u2 / rho, (2.0 / 3.0) / rho } };
+        memcpy(M, J, sizeof J);
+    }
+}
+
+/* eqP, eqM of the current W (every cell) */
+static void eq_cache(or_problem *p)
+{
+    if (p->eq_ok) return;
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+    for (int c = 0; c < p->nc; c++) {
+        double M[4][4];
+        eq_params(p, p->W + 4 * c, p->eqP + 4 * c, M);
+        memcpy(p->eqM + 16 * c, M, sizeof M);
+    }
+    p->eq_ok = 1;
+}
+
+/* d g_c / d W (2 x 4) at velocity k of cell c for the current W, through
+ * the equilibrium parameters, and (1/tau) d tau / d W (tau from the cell's
+ * own rho, theta) */
+static void dg_dW_cell(or_problem *p, int c, int k, double dg[2][4], double dtt[4])
+{
+    eq_cache(p);
+    const double *P = p->eqP + 4 * c, *M = p->eqM + 16 * c;
+    double rho, u1, u2, th;
+    prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+    double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
+    double g1 = maxwell1(P[0], P[1], P[2], P[3], v1, v2);
+    double c1 = v1 - P[1], c2 = v2 - P[2], cc = c1 * c1 + c2 * c2, t = P[3];
+    double d1[4] = { g1 / P[0], g1 * c1 / t, g1 * c2 / t, g1 * (cc / (2 * t * t) - 1.0 / t) };
+    double d2[4] = { 0.5 * t * d1[0], 0.5 * t * d1[1], 0.5 * t * d1[2], 0.5 * t * d1[3] + 0.5 * g1 };
+    /* d(rho, theta)/dW of the cell's own primitive variables for tau */
+    const double E = p->W[4 * c + 3] / p->W[4 * c];
+    const double drho[4] = { 1.0, 0.0, 0.0, 0.0 };
+    const double dth[4] = { (2.0 / 3.0) * (u1 * u1 + u2 * u2 - E) / rho, -(2.0 / 3.0) * u1 / rho,
+                            -(2.0 / 3.0) * u2 / rho, (2.0 / 3.0) / rho };
+    for (int m = 0; m < 4; m++) {
+        double a = 0, b = 0;
+        for (int q = 0; q < 4; q++) { a += d1[q] * M[4 * q + m]; b += d2[q] * M[4 * q + m]; }
+        dg[0][m] = a; dg[1][m] = b;
+        dtt[m] = -drho[m] / rho - 0.5 * dth[m] / th;
+    }
+}
+
+/* equilibrium (g1, g2) of cell c at velocity k for the current W */
+static void eq_cell_g(or_problem *p, int c, int k, double *g1, double *g2)
+{
+    eq_cache(p);
+    const double *P = p->eqP + 4 * c;
+    *g1 = maxwell1(P[0], P[1], P[2], P[3], p->v[2 * k], p->v[2 * k + 1]);
+    *g2 = 0.5 * P[3] * (*g1);
+}
+
+/* complex twin of eq_params (complex-step pins): the same Newton steps */
+static void eq_params_z(const or_problem *p, const double complex *W, double complex P[4])
+{
+    P[0] = W[0]; P[1] = W[1] / W[0]; P[2] = W[2] / W[0];
+    P[3] = (2.0 / 3.0) * (W[3] / W[0] - 0.5 * (P[1] * P[1] + P[2] * P[2]));
+    if (p->equilibrium != 1) return;
+    for (int it = 0; it < OR_EQ_NEWTON; it++) {
+        double complex m[4] = { 0, 0, 0, 0 }, A[4][5];
+        for (int a = 0; a < 4; a++) for (int b = 0; b < 5; b++) A[a][b] = 0;
+        for (int k = 0; k < p->nv; k++) {
+            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], w = p->w[k];
+            double complex c1 = v1 - P[1], c2 = v2 - P[2], cc = c1 * c1 + c2 * c2, t = P[3];
+            double complex g1 = P[0] / (2 * OR_PI * t) * cexp(-cc / (2 * t)), g2 = 0.5 * t * g1;
+            double complex d1[4] = { g1 / P[0], g1 * c1 / t, g1 * c2 / t, g1 * (cc / (2 * t * t) - 1.0 / t) };
+            double complex d2[4] = { 0.5 * t * d1[0], 0.5 * t * d1[1], 0.5 * t * d1[2], 0.5 * t * d1[3] + 0.5 * g1 };
+            double psi[4] = { 1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2) };
+            for (int a = 0; a < 4; a++) {
+                m[a] += w * (psi[a] * g1 + (a == 3 ? g2 : 0.0));
+                for (int b = 0; b < 4; b++) A[a][b] += w * (psi[a] * d1[b] + (a == 3 ? d2[b] : 0.0));
+            }
+        }
+        for (int a = 0; a < 4; a++) A[a][4] = W[a] - m[a];
+        for (int col = 0; col < 4; col++) {
+            int piv = col;
+            for (int r = col + 1; r < 4; r++) if (fabs(creal(A[r][col])) > fabs(creal(A[piv][col]))) piv = r;
+            if (piv != col) for (int b = 0; b < 5; b++) { double complex tt = A[col][b]; A[col][b] = A[piv][b]; A[piv][b] = tt; }
+            for (int r = col + 1; r < 4; r++) {
+                double complex fct = A[r][col] / A[col][col];
+                for (int b = col; b < 5; b++) A[r][b] -= fct * A[col][b];
+            }
+        }
+        double complex x[4];
+        for (int r = 3; r >= 0; r--) {
+            double complex acc = A[r][4];
+            for (int b = r + 1; b < 4; b++) acc -= A[r][b] * x[b];
+            x[r] = acc / A[r][r];
+        }
+        for (int a = 0; a < 4; a++) P[a] += x[a];
+    }
+}
+
+int or_set_equilibrium(or_problem *p, int kind)
+{
+    if (kind != 0 && kind != 1) return -1;
+    p->equilibrium = kind;
+    p->eq_ok = 0;
+    return 0;
+}
+
+/* equilibrium parameters of a moment vector (pins): P[4], M[4][4] = dP/dW */
+void or_eq_params(or_problem *p, const double *W, double *P, double *M)
+{
+    double Mm[4][4];
+    eq_params(p, W, P, Mm);
+    if (M) memcpy(M, Mm, sizeof Mm);
 }
 
 /* ------------------------------------------------------------------ */
@@ -429,6 +635,9 @@ or_problem *or_create(int topo, int ni, int nj, int nwake, const double *nodes,
     p->F = malloc(sizeof(double) * p->nw);
     p->cellred = malloc(sizeof(double) * 2 * p->nc);
     p->order = 1; p->limiter = 1; p->kcorr = 40;
+    p->equilibrium = 0; p->eq_ok = 0;
+    p->eqP = malloc(sizeof(double) * 4 * p->nc);
+    p->eqM = malloc(sizeof(double) * 16 * p->nc);
     if (!p->f || !p->fn || !p->phi || !p->phin) return NULL;
     return p;
 }
@@ -441,7 +650,7 @@ void or_destroy(or_problem *p)
     free(p->v); free(p->w); free(p->fd); free(p->gM); free(p->D); free(p->mJ);
     free(p->f); free(p->fn); free(p->W); free(p->F); free(p->phi); free(p->phin); free(p->cellred);
     free(p->nodes);
-    free(p->fm); free(p->corr); free(p->dF); free(p->psi); free(p->acorr);
+    free(p->fm); free(p->corr); free(p->dF); free(p->psi); free(p->acorr); free(p->eqP); free(p->eqM);
     free(p);
 }
 
@@ -490,6 +699,7 @@ void or_export_wall(const or_problem *p, double *D, double *F)
 static void update_W_F(or_problem *p, const double *f)
 {
     const int nv = p->nv;
+    p->eq_ok = 0;
 #pragma omp parallel for schedule(static) num_threads(p->nthreads)
     for (int c = 0; c < p->nc; c++)
         or_moments(nv, p->v, p->w, f + (size_t)c * nv * 2, p->W + 4 * c);
@@ -738,6 +948,7 @@ void or_so_faces(or_problem *p, const double *f, double *out)
                 o[1] = a2 + so_delta(p, G, c, q, k, 1, s);
             }
     memcpy(p->W, Ws, sizeof(double) * 4 * p->nc); memcpy(p->F, Fs, sizeof(double) * p->nw);
+    p->eq_ok = 0;
     free(G); free(F2); free(Ws); free(Fs);
 }
 
@@ -758,8 +969,9 @@ double or_primal_iterate(or_problem *p, int niter)
         for (int l = 0; l < p->nw; l++) Fw[l] = p->F[l] + (so ? p->dF[l] : 0.0);
 #pragma omp parallel for schedule(static) num_threads(p->nthreads)
         for (int c = 0; c < p->nc; c++) {
-            double rho, u1, u2, th;
+            double rho, u1, u2, th, P[4];
             prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+            eq_params(p, p->W + 4 * c, P, NULL);
             double itau = inv_tau_of(p, rho, th);
             double V = p->vol[c];
             for (int k = 0; k < nv; k++) {
@@ -778,7 +990,7 @@ double or_primal_iterate(or_problem *p, int niter)
                     in1 -= p->corr[((size_t)c * nv + k) * 2];
                     in2 -= p->corr[((size_t)c * nv + k) * 2 + 1];
                 }
-                double g1 = maxwell1(rho, u1, u2, th, v1, v2), g2 = 0.5 * th * g1;
+                double g1 = maxwell1(P[0], P[1], P[2], P[3], v1, v2), g2 = 0.5 * P[3] * g1;
                 double den = out + V * itau;
                 double *fo = p->fn + ((size_t)c * nv + k) * 2;
                 fo[0] = (in1 + V * itau * g1) / den;
@@ -871,6 +1083,7 @@ void or_primal_residual(or_problem *p, const double *f, double *out)
         double *Wsave = malloc(sizeof(double) * 4 * p->nc);
         memcpy(Wsave, p->W, sizeof(double) * 4 * p->nc);
         for (int c = 0; c < p->nc; c++) or_moments(nv, p->v, p->w, f + (size_t)c * nv * 2, p->W + 4 * c);
+        p->eq_ok = 0;
         for (int c = 0; c < p->nc; c++) {
             double rho, u1, u2, th;
             prim(p->W + 4 * c, &rho, &u1, &u2, &th);
@@ -883,12 +1096,14 @@ void or_primal_residual(or_problem *p, const double *f, double *out)
                     r1 += s * a[0]; r2 += s * a[1];
                 }
                 const double *fc = f + ((size_t)c * nv + k) * 2;
-                double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+                double g1, g2;
+                eq_cell_g(p, c, k, &g1, &g2);
                 out[((size_t)c * nv + k) * 2] = r1 + V * itau * (fc[0] - g1);
-                out[((size_t)c * nv + k) * 2 + 1] = r2 + V * itau * (fc[1] - 0.5 * th * g1);
+                out[((size_t)c * nv + k) * 2 + 1] = r2 + V * itau * (fc[1] - g2);
             }
         }
         memcpy(p->W, Wsave, sizeof(double) * 4 * p->nc);
+        p->eq_ok = 0;
         free(Wsave); free(fq);
         return;
     }
@@ -909,13 +1124,15 @@ void or_primal_residual(or_problem *p, const double *f, double *out)
                 if (s > 0) { r1 += s * fc[0]; r2 += s * fc[1]; }
                 else { double a1, a2; inflow_value(p, f, p->F, c, q, k, &a1, &a2); r1 += s * a1; r2 += s * a2; }
             }
-            double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+            double g1, g2;
+            eq_cell_g(p, c, k, &g1, &g2);
             out[((size_t)c * nv + k) * 2] = r1 + V * itau * (fc[0] - g1);
-            out[((size_t)c * nv + k) * 2 + 1] = r2 + V * itau * (fc[1] - 0.5 * th * g1);
+            out[((size_t)c * nv + k) * 2 + 1] = r2 + V * itau * (fc[1] - g2);
         }
     }
     memcpy(p->W, Wsave, sizeof(double) * 4 * p->nc);
     memcpy(p->F, Fsave, sizeof(double) * p->nw);
+    p->eq_ok = 0;
     free(Wsave); free(Fsave);
 }
 
@@ -1019,6 +1236,8 @@ void or_complex_step(or_problem *p, const double *u, double h, int which, double
             double complex rho = W0, u1 = W1 / W0, u2 = W2 / W0;
             double complex th = (2.0 / 3.0) * (W3 / W0 - 0.5 * (u1 * u1 + u2 * u2));
             double complex itau = itinf * rho * csqrt(2.0 * th);
+            double complex Wz[4] = { W0, W1, W2, W3 }, Pz[4];
+            eq_params_z(p, Wz, Pz);
             double V = p->vol[c];
             for (int k = 0; k < nv; k++) {
                 double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
@@ -1040,10 +1259,10 @@ void or_complex_step(or_problem *p, const double *u, double h, int which, double
                     }
                     r1 += s * a1; r2 += s * a2;
                 }
-                double complex c1 = v1 - u1, c2 = v2 - u2;
-                double complex g1 = rho / (2 * OR_PI * th) * cexp(-(c1 * c1 + c2 * c2) / (2 * th));
+                double complex c1 = v1 - Pz[1], c2 = v2 - Pz[2];
+                double complex g1 = Pz[0] / (2 * OR_PI * Pz[3]) * cexp(-(c1 * c1 + c2 * c2) / (2 * Pz[3]));
                 r1 += V * itau * (fc[2 * k] - g1);
-                r2 += V * itau * (fc[2 * k + 1] - 0.5 * th * g1);
+                r2 += V * itau * (fc[2 * k + 1] - 0.5 * Pz[3] * g1);
                 dR[((size_t)c * nv + k) * 2] = cimag(r1) / h;
                 dR[((size_t)c * nv + k) * 2 + 1] = cimag(r2) / h;
             }
@@ -1064,22 +1283,22 @@ void or_complex_step(or_problem *p, const double *u, double h, int which, double
 static void adjoint_moments(or_problem *p, const double *phi, double *What, double *rtau, double *Phi)
 {
     const int nv = p->nv;
+    eq_cache(p);
 #pragma omp parallel for schedule(static) num_threads(p->nthreads)
     for (int c = 0; c < p->nc; c++) {
         double rho, u1, u2, th;
         const double *W = p->W + 4 * c;
         prim(W, &rho, &u1, &u2, &th);
-        double E = W[3] / W[0];
         double itau = inv_tau_of(p, rho, th);
         double acc[4] = { 0, 0, 0, 0 }, rt = 0;
         for (int k = 0; k < nv; k++) {
-            double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
             double dg[2][4], dtt[4];
-            dg_dW(rho, u1, u2, th, E, v1, v2, dg, dtt);
+            dg_dW_cell(p, c, k, dg, dtt);
             const double *ph = phi + ((size_t)c * nv + k) * 2;
             const double *fc = p->f + ((size_t)c * nv + k) * 2;
             for (int m = 0; m < 4; m++) acc[m] += p->w[k] * (ph[0] * dg[0][m] + ph[1] * dg[1][m]);
-            double g1 = maxwell1(rho, u1, u2, th, v1, v2), g2 = 0.5 * th * g1;
+            double g1, g2;
+            eq_cell_g(p, c, k, &g1, &g2);
             rt += p->w[k] * (ph[0] * (g1 - fc[0]) + ph[1] * (g2 - fc[1])) * itau;
         }
         for (int m = 0; m < 4; m++) What[4 * c + m] = acc[m];
@@ -1107,11 +1326,10 @@ static void adjoint_source(const or_problem *p, int c, int k, const double *What
     double rho, u1, u2, th;
     const double *W = p->W + 4 * c;
     prim(W, &rho, &u1, &u2, &th);
-    double E = W[3] / W[0];
     double itau = inv_tau_of(p, rho, th);
     double v1 = p->v[2 * k], v2 = p->v[2 * k + 1];
     double dg[2][4], dtt[4];
-    dg_dW(rho, u1, u2, th, E, v1, v2, dg, dtt);
+    dg_dW_cell((or_problem *)p, c, k, dg, dtt);
     const double *Wh = What + 4 * c;
     double psi1[4] = { 1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2) };  /* first column of Psi */
     double eq1 = 0, tt1 = 0;
@@ -1423,6 +1641,7 @@ static void mesh_sensitivity_so(or_problem *p, double h, double *out)
     double *dF = malloc(sizeof(double) * (p->nw > 0 ? p->nw : 1));
     so_slopes(p, p->f, G, psi);
     so_wall_dF(p, G, dF);
+    eq_cache(p);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(p->nthreads)
     for (int m = 0; m < nn; m++) {
         const int im = m % (ni + 1), jm = m / (ni + 1);
@@ -1528,9 +1747,10 @@ static void mesh_sensitivity_so(or_problem *p, double h, double *out)
                         r1 += sq * a1;
                         r2 += sq * a2;
                     }
-                    const double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+                    double g1, g2;
+                    eq_cell_g(p, c, k, &g1, &g2);
                     r1 += gc->V * itau * (fc[2 * k] - g1);
-                    r2 += gc->V * itau * (fc[2 * k + 1] - 0.5 * th * g1);
+                    r2 += gc->V * itau * (fc[2 * k + 1] - g2);
                     L += p->w[k] * (pc[2 * k] * r1 + pc[2 * k + 1] * r2);
                 }
             }
@@ -1559,6 +1779,7 @@ void or_mesh_sensitivity(or_problem *p, double h, double *out)
         return;
     }
     const int ni = p->ni, nj = p->nj, nv = p->nv, nn = (ni + 1) * (nj + 1);
+    eq_cache(p);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(p->nthreads)
     for (int m = 0; m < nn; m++) {
         const int im = m % (ni + 1), jm = m / (ni + 1);
@@ -1611,9 +1832,10 @@ void or_mesh_sensitivity(or_problem *p, double h, double *out)
                             r1 += sq * a1;
                             r2 += sq * a2;
                         }
-                        const double g1 = maxwell1(rho, u1, u2, th, v1, v2);
+                        double g1, g2;
+                        eq_cell_g(p, c, k, &g1, &g2);
                         r1 += V * itau * (fc[2 * k] - g1);
-                        r2 += V * itau * (fc[2 * k + 1] - 0.5 * th * g1);
+                        r2 += V * itau * (fc[2 * k + 1] - g2);
                         L += p->w[k] * (pc[2 * k] * r1 + pc[2 * k + 1] * r2);
                     }
                 }

@@ -69,6 +69,7 @@ enum { DVM_OBJ_DRAG = 0, DVM_OBJ_HEAT = 1 };
 enum { DVM_VG_MIDPOINT = 0, DVM_VG_NEWTON_COTES = 1, DVM_VG_SINH = 2 };
 enum { DVM_STATE_F = 0, DVM_STATE_PHI = 1, DVM_STATE_PHI_ROWS = 2 };
 enum { DVM_LIMITER_NONE = 0, DVM_LIMITER_VENKAT = 1 };   /* second-order slope limiter */
+enum { DVM_EQ_POINTWISE = 0, DVM_EQ_CONSERVATIVE = 1 };   /* equilibrium on the velocity grid */
 #define DVM_MAX_PARAMS 64
 
 typedef struct {
@@ -147,6 +148,21 @@ int dvm_solver_create(const dvm_mesh *m, const dvm_vgrid *g, const dvm_flow *flo
  * The exact mesh sensitivity differentiates the second-order balance with
  * the limiter factors of f held fixed (exact with DVM_LIMITER_NONE). */
 int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_interval);
+/* Equilibrium of the BGK relaxation on the discrete velocity grid (Sec.
+ * 2.1, eqs. maxwell_reduce, kndefine), set before dvm_solver_bind
+ * (DVM_ESTATE once bound).  DVM_EQ_POINTWISE (the default): the reduced
+ * Maxwellian of the cell's primitive variables at each grid velocity; its
+ * grid moments differ from W by the grid's quadrature error, so the
+ * discrete collision term does not conserve exactly.  DVM_EQ_CONSERVATIVE:
+ * the reduced Maxwellian whose grid moments equal W exactly (its
+ * parameters rho', u', theta' found by Newton's method from the primitive
+ * variables, a fixed six steps, per cell and sweep); tau keeps the cell's
+ * own rho and theta; the adjoint differentiates through the parameters
+ * (dP'/dW = (dm/dP')^{-1}).  On grids whose quadrature of the Maxwellian
+ * is off (Newton-Cotes, sinh-stretched) the pointwise iteration can diverge
+ * in the near-continuum regime, where collisions amplify the moment error
+ * every sweep; the conservative one does not. */
+int dvm_solver_set_equilibrium(dvm_solver *s, int kind);
 /* Exact device bytes the solver needs (used for admission by footprint). */
 size_t dvm_solver_workspace_bytes(const dvm_solver *s);
 /* Bind a caller-owned device buffer (>= workspace bytes, 256-byte aligned)

@@ -77,6 +77,149 @@ __device__ __forceinline__ int xcd_item(int n, int b)
 }
 static inline int xcd_grid(int n) { return ((n + 7) >> 3) << 3; }
 
+// Solve a 4x4 system A x = b (Gaussian elimination, partial pivoting; A and
+// b are overwritten).  Called with the same values in every lane.
+__device__ __forceinline__ void solve4(double (&A)[4][4], double (&b)[4], double (&x)[4])
+{
+#pragma unroll
+    for (int col = 0; col < 4; col++) {
+        int piv = col;
+#pragma unroll
+        for (int r = col + 1; r < 4; r++)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            if (r == piv && r != col) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const double t = A[col][k];
+                    A[col][k] = A[r][k];
+                    A[r][k] = t;
+                }
+                const double t = b[col];
+                b[col] = b[r];
+                b[r] = t;
+            }
+#pragma unroll
+        for (int r = col + 1; r < 4; r++) {
+            const double fct = A[r][col] / A[col][col];
+#pragma unroll
+            for (int k = col; k < 4; k++) A[r][k] -= fct * A[col][k];
+            b[r] -= fct * b[col];
+        }
+    }
+#pragma unroll
+    for (int r = 3; r >= 0; r--) {
+        double acc = b[r];
+#pragma unroll
+        for (int k = r + 1; k < 4; k++) acc -= A[r][k] * x[k];
+        x[r] = acc / A[r][r];
+    }
+}
+
+// Discrete-conservative equilibrium (the reading of the equilibrium on a
+// discrete velocity grid): the parameters P = (rho, u1, u2, theta) of the
+// reduced Maxwellian whose grid moments equal W.  Newton from the primitive
+// variables of W, kEqNewton steps.  The Maxwellian factors as
+// rho/(2 pi theta) X(v1) Y(v2) on the tensor grid, so each step needs only
+// the 1-D sums R_p = sum_a wx_a X_a vx_a^p, T_p = sum_b wy_b Y_b vy_b^p
+// (p <= 4), summed per lane and reduced across the wave in a fixed order:
+// every lane ends with the same P.  Minv (may be null) receives
+// (dm/dP)^{-1} = dP/dW at the final P, row q = parameter, column m = moment.
+constexpr int kEqNewton = 6;
+
+__device__ __forceinline__ void eq_moments_jac(const DevSolve &d, const double (&P)[4], double (&m)[4],
+                                               double (&J)[4][4])
+{
+    const int lane = threadIdx.x % kWave;
+    const double u1 = P[1], u2 = P[2], th = P[3], h = 0.5 / th;
+    double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = lane; i < d.n1; i += kWave) {
+        const double v = d.vx[i], e = v - u1, X = d.wx[i] * exp(-e * e * h);
+        s[0] += X;
+        s[1] += X * v;
+        s[2] += X * v * v;
+        s[3] += X * v * v * v;
+        s[4] += X * v * v * v * v;
+    }
+    for (int i = lane; i < d.n2; i += kWave) {
+        const double v = d.vy[i], e = v - u2, Y = d.wy[i] * exp(-e * e * h);
+        s[5] += Y;
+        s[6] += Y * v;
+        s[7] += Y * v * v;
+        s[8] += Y * v * v * v;
+        s[9] += Y * v * v * v * v;
+    }
+    wave_sum<10>(s);
+    const double *R = s, *T = s + 5;
+    const double kap = P[0] / (2.0 * kPi * th);
+    // d R_p / d u1 and d R_p / d theta (p = 0..2), likewise T with u2
+    double Ru[3], Rt[3], Tu[3], Tt[3];
+    const double i2t2 = 1.0 / (2.0 * th * th);
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        Ru[q] = (R[q + 1] - u1 * R[q]) / th;
+        Tu[q] = (T[q + 1] - u2 * T[q]) / th;
+        Rt[q] = (R[q + 2] - 2.0 * u1 * R[q + 1] + u1 * u1 * R[q]) * i2t2;
+        Tt[q] = (T[q + 2] - 2.0 * u2 * T[q + 1] + u2 * u2 * T[q]) * i2t2;
+    }
+    const double b0 = R[0] * T[0], b1 = R[1] * T[0], b2 = R[0] * T[1];
+    const double b3 = 0.5 * (R[2] * T[0] + R[0] * T[2]) + 0.5 * th * R[0] * T[0];
+    m[0] = kap * b0;
+    m[1] = kap * b1;
+    m[2] = kap * b2;
+    m[3] = kap * b3;
+    // columns: rho, u1, u2, theta
+    J[0][0] = m[0] / P[0];
+    J[1][0] = m[1] / P[0];
+    J[2][0] = m[2] / P[0];
+    J[3][0] = m[3] / P[0];
+    J[0][1] = kap * Ru[0] * T[0];
+    J[1][1] = kap * Ru[1] * T[0];
+    J[2][1] = kap * Ru[0] * T[1];
+    J[3][1] = kap * (0.5 * (Ru[2] * T[0] + Ru[0] * T[2]) + 0.5 * th * Ru[0] * T[0]);
+    J[0][2] = kap * R[0] * Tu[0];
+    J[1][2] = kap * R[1] * Tu[0];
+    J[2][2] = kap * R[0] * Tu[1];
+    J[3][2] = kap * (0.5 * (R[2] * Tu[0] + R[0] * Tu[2]) + 0.5 * th * R[0] * Tu[0]);
+    const double db0 = Rt[0] * T[0] + R[0] * Tt[0];
+    J[0][3] = kap * (db0 - b0 / th);
+    J[1][3] = kap * (Rt[1] * T[0] + R[1] * Tt[0] - b1 / th);
+    J[2][3] = kap * (Rt[0] * T[1] + R[0] * Tt[1] - b2 / th);
+    J[3][3] = kap * (0.5 * (Rt[2] * T[0] + R[2] * Tt[0] + Rt[0] * T[2] + R[0] * Tt[2]) + 0.5 * R[0] * T[0] +
+                     0.5 * th * db0 - b3 / th);
+}
+
+__device__ __forceinline__ void eq_conservative(const DevSolve &d, const double (&W)[4], double (&P)[4],
+                                                double *Minv)
+{
+    for (int it = 0; it < kEqNewton; it++) {
+        double m[4], J[4][4], r[4], dP[4];
+        eq_moments_jac(d, P, m, J);
+#pragma unroll
+        for (int a = 0; a < 4; a++) r[a] = W[a] - m[a];
+        solve4(J, r, dP);
+#pragma unroll
+        for (int a = 0; a < 4; a++) P[a] += dP[a];
+    }
+    if (Minv) {
+        double m[4], J[4][4];
+        eq_moments_jac(d, P, m, J);
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            double A[4][4], e[4] = {0, 0, 0, 0}, x[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+#pragma unroll
+                for (int k = 0; k < 4; k++) A[r][k] = J[r][k];
+            e[b] = 1.0;
+            solve4(A, e, x);
+#pragma unroll
+            for (int a = 0; a < 4; a++) Minv[4 * a + b] = x[a];
+        }
+    }
+}
+
 // Instantiate for the storage type of a solve: float (mixed) or double (FP64).
 #define DVM_DISPATCH(mixed, ...) \
     do {                          \

@@ -265,6 +265,7 @@ struct dvm_solver {
     double inv_tau_inf, u_inf, theta_w, cd_scale;
     // spatial scheme: order 1, or 2 with limiter and K sweeps between corrections
     int order = 1, limiter = DVM_LIMITER_VENKAT, kcorr = 40;
+    int equil = DVM_EQ_POINTWISE;
     // workspace
     struct {
         size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
@@ -327,7 +328,7 @@ void layout(dvm_solver &s)
             o.aW[p] = take(8 * nc * sizeof(double));
             o.Phi[p] = take(nw * sizeof(double));
         }
-        o.acoef = take(16 * nc * sizeof(double));
+        o.acoef = take(dvm::kAcoef * nc * sizeof(double));
         o.sens = take(5 * nw * sizeof(double));
         o.dJdn = take(2 * nw * sizeof(double));
         o.jac = take(2 * nw * dvm::kMaxParams * sizeof(double));
@@ -375,6 +376,7 @@ void fill_dev(dvm_solver &s)
     d.mixed = s.mixed;
     d.order = s.order;
     d.limiter = s.limiter;
+    d.equil = s.equil;
     d.nbr = at<int32_t>(s, s.off.nbr);
     d.patch = at<int32_t>(s, s.off.patch);
     d.cell_of = at<int32_t>(s, s.off.cell_of);
@@ -806,6 +808,15 @@ int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_
     s->limiter = limiter;
     s->kcorr = correction_interval;
     layout(*s);
+    return DVM_OK;
+}
+
+int dvm_solver_set_equilibrium(dvm_solver *s, int kind)
+{
+    if (!s) return fail(DVM_EINVAL, "null solver");
+    if (s->base) return fail(DVM_ESTATE, "the equilibrium is set before dvm_solver_bind");
+    if (kind != DVM_EQ_POINTWISE && kind != DVM_EQ_CONSERVATIVE) return fail(DVM_EINVAL, "unknown equilibrium %d", kind);
+    s->equil = kind;
     return DVM_OK;
 }
 

@@ -12,6 +12,7 @@ constexpr int kBlock = 256;        // threads per workgroup of the per-cell and 
 constexpr int kWave = 64;          // wavefront width
 constexpr int kMaxN1D = 128;       // max velocity nodes per direction
 constexpr int kMaxParams = 64;
+constexpr int kAcoef = 32;         // doubles per cell of the adjoint coefficients
 
 // The sweeps give each workgroup a patch of kPatchI x kPatchJ cells, one
 // wave per cell; patches tile kTileI x kTileJ tiles, which follow each
@@ -34,6 +35,7 @@ struct DevSolve {
     int objective;
     int mixed;
     int order;               // spatial order of the scheme: 1, or 2 (reconstructed face values)
+    int equil;               // equilibrium: 0 pointwise Maxwellian, 1 discrete-conservative
     int limiter;             // order 2: 0 none, 1 Venkatakrishnan
     // mesh
     const int32_t *nbr;      // [nc][4] (device cell numbering)
@@ -64,7 +66,7 @@ struct DevSolve {
     double *aW[2];           // [nc][8]: What (4), rho_tau, pad
     double *Phi[2];          // [nw]
     const void *fstar;       // frozen primal f (= f[primal parity at adjoint init])
-    double *acoef;           // [nc][16] per-cell adjoint coefficients
+    double *acoef;           // [nc][kAcoef] per-cell adjoint coefficients (see k_adjoint_coef)
     // sensitivity / objective
     double *Jl;              // [nw]
     double *sens;            // [nw][5]: S_A, S_x(2), S_n(2)

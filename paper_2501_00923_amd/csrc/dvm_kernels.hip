@@ -136,7 +136,16 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
     const double th = (2.0 / 3.0) * (W3 / rho - 0.5 * (u1 * u1 + u2 * u2));
     const double itau = d.inv_tau_inf * rho * sqrt(2.0 * th);
     const double Vt = d.vol[c] * itau;
-    patch_tables<T, false>(d, sm, w, lane, u1, u2, 0.5 / th);
+    // the equilibrium's parameters: the primitive variables, or those whose
+    // grid moments equal W (tau keeps the cell's own rho and theta)
+    double Pe[4] = {rho, u1, u2, th};
+    if (d.equil) {
+        const double Wv[4] = {W0, W1, W2, W3};
+        eq_conservative(d, Wv, Pe, nullptr);
+#pragma unroll
+        for (int a = 0; a < 4; a++) Pe[a] = uni(Pe[a]);
+    }
+    patch_tables<T, false>(d, sm, w, lane, Pe[1], Pe[2], 0.5 / Pe[3]);
 
     const size_t row = (size_t)c * nv;
     int nb[4];
@@ -167,8 +176,8 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
         src[q] = n >= 0 ? fin + (size_t)n * nv : static_cast<const T2 *>(n == -1 ? d.fd : d.gw2);
         sc[q] = n <= -2 ? wcoef : (T)1;
     }
-    const T th2 = uni((T)(0.5 * th));
-    const T gc = uni((T)(rho / (2.0 * kPi * th))), VtT = uni((T)Vt);
+    const T th2 = uni((T)(0.5 * Pe[3]));
+    const T gc = uni((T)(Pe[0] / (2.0 * kPi * Pe[3]))), VtT = uni((T)Vt);
     __syncthreads();
 
     double m0 = 0, m1 = 0, m2 = 0, m3 = 0, mF = 0;
@@ -420,17 +429,18 @@ __device__ __forceinline__ void adjoint_terms(double &A0, double &A1, double &A2
 __device__ __forceinline__ void adjoint_store(const DevSolve &d, const double *ac, int wl, const double *acc,
                                               double *ao, double *Phi)
 {
-    const double rho = ac[0], u1 = ac[1], u2 = ac[2], th = ac[3], itau = ac[4], E = ac[10];
-    // phi . dg/dP with P = (rho, u1, u2, theta)
-    const double P0 = acc[0] / rho;
-    const double P1 = acc[1] / th, P2 = acc[2] / th;
-    const double P3 = acc[3] / (2.0 * th * th) - acc[0] / th + 0.5 * acc[4];
-    const double ir = 1.0 / rho;
-    // What_m = sum_q P_q dP_q/dW_m
-    ao[0] = P0 - P1 * u1 * ir - P2 * u2 * ir + P3 * (2.0 / 3.0) * (u1 * u1 + u2 * u2 - E) * ir;
-    ao[1] = P1 * ir - P3 * (2.0 / 3.0) * u1 * ir;
-    ao[2] = P2 * ir - P3 * (2.0 / 3.0) * u2 * ir;
-    ao[3] = P3 * (2.0 / 3.0) * ir;
+    const double rho = ac[0], th = ac[3], itau = ac[4];
+    const double *M = ac + 16;      // dP/dW, P = the equilibrium's (rho, u1, u2, theta)
+    // phi . dg/dP
+    double Pq[4];
+    Pq[0] = acc[0] / rho;
+    Pq[1] = acc[1] / th;
+    Pq[2] = acc[2] / th;
+    Pq[3] = acc[3] / (2.0 * th * th) - acc[0] / th + 0.5 * acc[4];
+    // What_m = sum_q (phi . dg/dP_q) dP_q/dW_m
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+        ao[m] = ((Pq[0] * M[m] + Pq[1] * M[4 + m]) + Pq[2] * M[8 + m]) + Pq[3] * M[12 + m];
     ao[4] = acc[5] * itau;
     if (wl >= 0) Phi[wl] = -acc[6] / (d.wall_A[wl] * d.D[wl]);
 }
@@ -459,7 +469,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
     const T2 *__restrict__ fst = static_cast<const T2 *>(d.fstar);
     const T2 *__restrict__ eterm = static_cast<const T2 *>(d.corr);
 
-    const double *ac = d.acoef + 16 * c;
+    const double *ac = d.acoef + kAcoef * c;
     const double u1 = uni(ac[1]), u2 = uni(ac[2]), th = uni(ac[3]), itau = uni(ac[4]);
     const double gcoef = ac[5];
     const double dt0 = ac[6], dt1 = ac[7], dt2 = ac[8], dt3 = ac[9];
@@ -697,7 +707,7 @@ __device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, 
     const T2 *__restrict__ pin = static_cast<const T2 *>(d.phi[par]);
     const T2 *__restrict__ fst = static_cast<const T2 *>(d.fstar);
     const T *__restrict__ gM = static_cast<const T *>(d.gM);
-    const double *ac = d.acoef + 16 * c;
+    const double *ac = d.acoef + kAcoef * c;
     const double u1 = uni(ac[1]), u2 = uni(ac[2]), th = uni(ac[3]);
     patch_tables<T, false>(d, sm, w, lane, u1, u2, 0.5 / th);
     const int l0 = uni(d.nbr[4 * c]);
@@ -898,32 +908,49 @@ __global__ void k_zero(T *p, size_t n)
         p[i] = (T)0;
 }
 
-// per-cell adjoint coefficients from the frozen moments
-__global__ void k_adjoint_coef(DevSolve d, const double *Wst)
+// per-cell adjoint coefficients from the frozen moments, one wave per cell:
+// ac[0..3] the equilibrium's (rho, u1, u2, theta), ac[4] 1/tau (the cell's
+// own rho, theta), ac[5] rho/(2 pi theta) of the equilibrium, ac[6..9]
+// (1/tau) dtau/dW, ac[16..31] dP/dW (row = parameter, column = moment)
+__global__ __launch_bounds__(kBlock) void k_adjoint_coef(DevSolve d, const double *Wst)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.nc) return;
+    const int c = blockIdx.x * (kBlock / kWave) + (int)(threadIdx.x / kWave);
+    if (c >= d.nc) return;                      // whole waves; the kernel has no block barrier
     const double *W = Wst + 4 * c;
     const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho, E = W[3] / rho;
     const double th = (2.0 / 3.0) * (E - 0.5 * (u1 * u1 + u2 * u2));
     const double itau = d.inv_tau_inf * rho * sqrt(2.0 * th);
-    double *ac = d.acoef + 16 * c;
-    ac[0] = rho;
-    ac[1] = u1;
-    ac[2] = u2;
-    ac[3] = th;
-    ac[4] = itau;
-    ac[5] = rho / (2.0 * kPi * th);
-    // (1/tau) dtau/dW, tau ~ 1 / (rho sqrt(theta)) (hard sphere)
     const double ir = 1.0 / rho, k23 = 2.0 / 3.0;
+    // d theta / dW of the cell's own primitive variables
     const double dth0 = k23 * (u1 * u1 + u2 * u2 - E) * ir, dth1 = -k23 * u1 * ir, dth2 = -k23 * u2 * ir,
                  dth3 = k23 * ir;
+    double P[4] = {rho, u1, u2, th}, M[16];
+    if (d.equil) {
+        const double Wv[4] = {W[0], W[1], W[2], W[3]};
+        eq_conservative(d, Wv, P, M);
+    } else {
+        const double J[16] = {1.0, 0.0, 0.0, 0.0, -u1 * ir, ir, 0.0, 0.0, -u2 * ir, 0.0, ir, 0.0,
+                              dth0, dth1, dth2, dth3};
+#pragma unroll
+        for (int q = 0; q < 16; q++) M[q] = J[q];
+    }
+    if (threadIdx.x % kWave != 0) return;
+    double *ac = d.acoef + kAcoef * c;
+    ac[0] = P[0];
+    ac[1] = P[1];
+    ac[2] = P[2];
+    ac[3] = P[3];
+    ac[4] = itau;
+    ac[5] = P[0] / (2.0 * kPi * P[3]);
+    // (1/tau) dtau/dW, tau ~ 1 / (rho sqrt(theta)) (hard sphere)
     const double h = 0.5 / th;
     ac[6] = -ir - h * dth0;
     ac[7] = -h * dth1;
     ac[8] = -h * dth2;
     ac[9] = -h * dth3;
     ac[10] = E;
+    for (int q = 11; q < 16; q++) ac[q] = 0.0;
+    for (int q = 0; q < 16; q++) ac[16 + q] = M[q];
 }
 
 // Phi_l of phi = 0 (only the objective's m_J term): one block per element
@@ -1068,7 +1095,8 @@ hipError_t launch_objective(const DevSolve &d, int par, hipStream_t st)
 
 hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adjoint_coef, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d, d.W[fpar]);
+    constexpr int per_block = kBlock / kWave;
+    hipLaunchKernelGGL(k_adjoint_coef, dim3((d.nc + per_block - 1) / per_block), dim3(kBlock), 0, st, d, d.W[fpar]);
     if (hipError_t e = hipGetLastError()) return e;
     const size_t n = (size_t)d.nc * d.nv * 2;
     if (d.mixed)

@@ -194,11 +194,10 @@ __global__ __launch_bounds__(kBlock) void k_mesh_sens_cell(DevSolve d, int fpar,
     const T2 *ph = static_cast<const T2 *>(d.phi[ppar]);
     const T2 *fd = static_cast<const T2 *>(d.fd);
     const T *gM = static_cast<const T *>(d.gM);
-    const double *W = d.W[fpar] + 4 * c;
-    const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho;
-    const double th = (2.0 / 3.0) * (W[3] / rho - 0.5 * (u1 * u1 + u2 * u2));
-    const double itau = d.inv_tau_inf * rho * sqrt(2.0 * th);
-    const double gc = rho / (2.0 * kPi * th);
+    // the frozen state's equilibrium (parameters and 1/tau from the adjoint
+    // coefficients)
+    const double *ac = d.acoef + kAcoef * c;
+    const double u1 = ac[1], u2 = ac[2], th = ac[3], itau = ac[4], gc = ac[5];
     int nb[4];
     double Sx[4], Sy[4];
     for (int q = 0; q < 4; q++) {
@@ -318,11 +317,10 @@ __global__ __launch_bounds__(kBlock) void k_mesh_sens_cell_so(DevSolve d, int fp
     const T *gM = static_cast<const T *>(d.gM);
     const T *Gs = static_cast<const T *>(d.G);
     const T2 *ps = static_cast<const T2 *>(d.psi);
-    const double *W = d.W[fpar] + 4 * c;
-    const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho;
-    const double th = (2.0 / 3.0) * (W[3] / rho - 0.5 * (u1 * u1 + u2 * u2));
-    const double itau = d.inv_tau_inf * rho * sqrt(2.0 * th);
-    const double gc = rho / (2.0 * kPi * th);
+    // the frozen state's equilibrium (parameters and 1/tau from the adjoint
+    // coefficients)
+    const double *ac = d.acoef + kAcoef * c;
+    const double u1 = ac[1], u2 = ac[2], th = ac[3], itau = ac[4], gc = ac[5];
     int nb[4];
     double Sx[4], Sy[4], rfx[4], rfy[4], rnx[4], rny[4];
     for (int q = 0; q < 4; q++) {

@@ -182,3 +182,94 @@ def test_c1_circle_full_size():
     assert abs(J - Jo) <= 1e-10 * abs(Jo)
     assert abs(Cd - Jo / o.cd_scale()) <= 1e-10 * abs(Cd)
     assert _rel(g, go) <= 1e-10
+
+
+EQ_CASES = ["tiny_circle", "tiny_naca", "c_nc24", "c_sinh36", "heat_hotwall", "o12x6_v17", "o70x20_tiles"]
+
+
+def _run_eq(wl, precision, n_primal, n_adjoint, order=1):
+    """Both sides with the discrete-conservative equilibrium."""
+    _say(f"[gpu-eq] {wl.name} precision={precision} order={order} primal={n_primal} adjoint={n_adjoint}")
+    s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=dvm.EQ_CONSERVATIVE, order=order,
+                                 correction_every=5)
+    o = oracle.Problem.from_workload(wl, nthreads=NTHREADS)
+    o.set_equilibrium(1)
+    if order == 2:
+        o.set_scheme(2, True, 5)
+    s.primal_init()
+    o.primal_init()
+    _, rps = s.primal_iterate(n_primal)
+    rpo = o.primal_iterate(n_primal)
+    s.adjoint_init()
+    o.adjoint_init()
+    _, ras = s.adjoint_iterate(n_adjoint)
+    rao = o.adjoint_iterate(n_adjoint)
+    return s, o, (rps, rpo), (ras, rao)
+
+
+@pytest.mark.parametrize("name", EQ_CASES)
+def test_fp64_conservative_equilibrium_parity(name):
+    wl = _case(name)
+    s, o, rp, ra = _run_eq(wl, dvm.FP64, 37, 29)
+    check_resid(*rp, label=f"{name} conservative primal")
+    check_resid(*ra, label=f"{name} conservative adjoint")
+    ef, eW, ep = _rel(s.state_array(dvm.STATE_F), o.f), _rel(s.moments(), o.W), _rel(s.state_array(dvm.STATE_PHI), o.phi)
+    J, _ = s.objective()
+    Jo = o.objective()
+    _say(f"[gpu-eq] {name}: f {ef:.2e} W {eW:.2e} phi {ep:.2e} J {abs(J - Jo) / abs(Jo):.2e}")
+    assert ef <= 1e-11 and eW <= 1e-11 and ep <= 1e-11
+    assert abs(J - Jo) <= 1e-10 * abs(Jo)
+    check_sens(s.wall_sensitivity(), o.wall_sensitivity(), 1e-10, f"{name} conservative")
+    assert _rel(s.mesh_sensitivity(), o.mesh_sensitivity()) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["tiny_circle", "c_sinh36", "o12x6_v17"])
+def test_mixed_conservative_equilibrium_parity(name):
+    wl = _case(name)
+    s, o, _, _ = _run_eq(wl, dvm.MIXED, 37, 29)
+    ef = _rel(s.state_array(dvm.STATE_F), o.f)
+    J, _ = s.objective()
+    Jo = o.objective()
+    eS = check_sens(s.wall_sensitivity(), o.wall_sensitivity(), 1e-3, f"{name} conservative mixed")
+    _say(f"[gpu-eq mixed] {name}: f {ef:.2e} J {abs(J - Jo) / abs(Jo):.2e} sens {eS:.2e}")
+    assert ef <= 2e-5 and abs(J - Jo) <= 2e-5 * abs(Jo)
+
+
+def test_second_order_conservative_equilibrium_parity():
+    wl = _case("tiny_naca")
+    s, o, rp, ra = _run_eq(wl, dvm.FP64, 23, 17, order=2)
+    check_resid(*rp, label="order-2 conservative primal")
+    check_resid(*ra, label="order-2 conservative adjoint")
+    assert _rel(s.state_array(dvm.STATE_F), o.f) <= 1e-11
+    assert _rel(s.state_array(dvm.STATE_PHI), o.phi) <= 1e-11
+    check_sens(s.wall_sensitivity(), o.wall_sensitivity(), 1e-10, "order 2 conservative")
+
+
+def test_near_continuum_case_converges_with_the_conservative_equilibrium():
+    """128x64 NACA0012 C-grid, 32x32 Newton-Cotes velocities on [-6, 6],
+    Kn 0.01, Ma 0.5: the pointwise equilibrium's Jacobi iteration turns
+    non-finite within 400 sweeps (DVM_ENAN); the conservative one decreases
+    its residual every 50 sweeps and matches the oracle after 100."""
+    g = I.naca_cgrid(16, 48, 64, t=0.12, m=0.0)
+    wl = I.Workload("naca0012_c128x64_v32nc_kn0.01", g, I.VGridSpec(I.VG_NEWTON_COTES, 32, 32, 6.0),
+                    I.FlowSpec(0.01, 0.5), 0)
+    _say("[gpu-eq] near-continuum case: pointwise")
+    p = dvm.Solver.from_workload(wl)
+    p.primal_init()
+    with pytest.raises(dvm.DvmError) as ei:
+        p.primal_iterate(400, tol=1e-300, check_every=50)
+    assert ei.value.code == dvm.DVM_ENAN
+    _say("[gpu-eq] near-continuum case: conservative")
+    s = dvm.Solver.from_workload(wl, equilibrium=dvm.EQ_CONSERVATIVE)
+    s.primal_init()
+    rs = [s.primal_iterate(50)[1] for _ in range(8)]
+    _say(f"[gpu-eq] residuals every 50 sweeps: {' '.join(f'{r:.2e}' for r in rs)}")
+    assert all(b < a for a, b in zip(rs, rs[1:]))
+    o = oracle.Problem.from_workload(wl, nthreads=NTHREADS)
+    o.set_equilibrium(1)
+    o.primal_init()
+    o.primal_iterate(100)
+    t = dvm.Solver.from_workload(wl, equilibrium=dvm.EQ_CONSERVATIVE)
+    t.primal_init()
+    t.primal_iterate(100)
+    assert _rel(t.state_array(dvm.STATE_F), o.f) <= 1e-11

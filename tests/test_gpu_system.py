@@ -185,3 +185,42 @@ def test_runs_on_a_side_stream():
         s.primal_init()
         s.primal_sweeps(8)
     assert np.array_equal(ref.state_save(dvm.STATE_F), s.state_save(dvm.STATE_F))
+
+
+@pytest.mark.parametrize("precision", [dvm.FP64, dvm.MIXED])
+def test_batch_with_conservative_members_bitwise(precision):
+    """Members with the conservative equilibrium beside pointwise ones: each
+    ends bitwise where it would alone; a checkpointed state continues
+    bitwise."""
+    _say(f"[gpu] batch with conservative-equilibrium members precision={precision}")
+    def make(wl, eq):
+        s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=eq)
+        s.primal_init()
+        return s
+    alone = []
+    for i, wl in enumerate(MIX):
+        s = make(wl, i % 2)
+        s.primal_sweeps(9)
+        s.adjoint_init()
+        s.adjoint_sweeps(4)
+        alone.append(s.state_save(dvm.STATE_PHI))
+    members = [make(wl, i % 2) for i, wl in enumerate(MIX)]
+    b = dvm.Batch(members)
+    b.run(9)
+    b.close()
+    for s in members:
+        s.adjoint_init()
+    b = dvm.Batch(members)
+    b.run(4)
+    b.close()
+    for a, s in zip(alone, members):
+        assert np.array_equal(a, s.state_save(dvm.STATE_PHI))
+    # resume from a checkpoint of f (conservative member)
+    s = make(MIX[2], 1)
+    s.primal_sweeps(6)
+    snap = s.state_save(dvm.STATE_F)
+    s.primal_sweeps(5)
+    t = dvm.Solver.from_workload(MIX[2], precision=precision, equilibrium=1)
+    t.state_load(dvm.STATE_F, snap)
+    t.primal_sweeps(5)
+    assert np.array_equal(s.state_save(dvm.STATE_F), t.state_save(dvm.STATE_F))

@@ -81,6 +81,9 @@ def lib():
         L.or_set_equilibrium.restype = I
         L.or_set_equilibrium.argtypes = [P, I]
         L.or_eq_params.argtypes = [P, dp, dp, dp]
+        L.or_set_acceleration.restype = I
+        L.or_set_acceleration.argtypes = [P, I, I]
+        L.or_macro_system.argtypes = [P, dp, dp, dp]
         L.or_wall_JB.restype = D
         L.or_wall_JB.argtypes = [P, I, D, D, D, D, D]
         L.or_set_scheme.restype = I
@@ -157,6 +160,21 @@ class Problem:
         if lib().or_set_equilibrium(self._h, int(kind)) != 0:
             raise ValueError("oracle: invalid equilibrium")
         self.equilibrium = int(kind)
+
+    def set_acceleration(self, every: int, inner: int):
+        """Macroscopic prediction every `every` primal sweeps (0: off) with
+        `inner` red-black block Gauss-Seidel steps (first-order scheme)."""
+        if lib().or_set_acceleration(self._h, int(every), int(inner)) != 0:
+            raise ValueError("oracle: invalid acceleration")
+
+    def macro_system(self):
+        """The macroscopic prediction's system at the current state: r [nc,4],
+        D^-1 [nc,4,4], off-diagonal blocks [nc,4(face),4,4]."""
+        r = np.zeros((self.nc, 4))
+        Dinv = np.zeros((self.nc, 4, 4))
+        O = np.zeros((self.nc, 4, 4, 4))
+        lib().or_macro_system(self._h, r, Dinv, O)
+        return r, Dinv, O
 
     def eq_params(self, W):
         """Equilibrium parameters (rho', u1', u2', theta') of a moment vector

@@ -134,6 +134,12 @@ typedef struct {
     double *eqP;       /* [nc][4] (rho', u1', u2', theta') of the current W */
     double *eqM;       /* [nc][4][4] d(rho', u1', u2', theta')/dW */
     int eq_ok;         /* eqP, eqM hold the current W */
+
+    /* prediction acceleration (primal, first order; see "macroscopic
+     * prediction"): every acc_every sweeps, acc_inner red-black block
+     * Gauss-Seidel steps on the macroscopic system */
+    int acc_every, acc_inner, acc_sweeps;
+    double acc_alpha;
 } or_problem;
 
 /* ------------------------------------------------------------------ */
@@ -721,6 +727,7 @@ void or_primal_init(or_problem *p)
         memcpy(p->f + (size_t)c * nv * 2, p->fd, sizeof(double) * 2 * nv);
     update_W_F(p, p->f);
     p->corr_ok = 0;
+    p->acc_sweeps = 0;
 }
 
 /* value of f carried into cell c through face q at velocity k (s <= 0);
@@ -952,6 +959,186 @@ void or_so_faces(or_problem *p, const double *f, double *out)
     free(G); free(F2); free(Ws); free(Fs);
 }
 
+/* ------------------------------------------------------------------ */
+/* macroscopic prediction                                              */
+/* ------------------------------------------------------------------ */
+/* Sec. 3.1 accelerates the primal (and adjoint) kinetic iterations with
+ * "prediction" solutions of approximate macroscopic equations taken from the
+ * continuum limit and defers the scheme to its references.  The reading
+ * taken here is a synthetic-acceleration step in the spirit of the implicit
+ * gas-kinetic schemes' macroscopic prediction (Zhu, Zhong & Xu, J. Comput.
+ * Phys. 2016) and of the general synthetic iterative scheme (Su, Zhu & Wu,
+ * J. Comput. Phys. 2020): every K sweeps,
+ *   1. r_c = sum_k w Psi_k R_c,k, the moments of the kinetic residual R of
+ *      eq. (numerpr_gov) at the current f (zero at the discrete solution:
+ *      the step cannot move the fixed point);
+ *   2. A dW = -r, with A the moments of the upwind transport of Maxwellian
+ *      perturbations, A dW = sum_k w Psi_k sum_q (v_k . S_q) dg_face,k: the
+ *      outflow faces carry the cell's own dg/dW dW_c, the inflow faces the
+ *      neighbour's, nothing from the far field, and the wall face the
+ *      diffuse value's response gbar_k dF_l (dF_l = sum_{v.n>0} w (v.n)
+ *      dg1/dW dW_c) -- the exact linearisation of the transport of the
+ *      discrete scheme restricted to local equilibria (a kinetic
+ *      flux-vector-split Euler operator), solved approximately by
+ *      red-black block Gauss-Seidel steps from dW = 0;
+ *   3. each cell's correction is limited so that rho and theta change by
+ *      at most a fraction alpha (0.2) in one step;
+ *   4. the predicted moments W + dW replace W as the state the next sweep
+ *      relaxes towards (g and tau of that sweep).  The sweep weights the
+ *      prediction per velocity by its collision share V/tau / (V/tau +
+ *      sum_out v.S): it takes hold where collisions dominate and fades in
+ *      cells thinner than a mean free path, where the kinetic sweep itself
+ *      is the right solver and the inviscid macroscopic operator is not.
+ * A fixed point of the accelerated iteration has r = 0, i.e. solves the
+ * discrete equations, and the plain iteration's solution has r = 0, dW = 0:
+ * both iterations share their solutions. */
+
+/* the macroscopic system of the current f (first order): r [nc][4], Dinv
+ * [nc][16] (inverse of the cell's own block), O [nc][4][16] (blocks of the
+ * four face neighbours; zero for boundary faces) */
+static void macro_assemble(or_problem *p, double *r, double *Dinv, double *O)
+{
+    const int nv = p->nv;
+    eq_cache(p);
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+    for (int c = 0; c < p->nc; c++) {
+        double rho, u1, u2, th;
+        prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+        const double itau = inv_tau_of(p, rho, th), V = p->vol[c];
+        double rc[4] = { 0, 0, 0, 0 }, Dc[4][4] = { { 0 } }, Oc[4][4][4] = { { { 0 } } };
+        int wl = -1;
+        for (int q = 0; q < 4; q++) if (p->nbr[4 * c + q] <= -2) wl = -2 - p->nbr[4 * c + q];
+        double dF[4] = { 0, 0, 0, 0 }, wall1[4] = { 0, 0, 0, 0 };
+        for (int k = 0; k < nv; k++) {
+            const double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], wk = p->w[k];
+            const double psi[4] = { 1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2) };
+            const double *fc = p->f + ((size_t)c * nv + k) * 2;
+            double dgc[2][4], dtt[4], g1, g2;
+            dg_dW_cell(p, c, k, dgc, dtt);
+            eq_cell_g(p, c, k, &g1, &g2);
+            /* collision part of the residual (zero for the conservative equilibrium) */
+            const double e1 = V * itau * (fc[0] - g1), e2 = V * itau * (fc[1] - g2);
+            for (int a = 0; a < 4; a++) rc[a] += wk * (psi[a] * e1 + (a == 3 ? e2 : 0.0));
+            for (int q = 0; q < 4; q++) {
+                const double s = v1 * p->S[8 * c + 2 * q] + v2 * p->S[8 * c + 2 * q + 1];
+                double a1, a2;
+                if (s > 0) {
+                    a1 = fc[0]; a2 = fc[1];
+                    for (int a = 0; a < 4; a++)
+                        for (int b = 0; b < 4; b++) Dc[a][b] += wk * s * (psi[a] * dgc[0][b] + (a == 3 ? dgc[1][b] : 0.0));
+                } else {
+                    inflow_value(p, p->f, p->F, c, q, k, &a1, &a2);
+                    const int nb = p->nbr[4 * c + q];
+                    if (nb >= 0) {
+                        double dgn[2][4], dttn[4];
+                        dg_dW_cell(p, nb, k, dgn, dttn);
+                        for (int a = 0; a < 4; a++)
+                            for (int b = 0; b < 4; b++)
+                                Oc[q][a][b] += wk * s * (psi[a] * dgn[0][b] + (a == 3 ? dgn[1][b] : 0.0));
+                    } else if (nb <= -2) {
+                        const double gb1 = p->gM[k] / p->D[wl], gb2 = 0.5 * p->theta_w * gb1;
+                        for (int a = 0; a < 4; a++) wall1[a] += wk * s * (psi[a] * gb1 + (a == 3 ? gb2 : 0.0));
+                    }
+                }
+                for (int a = 0; a < 4; a++) rc[a] += wk * s * (psi[a] * a1 + (a == 3 ? a2 : 0.0));
+            }
+            if (wl >= 0) {
+                const double vn = v1 * p->wn[2 * wl] + v2 * p->wn[2 * wl + 1];
+                if (vn > 0) for (int b = 0; b < 4; b++) dF[b] += wk * vn * dgc[0][b];
+            }
+        }
+        for (int a = 0; a < 4; a++) for (int b = 0; b < 4; b++) Dc[a][b] += wall1[a] * dF[b];
+        for (int b = 0; b < 4; b++) {
+            double e[4] = { 0, 0, 0, 0 }, col[4];
+            e[b] = 1.0;
+            solve4(Dc, e, col);
+            for (int a = 0; a < 4; a++) Dinv[16 * c + 4 * a + b] = col[a];
+        }
+        for (int q = 0; q < 4; q++)
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) O[64 * c + 16 * q + 4 * a + b] = Oc[q][a][b];
+        for (int a = 0; a < 4; a++) r[4 * c + a] = rc[a];
+    }
+}
+
+/* red-black block Gauss-Seidel from x = 0: colour (i + j) % 2 in mesh
+ * numbering, red (0) first; each half step reads the other array */
+static void macro_solve(or_problem *p, const double *r, const double *Dinv, const double *O, double *x)
+{
+    const int nc = p->nc;
+    double *y = calloc(4 * (size_t)nc, sizeof(double));
+    memset(x, 0, sizeof(double) * 4 * nc);
+    for (int it = 0; it < p->acc_inner; it++) {
+        for (int col = 0; col < 2; col++) {
+            const double *src = col == 0 ? x : y;
+            double *dst = col == 0 ? y : x;
+            for (int c = 0; c < nc; c++) {
+                const int i = c % p->ni, j = c / p->ni;
+                if ((i + j) % 2 != col) { for (int a = 0; a < 4; a++) dst[4 * c + a] = src[4 * c + a]; continue; }
+                double b[4];
+                for (int a = 0; a < 4; a++) b[a] = -r[4 * c + a];
+                for (int q = 0; q < 4; q++) {
+                    const int nb = p->nbr[4 * c + q];
+                    if (nb < 0) continue;
+                    for (int a = 0; a < 4; a++)
+                        for (int e = 0; e < 4; e++) b[a] -= O[64 * c + 16 * q + 4 * a + e] * src[4 * nb + e];
+                }
+                for (int a = 0; a < 4; a++) {
+                    double acc = 0;
+                    for (int e = 0; e < 4; e++) acc += Dinv[16 * c + 4 * a + e] * b[e];
+                    dst[4 * c + a] = acc;
+                }
+            }
+        }
+    }
+    free(y);
+}
+
+/* theta of a moment vector */
+static double theta_of(const double *W)
+{
+    double rho, u1, u2, th;
+    prim(W, &rho, &u1, &u2, &th);
+    return th;
+}
+
+static void macro_predict(or_problem *p)
+{
+    const int nc = p->nc;
+    double *r = malloc(sizeof(double) * 4 * nc), *Dinv = malloc(sizeof(double) * 16 * nc);
+    double *O = malloc(sizeof(double) * 64 * (size_t)nc);
+    double *x = malloc(sizeof(double) * 4 * nc);
+    macro_assemble(p, r, Dinv, O);
+    macro_solve(p, r, Dinv, O, x);
+    for (int c = 0; c < nc; c++) {
+        double *W = p->W + 4 * c, Wt[4];
+        for (int a = 0; a < 4; a++) Wt[a] = W[a] + x[4 * c + a];
+        const double th0 = theta_of(W), th1 = theta_of(Wt);
+        const double ch = fmax(fabs(x[4 * c]) / W[0], fabs(th1 - th0) / th0);
+        double fac = 0.0;
+        if (Wt[0] > 0 && th1 > 0 && isfinite(ch)) fac = ch > p->acc_alpha ? p->acc_alpha / ch : 1.0;
+        for (int a = 0; a < 4; a++) W[a] += fac * x[4 * c + a];
+    }
+    p->eq_ok = 0;
+    free(r); free(Dinv); free(O); free(x);
+}
+
+int or_set_acceleration(or_problem *p, int every, int inner)
+{
+    if (every < 0 || inner < 0) return -1;
+    p->acc_every = every;
+    p->acc_inner = inner;
+    p->acc_alpha = 0.2;
+    return 0;
+}
+
+/* the macroscopic system of the current state (pins): r [nc][4], D^-1
+ * [nc][4][4], O [nc][4][4][4] */
+void or_macro_system(or_problem *p, double *r, double *Dinv, double *O)
+{
+    macro_assemble(p, r, Dinv, O);
+}
+
 /* One Jacobi sweep of eq. (numerpr_gov), every cell from f^n.  Returns the
  * relative change of W in the 2-norm. */
 double or_primal_iterate(or_problem *p, int niter)
@@ -1011,13 +1198,15 @@ double or_primal_iterate(or_problem *p, int niter)
         }
         free(Wold);
         r = sqrt(num / den);
+        p->acc_sweeps++;
+        if (p->acc_every > 0 && p->order == 1 && p->acc_sweeps % p->acc_every == 0) macro_predict(p);
     }
     free(Fw);
     return r;
 }
 
 void or_get_f(const or_problem *p, double *out) { memcpy(out, p->f, sizeof(double) * (size_t)p->nc * p->nv * 2); }
-void or_set_f(or_problem *p, const double *in) { memcpy(p->f, in, sizeof(double) * (size_t)p->nc * p->nv * 2); update_W_F(p, p->f); p->corr_ok = 0; }
+void or_set_f(or_problem *p, const double *in) { memcpy(p->f, in, sizeof(double) * (size_t)p->nc * p->nv * 2); update_W_F(p, p->f); p->corr_ok = 0; p->acc_sweeps = 0; }
 void or_get_W(const or_problem *p, double *out) { memcpy(out, p->W, sizeof(double) * 4 * p->nc); }
 void or_get_phi(const or_problem *p, double *out) { memcpy(out, p->phi, sizeof(double) * (size_t)p->nc * p->nv * 2); }
 void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); p->acorr_ok = 0; }

@@ -463,6 +463,7 @@ static void eq_params_z(const or_problem *p, const double complex *W, double com
 int or_set_equilibrium(or_problem *p, int kind)
 {
     if (kind != 0 && kind != 1) return -1;
+    if (kind != 1 && p->acc_every > 0) return -1;
     p->equilibrium = kind;
     p->eq_ok = 0;
     return 0;
@@ -991,7 +992,10 @@ void or_so_faces(or_problem *p, const double *f, double *out)
  *      is the right solver and the inviscid macroscopic operator is not.
  * A fixed point of the accelerated iteration has r = 0, i.e. solves the
  * discrete equations, and the plain iteration's solution has r = 0, dW = 0:
- * both iterations share their solutions. */
+ * both iterations share their solutions.  The step needs the conservative
+ * equilibrium: the macroscopic equations are conservation laws, and only
+ * then does an equilibrium perturbation dg/dW dW carry the moments dW (the
+ * collision term's moments then vanish identically). */
 
 /* the macroscopic system of the current f (first order): r [nc][4], Dinv
  * [nc][16] (inverse of the cell's own block), O [nc][4][16] (blocks of the
@@ -1125,7 +1129,9 @@ static void macro_predict(or_problem *p)
 
 int or_set_acceleration(or_problem *p, int every, int inner)
 {
-    if (every < 0 || inner < 0) return -1;
+    /* the macroscopic equations are conservation laws: the conservative
+     * equilibrium, first order */
+    if (every < 0 || inner < 0 || (every > 0 && p->equilibrium != 1)) return -1;
     p->acc_every = every;
     p->acc_inner = inner;
     p->acc_alpha = 0.2;

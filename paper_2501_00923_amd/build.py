@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdvm.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("dvm_kernels.hip", "dvm_sens.hip", "dvm_so.hip", "dvm_rbf.hip", "dvm_host.cpp",
-                                                 "dvm_shape.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("dvm_kernels.hip", "dvm_sens.hip", "dvm_so.hip", "dvm_macro.hip", "dvm_rbf.hip",
+                                                 "dvm_host.cpp", "dvm_shape.cpp")]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
 # -ffp-contract=off: every a*b+c is rounded as written, so a kernel body gives

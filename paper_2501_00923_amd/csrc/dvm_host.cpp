@@ -266,10 +266,14 @@ struct dvm_solver {
     // spatial scheme: order 1, or 2 with limiter and K sweeps between corrections
     int order = 1, limiter = DVM_LIMITER_VENKAT, kcorr = 40;
     int equil = DVM_EQ_POINTWISE;
+    // macroscopic prediction every acc_every primal sweeps (0: off) with
+    // acc_inner red-black steps; acc_count = primal sweeps since the state began
+    int acc_every = 0, acc_inner = 0, acc_count = 0;
     // workspace
     struct {
         size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
         size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, msens, dJdx, out;
+        size_t mstate, mr, mDinv, mO, mx[2];
         size_t rf, rn, G, corr, psi, dF, total;
     } off;
     char *base = nullptr;
@@ -351,6 +355,16 @@ void layout(dvm_solver &s)
     } else {
         o.rf = o.rn = o.G = o.corr = o.dF = o.psi = (size_t)-1;
     }
+    if (s.acc_every > 0) {
+        o.mstate = take(20 * nc * sizeof(double));
+        o.mr = take(4 * nc * sizeof(double));
+        o.mDinv = take(16 * nc * sizeof(double));
+        o.mO = take(64 * nc * sizeof(double));
+        o.mx[0] = take(4 * nc * sizeof(double));
+        o.mx[1] = take(4 * nc * sizeof(double));
+    } else {
+        o.mstate = o.mr = o.mDinv = o.mO = o.mx[0] = o.mx[1] = (size_t)-1;
+    }
     o.total = cur;
 }
 
@@ -424,6 +438,12 @@ void fill_dev(dvm_solver &s)
     d.corr = at<void>(s, s.off.corr);
     d.psi = at<void>(s, s.off.psi);
     d.dF = at<double>(s, s.off.dF);
+    d.mstate = at<double>(s, s.off.mstate);
+    d.mr = at<double>(s, s.off.mr);
+    d.mDinv = at<double>(s, s.off.mDinv);
+    d.mO = at<double>(s, s.off.mO);
+    d.mx[0] = at<double>(s, s.off.mx[0]);
+    d.mx[1] = at<double>(s, s.off.mx[1]);
 }
 
 int upload(dvm_solver &s, size_t off, const void *src, size_t bytes)
@@ -493,6 +513,8 @@ int sweeps(dvm_solver &s, int adjoint, int n)
         } else {
             HIP_OK(dvm::launch_primal_sweep(s.dev, s.fpar, s.stream));
             s.fpar ^= 1;
+            if (s.acc_every > 0 && ++s.acc_count % s.acc_every == 0)
+                HIP_OK(dvm::launch_macro_predict(s.dev, s.fpar, s.acc_inner, s.stream));
         }
         s.since[adjoint]++;
     }
@@ -804,6 +826,7 @@ int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_
     if (order != 1 && order != 2) return fail(DVM_EINVAL, "order must be 1 or 2 (got %d)", order);
     if (limiter != DVM_LIMITER_NONE && limiter != DVM_LIMITER_VENKAT) return fail(DVM_EINVAL, "unknown limiter %d", limiter);
     if (correction_interval < 1) return fail(DVM_EINVAL, "correction interval must be >= 1");
+    if (order == 2 && s->acc_every > 0) return fail(DVM_EINVAL, "the macroscopic prediction is first-order only");
     s->order = order;
     s->limiter = limiter;
     s->kcorr = correction_interval;
@@ -817,6 +840,18 @@ int dvm_solver_set_equilibrium(dvm_solver *s, int kind)
     if (s->base) return fail(DVM_ESTATE, "the equilibrium is set before dvm_solver_bind");
     if (kind != DVM_EQ_POINTWISE && kind != DVM_EQ_CONSERVATIVE) return fail(DVM_EINVAL, "unknown equilibrium %d", kind);
     s->equil = kind;
+    return DVM_OK;
+}
+
+int dvm_solver_set_acceleration(dvm_solver *s, int every, int inner)
+{
+    if (!s) return fail(DVM_EINVAL, "null solver");
+    if (s->base) return fail(DVM_ESTATE, "the acceleration is set before dvm_solver_bind");
+    if (every < 0 || inner < 0 || inner > 100000) return fail(DVM_EINVAL, "every >= 0 and 0 <= inner <= 100000");
+    if (every > 0 && s->order != 1) return fail(DVM_EINVAL, "the macroscopic prediction is first-order only");
+    s->acc_every = every;
+    s->acc_inner = inner;
+    layout(*s);
     return DVM_OK;
 }
 
@@ -893,6 +928,7 @@ int dvm_primal_init(dvm_solver *s)
     if (int e = check_bound(s)) return e;
     HIP_OK(dvm::launch_primal_init(s->dev, s->stream));
     s->fpar = 0;
+    s->acc_count = 0;
     s->phase = 0;
     s->iters[0] = s->iters[1] = 0;
     s->corr_ok[0] = 0;
@@ -1086,6 +1122,7 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
         rows_to_dev(*s, src, tmp.data(), rowb);
         if (which == DVM_STATE_F) {
             s->fpar = 0;
+            s->acc_count = 0;
             HIP_OK(hipMemcpyAsync(s->dev.f[0], tmp.data(), all, hipMemcpyHostToDevice, s->stream));
             HIP_OK(dvm::launch_moments(s->dev, 0, s->stream));
             s->phase = 0;
@@ -1127,6 +1164,7 @@ int dvm_state_copy(dvm_solver *dst, const dvm_solver *src, int which)
     if (which == DVM_STATE_F) {
         const int par = src->phase == 1 ? src->frozen_fpar : src->fpar;
         dst->fpar = 0;
+        dst->acc_count = 0;
         HIP_OK(hipMemcpyAsync(dst->dev.f[0], src->dev.f[par], all, hipMemcpyDeviceToDevice, dst->stream));
         HIP_OK(dvm::launch_moments(dst->dev, 0, dst->stream));
         dst->phase = 0;
@@ -1400,6 +1438,13 @@ int dvm_batch_run(dvm_batch *b, int iters)
             HIP_OK(dvm::launch_batch(tab, bs + off, bc + off, par, b->step + it, b->nb_group[g], b->mixed, g >> 1,
                                      g & 1, b->stream));
             off += b->nb_group[g];
+        }
+        // primal members with the macroscopic prediction, on their own cadence
+        // (the state after this sweep sits in buffer fpar ^ ((it + 1) & 1))
+        for (int m = 0; m < b->n; m++) {
+            dvm_solver *s = b->members[m];
+            if (s->phase == 0 && s->acc_every > 0 && ++s->acc_count % s->acc_every == 0)
+                HIP_OK(dvm::launch_macro_predict(s->dev, s->fpar ^ ((it + 1) & 1), s->acc_inner, b->stream));
         }
     }
     b->step += iters;

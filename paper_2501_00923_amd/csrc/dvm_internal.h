@@ -83,6 +83,12 @@ struct DevSolve {
     void *corr;              // [nc][nv][2] held flux correction c; adjoint: held term E (storage type)
     void *psi;               // [nc][nv][2] limiter factors of the frozen f (storage type)
     double *dF;              // [nw] held wall-flux correction
+    // macroscopic prediction (primal acceleration; null when off)
+    double *mstate;          // [nc][20] equilibrium parameters P' and dP'/dW
+    double *mr;              // [nc][4] moments of the kinetic residual
+    double *mDinv;           // [nc][16] inverse of the cell's own block
+    double *mO;              // [nc][4][16] blocks of the face neighbours
+    double *mx[2];           // [nc][4] red-black iterates
 };
 
 // launches (all on `st`); par = index of the current f / phi buffer
@@ -97,6 +103,10 @@ hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_adjoint_moments(const DevSolve &d, int par, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
 hipError_t launch_mesh_sens(const DevSolve &d, int fpar, int ppar, hipStream_t st);
+// macroscopic prediction of the moments W[par] of f[par] (first-order
+// scheme): assembly, `inner` red-black block Gauss-Seidel steps, limited
+// update of W[par]
+hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream_t st);
 
 // second-order scheme: the slopes G and dF of f[par]; the held primal
 // correction c (with G and dF) from f[par]; the

@@ -33,7 +33,8 @@ _ERRNAMES = {DVM_EINVAL: "EINVAL", DVM_ENOMEM: "ENOMEM", DVM_EHIP: "EHIP", DVM_E
 EXPORTED = [
     "dvm_mesh_create", "dvm_mesh_info", "dvm_mesh_export", "dvm_mesh_destroy",
     "dvm_vgrid_create", "dvm_vgrid_info", "dvm_vgrid_export", "dvm_vgrid_destroy",
-    "dvm_solver_create", "dvm_solver_set_scheme", "dvm_solver_set_equilibrium", "dvm_solver_workspace_bytes",
+    "dvm_solver_create", "dvm_solver_set_scheme", "dvm_solver_set_equilibrium", "dvm_solver_set_acceleration",
+    "dvm_solver_workspace_bytes",
     "dvm_solver_bind",
     "dvm_solver_set_stream",
     "dvm_primal_init", "dvm_primal_iterate", "dvm_primal_sweeps", "dvm_objective", "dvm_read_moments",
@@ -91,6 +92,7 @@ def lib():
         "dvm_solver_create": (i32, [vp, vp, vp, i32, i32, pvp]),
         "dvm_solver_set_scheme": (i32, [vp, i32, i32, i32]),
         "dvm_solver_set_equilibrium": (i32, [vp, i32]),
+        "dvm_solver_set_acceleration": (i32, [vp, i32, i32]),
         "dvm_solver_workspace_bytes": (sz, [vp]),
         "dvm_solver_bind": (i32, [vp, vp, sz, vp]),
         "dvm_solver_set_stream": (i32, [vp, vp]),
@@ -235,7 +237,7 @@ class Solver:
     def __init__(self, mesh: Mesh, vgrid: VGrid, Kn: float, Ma: float, Tw: float = 1.0,
                  objective: int = OBJ_DRAG, precision: int = FP64, want_adjoint: bool = True,
                  buffer=None, stream=None, bind: bool = True, order: int = 1, limiter: int = LIMITER_VENKAT,
-                 correction_every: int = 40, equilibrium: int = EQ_POINTWISE):
+                 correction_every: int = 40, equilibrium: int = EQ_POINTWISE, accelerate=None):
         fl = _Flow(float(Kn), float(Ma), float(Tw), int(objective))
         h = C.c_void_p()
         _check(lib().dvm_solver_create(mesh._h, vgrid._h, C.byref(fl), precision, 1 if want_adjoint else 0,
@@ -245,6 +247,10 @@ class Solver:
             _check(lib().dvm_solver_set_scheme(h, int(order), int(limiter), int(correction_every)))
         if equilibrium != EQ_POINTWISE:
             _check(lib().dvm_solver_set_equilibrium(h, int(equilibrium)))
+        if accelerate:
+            # (every, inner): macroscopic prediction every `every` primal sweeps
+            _check(lib().dvm_solver_set_acceleration(h, int(accelerate[0]), int(accelerate[1])))
+        self.accelerate = tuple(accelerate) if accelerate else None
         self.order = order
         self.equilibrium = equilibrium
         self.nc, self.nw, self.nv = mesh.nc, mesh.nw, vgrid.nv

@@ -9,7 +9,7 @@ sweep relaxes towards).
   complex twin) in the direction of the equilibrium perturbation dg/dW dW
   equal D dW_c + sum_q O_q dW_nbr (conservative equilibrium: the collision
   part's moments vanish), wall coupling included; r is the moment vector of
-  the residual.
+  the residual.  The prediction is refused with the pointwise Maxwellian.
 * The discrete solution is a fixed point of the accelerated iteration, and
   the plain and accelerated iterations converge to the same state.
 * The first prediction changes rho and theta by at most 20% in any cell.
@@ -118,3 +118,13 @@ def test_prediction_is_limited_and_accelerates_near_the_continuum():
     r_q = q.primal_iterate(it_q - 5)
     assert r < 1e-8 and it + 5 <= 300, (it, r)
     assert r_q > 1e-5, r_q
+
+
+def test_prediction_needs_the_conservative_equilibrium():
+    p = oracle.Problem.from_workload(I.tiny_circle(), nthreads=1)
+    with pytest.raises(ValueError):
+        p.set_acceleration(5, 20)
+    p.set_equilibrium(1)
+    p.set_acceleration(5, 20)
+    with pytest.raises(ValueError):
+        p.set_equilibrium(0)

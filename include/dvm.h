@@ -165,9 +165,11 @@ int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_
 int dvm_solver_set_equilibrium(dvm_solver *s, int kind);
 /* Macroscopic prediction of the primal iteration (Sec. 3.1: approximate
  * macroscopic equations from the continuum limit provide prediction
- * solutions that accelerate the kinetic iteration), first-order scheme,
- * set before dvm_solver_bind (the workspace grows by 108 doubles per cell;
- * DVM_ESTATE once bound, DVM_EINVAL with order 2).  every > 0: after every
+ * solutions that accelerate the kinetic iteration), first-order scheme and
+ * conservative equilibrium (the macroscopic equations are conservation
+ * laws; DVM_EINVAL with order 2 or the pointwise Maxwellian), set before
+ * dvm_solver_bind (the workspace grows by 108 doubles per cell; DVM_ESTATE
+ * once bound).  every > 0: after every
  * `every`-th primal sweep (counted from dvm_primal_init, a loaded or
  * copied f), the moments r of the kinetic residual of eq. (numerpr_gov)
  * drive the linearised macroscopic system A dW = -r, A being the moments of

@@ -839,6 +839,8 @@ int dvm_solver_set_equilibrium(dvm_solver *s, int kind)
     if (!s) return fail(DVM_EINVAL, "null solver");
     if (s->base) return fail(DVM_ESTATE, "the equilibrium is set before dvm_solver_bind");
     if (kind != DVM_EQ_POINTWISE && kind != DVM_EQ_CONSERVATIVE) return fail(DVM_EINVAL, "unknown equilibrium %d", kind);
+    if (kind != DVM_EQ_CONSERVATIVE && s->acc_every > 0)
+        return fail(DVM_EINVAL, "the macroscopic prediction needs the conservative equilibrium");
     s->equil = kind;
     return DVM_OK;
 }
@@ -849,6 +851,8 @@ int dvm_solver_set_acceleration(dvm_solver *s, int every, int inner)
     if (s->base) return fail(DVM_ESTATE, "the acceleration is set before dvm_solver_bind");
     if (every < 0 || inner < 0 || inner > 100000) return fail(DVM_EINVAL, "every >= 0 and 0 <= inner <= 100000");
     if (every > 0 && s->order != 1) return fail(DVM_EINVAL, "the macroscopic prediction is first-order only");
+    if (every > 0 && s->equil != DVM_EQ_CONSERVATIVE)
+        return fail(DVM_EINVAL, "the macroscopic prediction needs the conservative equilibrium");
     s->acc_every = every;
     s->acc_inner = inner;
     layout(*s);

@@ -3,8 +3,8 @@ convergence.
 
 * Parity: the HIP path and the oracle, both with the prediction every 5
   sweeps (20 red-black steps), 37 sweeps from the free stream: f, W <= 1e-11
-  (FP64), J <= 1e-10 relative, the stopping residuals; pointwise and
-  conservative equilibria, O- and C-grids, odd grid sizes (the red-black
+  (FP64), J <= 1e-10 relative, the stopping residuals (conservative
+  equilibrium, which the prediction needs); O- and C-grids, odd grid sizes (the red-black
   colouring meets itself across the periodic seam), one cell row, ragged
   velocity passes; mixed precision <= 2e-5.
 * Batched members with the prediction end bitwise where they would alone.
@@ -51,8 +51,8 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = [("tiny_circle", 0), ("tiny_circle", 1), ("tiny_naca", 1), ("c_nc24", 1), ("c_sinh36", 0), ("o13x7_odd", 1),
-         ("one_row", 0), ("o70x20_tiles", 1)]
+CASES = [("tiny_circle", 1), ("tiny_naca", 1), ("c_nc24", 1), ("c_sinh36", 1), ("o13x7_odd", 1), ("one_row", 1),
+         ("o70x20_tiles", 1)]
 
 
 def _run(wl, precision, eq, n):
@@ -148,3 +148,13 @@ def test_prediction_reaches_the_tolerance_near_the_continuum():
     _say(f"[gpu-acc] Kn 0.01 128x64: accelerated {it} sweeps to r {r:.2e}; plain after {it} sweeps r {rp:.2e}")
     assert r < 1e-8
     assert rp > 100 * r
+
+
+def test_prediction_argument_errors():
+    wl = _case("tiny_circle")
+    with pytest.raises(dvm.DvmError) as ei:
+        dvm.Solver.from_workload(wl, accelerate=(5, 20))                  # pointwise equilibrium
+    assert ei.value.code == dvm.DVM_EINVAL
+    with pytest.raises(dvm.DvmError) as ei:
+        dvm.Solver.from_workload(wl, equilibrium=1, order=2, accelerate=(5, 20))
+    assert ei.value.code == dvm.DVM_EINVAL

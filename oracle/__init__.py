@@ -84,6 +84,7 @@ def lib():
         L.or_set_acceleration.restype = I
         L.or_set_acceleration.argtypes = [P, I, I]
         L.or_macro_system.argtypes = [P, dp, dp, dp]
+        L.or_adjoint_macro_residual.argtypes = [P, dp]
         L.or_wall_JB.restype = D
         L.or_wall_JB.argtypes = [P, I, D, D, D, D, D]
         L.or_set_scheme.restype = I
@@ -175,6 +176,13 @@ class Problem:
         O = np.zeros((self.nc, 4, 4, 4))
         lib().or_macro_system(self._h, r, Dinv, O)
         return r, Dinv, O
+
+    def adjoint_macro_residual(self):
+        """r*_c = sum_k w (dg_c,k/dW)^T R*_c,k of the adjoint residual at the
+        current phi [nc, 4]."""
+        out = np.zeros((self.nc, 4))
+        lib().or_adjoint_macro_residual(self._h, out)
+        return out
 
     def eq_params(self, W):
         """Equilibrium parameters (rho', u1', u2', theta') of a moment vector

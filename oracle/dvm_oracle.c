@@ -140,6 +140,10 @@ typedef struct {
      * Gauss-Seidel steps on the macroscopic system */
     int acc_every, acc_inner, acc_sweeps;
     double acc_alpha;
+    /* adjoint prediction: the transposed system at the frozen f, the
+     * pending correction of the adjoint moments, sweeps of the adjoint phase */
+    double *aDinv, *aOT, *apred;
+    int acc_asweeps, apred_on;
 } or_problem;
 
 /* ------------------------------------------------------------------ */
@@ -658,6 +662,7 @@ void or_destroy(or_problem *p)
     free(p->f); free(p->fn); free(p->W); free(p->F); free(p->phi); free(p->phin); free(p->cellred);
     free(p->nodes);
     free(p->fm); free(p->corr); free(p->dF); free(p->psi); free(p->acorr); free(p->eqP); free(p->eqM);
+    free(p->aDinv); free(p->aOT); free(p->apred);
     free(p);
 }
 
@@ -1127,6 +1132,88 @@ static void macro_predict(or_problem *p)
     free(r); free(Dinv); free(O); free(x);
 }
 
+/* ---- adjoint prediction ----
+ * The adjoint counterpart of the step above (Sec. 3.1 accelerates the
+ * adjoint system the same way): with the conservative equilibrium the
+ * adjoint operator maps collision-invariant perturbations Psi . dl (dl in
+ * R^4 per cell) onto residuals whose dg/dW-weighted moments are A^T dl,
+ * the transpose of the primal macroscopic system at the frozen f (the
+ * adjoint operator is the transpose of the primal linearisation under
+ * sum_k w_k, and Psi . dl leaves the collision part unchanged).  So every K
+ * adjoint sweeps r*_c = sum_k w (dg_c,k/dW)^T R*_c,k of the adjoint residual
+ * R* drives A^T dl = -r* (red-black block Gauss-Seidel from 0), and dl is
+ * added to the adjoint moments What that the next sweep's phi_eq is built
+ * from.  r* vanishes at the adjoint solution. */
+
+/* the transposed system: Dinv^T is read from Dinv; OT[c][q] = O[n][q']^T for
+ * the face q' of neighbour n = nbr[c][q] that faces c */
+static void macro_transpose(const or_problem *p, const double *O, double *OT)
+{
+    for (int c = 0; c < p->nc; c++)
+        for (int q = 0; q < 4; q++) {
+            double *o = OT + 64 * (size_t)c + 16 * q;
+            memset(o, 0, sizeof(double) * 16);
+            const int n = p->nbr[4 * c + q];
+            if (n < 0) continue;
+            int qb = -1;
+            for (int t = 0; t < 4; t++) if (p->nbr[4 * n + t] == c) { qb = t; break; }
+            if (qb < 0) continue;
+            const double *src = O + 64 * (size_t)n + 16 * qb;
+            for (int a = 0; a < 4; a++) for (int b = 0; b < 4; b++) o[4 * a + b] = src[4 * b + a];
+        }
+}
+
+/* A^T x = -r* by red-black block Gauss-Seidel from x = 0 */
+static void macro_solve_T(or_problem *p, const double *r, const double *Dinv, const double *OT, double *x)
+{
+    const int nc = p->nc;
+    double *y = calloc(4 * (size_t)nc, sizeof(double));
+    memset(x, 0, sizeof(double) * 4 * nc);
+    for (int it = 0; it < p->acc_inner; it++) {
+        for (int col = 0; col < 2; col++) {
+            const double *src = col == 0 ? x : y;
+            double *dst = col == 0 ? y : x;
+            for (int c = 0; c < nc; c++) {
+                const int i = c % p->ni, j = c / p->ni;
+                if ((i + j) % 2 != col) { for (int a = 0; a < 4; a++) dst[4 * c + a] = src[4 * c + a]; continue; }
+                double b[4];
+                for (int a = 0; a < 4; a++) b[a] = -r[4 * c + a];
+                for (int q = 0; q < 4; q++) {
+                    const int nb = p->nbr[4 * c + q];
+                    if (nb < 0) continue;
+                    for (int a = 0; a < 4; a++)
+                        for (int e = 0; e < 4; e++) b[a] -= OT[64 * c + 16 * q + 4 * a + e] * src[4 * nb + e];
+                }
+                for (int a = 0; a < 4; a++) {
+                    double acc = 0;
+                    for (int e = 0; e < 4; e++) acc += Dinv[16 * c + 4 * e + a] * b[e];
+                    dst[4 * c + a] = acc;
+                }
+            }
+        }
+    }
+    free(y);
+}
+
+void or_adjoint_operator(or_problem *p, const double *phi, int with_source, double *out);
+
+static void macro_adjoint_predict(or_problem *p)
+{
+    const int nc = p->nc, nv = p->nv;
+    double *R = malloc(sizeof(double) * 2 * (size_t)nc * nv), *r = calloc(4 * (size_t)nc, sizeof(double));
+    or_adjoint_operator(p, p->phi, 1, R);
+    for (int c = 0; c < nc; c++)
+        for (int k = 0; k < nv; k++) {
+            double dg[2][4], dtt[4];
+            dg_dW_cell(p, c, k, dg, dtt);
+            const double *Rk = R + ((size_t)c * nv + k) * 2;
+            for (int m = 0; m < 4; m++) r[4 * c + m] += p->w[k] * (dg[0][m] * Rk[0] + dg[1][m] * Rk[1]);
+        }
+    macro_solve_T(p, r, p->aDinv, p->aOT, p->apred);
+    p->apred_on = 1;
+    free(R); free(r);
+}
+
 int or_set_acceleration(or_problem *p, int every, int inner)
 {
     /* the macroscopic equations are conservation laws: the conservative
@@ -1136,6 +1223,24 @@ int or_set_acceleration(or_problem *p, int every, int inner)
     p->acc_inner = inner;
     p->acc_alpha = 0.2;
     return 0;
+}
+
+/* the adjoint prediction's right-hand side r* [nc][4] at the current phi
+ * (pins) */
+void or_adjoint_macro_residual(or_problem *p, double *rs)
+{
+    const int nc = p->nc, nv = p->nv;
+    double *R = malloc(sizeof(double) * 2 * (size_t)nc * nv);
+    or_adjoint_operator(p, p->phi, 1, R);
+    memset(rs, 0, sizeof(double) * 4 * nc);
+    for (int c = 0; c < nc; c++)
+        for (int k = 0; k < nv; k++) {
+            double dg[2][4], dtt[4];
+            dg_dW_cell(p, c, k, dg, dtt);
+            const double *Rk = R + ((size_t)c * nv + k) * 2;
+            for (int m = 0; m < 4; m++) rs[4 * c + m] += p->w[k] * (dg[0][m] * Rk[0] + dg[1][m] * Rk[1]);
+        }
+    free(R);
 }
 
 /* the macroscopic system of the current state (pins): r [nc][4], D^-1
@@ -1215,7 +1320,7 @@ void or_get_f(const or_problem *p, double *out) { memcpy(out, p->f, sizeof(doubl
 void or_set_f(or_problem *p, const double *in) { memcpy(p->f, in, sizeof(double) * (size_t)p->nc * p->nv * 2); update_W_F(p, p->f); p->corr_ok = 0; p->acc_sweeps = 0; }
 void or_get_W(const or_problem *p, double *out) { memcpy(out, p->W, sizeof(double) * 4 * p->nc); }
 void or_get_phi(const or_problem *p, double *out) { memcpy(out, p->phi, sizeof(double) * (size_t)p->nc * p->nv * 2); }
-void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); p->acorr_ok = 0; }
+void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); p->acorr_ok = 0; p->apred_on = 0; p->acc_asweeps = 0; }
 
 /* wall value f1_{l,k}: cell value on Xi^+, F_l gbar1 on Xi^- (Sec. 3.2) */
 static double wall_f1(const or_problem *p, const double *f, int l, int k)
@@ -1598,6 +1703,20 @@ static void so_adjoint_term(const or_problem *p, const double *phi, const double
 void or_adjoint_init(or_problem *p)
 {
     memset(p->phi, 0, sizeof(double) * (size_t)p->nc * p->nv * 2);
+    p->acc_asweeps = 0;
+    p->apred_on = 0;
+    if (p->acc_every > 0 && p->order == 1) {
+        /* the primal macroscopic system at the frozen f, transposed */
+        const size_t nc = p->nc;
+        double *r = malloc(sizeof(double) * 4 * nc), *O = malloc(sizeof(double) * 64 * nc);
+        free(p->aDinv); free(p->aOT); free(p->apred);
+        p->aDinv = malloc(sizeof(double) * 16 * nc);
+        p->aOT = malloc(sizeof(double) * 64 * nc);
+        p->apred = calloc(4 * nc, sizeof(double));
+        macro_assemble(p, r, p->aDinv, O);
+        macro_transpose(p, O, p->aOT);
+        free(r); free(O);
+    }
     if (p->order == 2) {
         /* limiter factors of the converged f, frozen for the adjoint */
         double *G = malloc(sizeof(double) * 4 * (size_t)p->nc * p->nv);
@@ -1617,6 +1736,10 @@ double or_adjoint_iterate(or_problem *p, int niter)
     double r = 0;
     for (int it = 0; it < niter; it++) {
         adjoint_moments(p, p->phi, What, rtau, Phi);
+        if (p->apred_on) {
+            for (int q = 0; q < 4 * p->nc; q++) What[q] += p->apred[q];
+            p->apred_on = 0;
+        }
         const int so = p->order == 2;
         if (so && (!p->acorr_ok || p->asince == p->kcorr)) {
             so_adjoint_term(p, p->phi, Phi, p->acorr);
@@ -1661,6 +1784,8 @@ double or_adjoint_iterate(or_problem *p, int niter)
         r = den > 0 ? sqrt(num / den) : 0.0;
         double *t = p->phi; p->phi = p->phin; p->phin = t;
         if (so) p->asince++;
+        p->acc_asweeps++;
+        if (p->acc_every > 0 && p->aDinv && !so && p->acc_asweeps % p->acc_every == 0) macro_adjoint_predict(p);
     }
     free(What); free(rtau); free(Phi);
     return r;

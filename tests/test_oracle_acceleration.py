@@ -128,3 +128,60 @@ def test_prediction_needs_the_conservative_equilibrium():
     p.set_acceleration(5, 20)
     with pytest.raises(ValueError):
         p.set_equilibrium(0)
+
+
+def _adjoint_case(wl, acc, tol=1e-13, max_iter=40000):
+    p = oracle.Problem.from_workload(wl, nthreads=4)
+    p.set_equilibrium(1)
+    if acc:
+        p.set_acceleration(*acc)
+    p.primal_init()
+    p.primal_solve(1e-14, 40000, check_every=5)
+    p.adjoint_init()
+    it, r = p.adjoint_solve(tol, max_iter, check_every=5)
+    return p, it, r
+
+
+def test_adjoint_macroscopic_system_is_the_transpose():
+    """For collision-invariant perturbations Psi . dl, the dg/dW-weighted
+    moments of the change of the adjoint residual (the oracle's adjoint
+    operator, written independently of the assembly) are A^T dl, A the
+    primal macroscopic system at the frozen f."""
+    wl = I.tiny_naca(Kn=0.02, Ma=0.9)
+    p = oracle.Problem.from_workload(wl, nthreads=4)
+    p.set_equilibrium(1)
+    p.primal_init()
+    p.primal_iterate(9)
+    p.adjoint_init()
+    p.adjoint_iterate(4)
+    _, Dinv, O = p.macro_system()
+    r0 = p.adjoint_macro_residual()
+    v, _ = p.vgrid()
+    rng = np.random.default_rng(7)
+    dl = rng.standard_normal((p.nc, 4))
+    psi = np.stack([np.ones(p.nv), v[:, 0], v[:, 1], 0.5 * (v[:, 0] ** 2 + v[:, 1] ** 2)], -1)
+    phi = p.phi
+    dphi = np.zeros_like(phi)
+    dphi[..., 0] = dl @ psi.T
+    dphi[..., 1] = dl[:, 3:4]
+    p.phi = phi + dphi
+    r1 = p.adjoint_macro_residual()
+    m = p.mesh()
+    D = np.linalg.inv(Dinv)
+    ATdl = np.einsum("cba,cb->ca", D, dl)
+    for c in range(p.nc):
+        for q in range(4):
+            n = m["nbr"][c, q]
+            if n >= 0:
+                ATdl[n] += O[c, q].T @ dl[c]
+    assert np.max(np.abs((r1 - r0) - ATdl)) <= 1e-10 * np.max(np.abs(ATdl))
+
+
+def test_adjoint_prediction_shares_the_solution_and_accelerates():
+    wl = I.tiny_circle(Kn=0.02, Ma=0.5)
+    plain, it_p, r_p = _adjoint_case(wl, None)
+    acc, it_a, r_a = _adjoint_case(wl, (5, 50))
+    assert r_p < 1e-13 and r_a < 1e-13 and it_a < it_p / 3, (it_p, it_a)
+    assert np.max(np.abs(acc.phi - plain.phi)) <= 1e-9 * np.max(np.abs(plain.phi))
+    sa, sp = acc.wall_sensitivity(), plain.wall_sensitivity()
+    assert np.max(np.abs(sa["dJ_dnodes"] - sp["dJ_dnodes"])) <= 1e-9 * np.max(np.abs(sp["dJ_dnodes"]))

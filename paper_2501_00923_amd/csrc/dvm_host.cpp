@@ -268,12 +268,12 @@ struct dvm_solver {
     int equil = DVM_EQ_POINTWISE;
     // macroscopic prediction every acc_every primal sweeps (0: off) with
     // acc_inner red-black steps; acc_count = primal sweeps since the state began
-    int acc_every = 0, acc_inner = 0, acc_count = 0;
+    int acc_every = 0, acc_inner = 0, acc_count = 0, acc_acount = 0;
     // workspace
     struct {
         size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
         size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, msens, dJdx, out;
-        size_t mstate, mr, mDinv, mO, mx[2];
+        size_t mstate, mr, mDinv, mO, mx[2], mOT;
         size_t rf, rn, G, corr, psi, dF, total;
     } off;
     char *base = nullptr;
@@ -362,8 +362,9 @@ void layout(dvm_solver &s)
         o.mO = take(64 * nc * sizeof(double));
         o.mx[0] = take(4 * nc * sizeof(double));
         o.mx[1] = take(4 * nc * sizeof(double));
+        o.mOT = s.want_adjoint ? take(64 * nc * sizeof(double)) : (size_t)-1;
     } else {
-        o.mstate = o.mr = o.mDinv = o.mO = o.mx[0] = o.mx[1] = (size_t)-1;
+        o.mstate = o.mr = o.mDinv = o.mO = o.mx[0] = o.mx[1] = o.mOT = (size_t)-1;
     }
     o.total = cur;
 }
@@ -444,6 +445,7 @@ void fill_dev(dvm_solver &s)
     d.mO = at<double>(s, s.off.mO);
     d.mx[0] = at<double>(s, s.off.mx[0]);
     d.mx[1] = at<double>(s, s.off.mx[1]);
+    d.mOT = at<double>(s, s.off.mOT);
 }
 
 int upload(dvm_solver &s, size_t off, const void *src, size_t bytes)
@@ -510,6 +512,8 @@ int sweeps(dvm_solver &s, int adjoint, int n)
         if (adjoint) {
             HIP_OK(dvm::launch_adjoint_sweep(s.dev, s.ppar, s.stream));
             s.ppar ^= 1;
+            if (s.acc_every > 0 && ++s.acc_acount % s.acc_every == 0)
+                HIP_OK(dvm::launch_macro_adjoint_predict(s.dev, s.ppar, s.acc_inner, s.stream));
         } else {
             HIP_OK(dvm::launch_primal_sweep(s.dev, s.fpar, s.stream));
             s.fpar ^= 1;
@@ -992,6 +996,8 @@ int dvm_adjoint_init(dvm_solver *s)
     fill_dev(*s);
     HIP_OK(dvm::launch_adjoint_init(s->dev, s->frozen_fpar, s->stream));
     if (s->order == 2) HIP_OK(dvm::launch_so_freeze(s->dev, s->frozen_fpar, s->stream));
+    if (s->acc_every > 0) HIP_OK(dvm::launch_macro_adjoint_setup(s->dev, s->frozen_fpar, s->stream));
+    s->acc_acount = 0;
     s->ppar = 0;
     s->phase = 1;
     s->iters[1] = 0;
@@ -1136,6 +1142,7 @@ int dvm_state_load(dvm_solver *s, int which, const void *host_src, size_t bytes)
             HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], tmp.data(), all, hipMemcpyHostToDevice, s->stream));
             HIP_OK(dvm::launch_adjoint_moments(s->dev, s->ppar, s->stream));
             s->corr_ok[1] = 0;
+            s->acc_acount = 0;
         } else {
             rows_to_dev(*s, src + all, tmp.data() + all, awb);
             HIP_OK(hipMemcpyAsync(s->dev.phi[s->ppar], tmp.data(), all, hipMemcpyHostToDevice, s->stream));
@@ -1447,8 +1454,11 @@ int dvm_batch_run(dvm_batch *b, int iters)
         // (the state after this sweep sits in buffer fpar ^ ((it + 1) & 1))
         for (int m = 0; m < b->n; m++) {
             dvm_solver *s = b->members[m];
-            if (s->phase == 0 && s->acc_every > 0 && ++s->acc_count % s->acc_every == 0)
+            if (s->acc_every <= 0) continue;
+            if (s->phase == 0 && ++s->acc_count % s->acc_every == 0)
                 HIP_OK(dvm::launch_macro_predict(s->dev, s->fpar ^ ((it + 1) & 1), s->acc_inner, b->stream));
+            if (s->phase == 1 && ++s->acc_acount % s->acc_every == 0)
+                HIP_OK(dvm::launch_macro_adjoint_predict(s->dev, s->ppar ^ ((it + 1) & 1), s->acc_inner, b->stream));
         }
     }
     b->step += iters;

@@ -89,6 +89,7 @@ struct DevSolve {
     double *mDinv;           // [nc][16] inverse of the cell's own block
     double *mO;              // [nc][4][16] blocks of the face neighbours
     double *mx[2];           // [nc][4] red-black iterates
+    double *mOT;             // [nc][4][16] transposed neighbour blocks (adjoint prediction)
 };
 
 // launches (all on `st`); par = index of the current f / phi buffer
@@ -107,6 +108,11 @@ hipError_t launch_mesh_sens(const DevSolve &d, int fpar, int ppar, hipStream_t s
 // scheme): assembly, `inner` red-black block Gauss-Seidel steps, limited
 // update of W[par]
 hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream_t st);
+// adjoint prediction: the system at the frozen f[fpar] and its transpose
+// (at the adjoint's start); every K adjoint sweeps, A^T dl = -r* and What of
+// phi[ppar] += dl
+hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t st);
+hipError_t launch_macro_adjoint_predict(const DevSolve &d, int ppar, int inner, hipStream_t st);
 
 // second-order scheme: the slopes G and dF of f[par]; the held primal
 // correction c (with G and dF) from f[par]; the

@@ -272,9 +272,11 @@ __global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
 // ---------------------------------------------------------------------------
 // one colour of a red-black block Gauss-Seidel step, a thread per cell
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, const double *__restrict__ src,
-                                                       double *__restrict__ dst)
+__global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, int transposed,
+                                                       const double *__restrict__ src, double *__restrict__ dst)
 {
+    // transposed: the adjoint's A^T, diagonal D^T (read from D^-1 by
+    // columns) and the transposed neighbour blocks
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.nc) return;
     const int m = d.cell_of[c];
@@ -287,21 +289,23 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, c
     double b[4];
 #pragma unroll
     for (int a = 0; a < 4; a++) b[a] = -d.mr[4 * c + a];
+    const double *Ob = transposed ? d.mOT : d.mO;
     for (int q = 0; q < 4; q++) {
         const int n = d.nbr[4 * c + q];
         if (n < 0) continue;
-        const double *O = d.mO + 64 * c + 16 * q;
+        const double *O = Ob + 64 * c + 16 * q;
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
             for (int e = 0; e < 4; e++) b[a] -= O[4 * a + e] * src[4 * n + e];
     }
     const double *Di = d.mDinv + 16 * c;
+    const int sa = transposed ? 1 : 4, se = transposed ? 4 : 1;
 #pragma unroll
     for (int a = 0; a < 4; a++) {
         double acc = 0;
 #pragma unroll
-        for (int e = 0; e < 4; e++) acc += Di[4 * a + e] * b[e];
+        for (int e = 0; e < 4; e++) acc += Di[sa * a + se * e] * b[e];
         dst[4 * c + a] = acc;
     }
 }
@@ -348,11 +352,158 @@ hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream
     hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mx[0], 4 * d.nc);
     if (hipError_t e = hipGetLastError()) return e;
     for (int it = 0; it < inner; it++) {
-        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, d.mx[0], d.mx[1]);
-        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 1, d.mx[1], d.mx[0]);
+        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, 0, d.mx[0], d.mx[1]);
+        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 1, 0, d.mx[1], d.mx[0]);
         if (hipError_t e = hipGetLastError()) return e;
     }
     hipLaunchKernelGGL(k_macro_apply, dim3(gt), dim3(kBlock), 0, st, d, par, d.mx[0]);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// adjoint prediction: with the conservative equilibrium the adjoint operator
+// maps collision-invariant perturbations Psi . dl onto residuals whose
+// dg/dW-weighted moments are A^T dl (A the primal system at the frozen f,
+// assembled once at the adjoint's start).  Every K adjoint sweeps the
+// dg/dW-weighted moments r* of the adjoint residual of eq. (numerad_gov)
+// drive A^T dl = -r*, and dl joins the adjoint moments What that the next
+// sweep builds phi_eq from.
+// ---------------------------------------------------------------------------
+
+// the transposed neighbour blocks: OT[c][q] = O[n][q']^T for the face q' of
+// n = nbr[c][q] that faces c, a thread per cell
+__global__ __launch_bounds__(kBlock) void k_macro_transpose(DevSolve d)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    for (int q = 0; q < 4; q++) {
+        double *o = d.mOT + 64 * c + 16 * q;
+        const int n = d.nbr[4 * c + q];
+        int qb = -1;
+        if (n >= 0)
+            for (int t = 0; t < 4; t++)
+                if (d.nbr[4 * n + t] == c) {
+                    qb = t;
+                    break;
+                }
+        const double *src = d.mO + 64 * (size_t)(n >= 0 ? n : c) + 16 * (qb >= 0 ? qb : 0);
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) o[4 * a + b] = qb >= 0 ? src[4 * b + a] : 0.0;
+    }
+}
+
+// r*_c = sum_k w (dg_c,k/dW)^T R*_c,k, R* the adjoint residual of phi[ppar]
+// (downstream values: neighbour, 0 at the far field, (Phi_l - m_J, 0) at the
+// wall; source phi_eq / tau + phi_tau from the adjoint moments of phi[ppar]),
+// one wave per cell
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_macro_adj_residual(DevSolve d, int ppar)
+{
+    using T2 = typename Vec2<T>::type;
+    __shared__ double tabX[kBlock / kWave][kMaxN1D], tabY[kBlock / kWave][kMaxN1D];
+    const int w = (int)(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+    const int c0 = blockIdx.x * (kBlock / kWave) + w;
+    const bool act = c0 < d.nc;                 // idle waves of the last workgroup only join the barrier
+    const int c = act ? c0 : d.nc - 1;
+    const int nv = d.nv, n1 = d.n1, obj = d.objective;
+    const T2 *__restrict__ ph = static_cast<const T2 *>(d.phi[ppar]);
+    const double *ac = d.acoef + kAcoef * c;
+    const double P[4] = {ac[0], ac[1], ac[2], ac[3]}, itau = ac[4], kap = ac[5];
+    const double *aw = d.aW[ppar] + 8 * c;
+    const double rt = aw[4];
+    const double C0 = aw[0] * itau - rt * ac[6], C1 = aw[1] * itau - rt * ac[7];
+    const double C2 = aw[2] * itau - rt * ac[8], C3 = aw[3] * itau - rt * ac[9];
+    const double V = d.vol[c];
+    int nb[4];
+    double Sx[4], Sy[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        nb[q] = d.nbr[4 * c + q];
+        Sx[q] = d.S[8 * c + 2 * q];
+        Sy[q] = d.S[8 * c + 2 * q + 1];
+    }
+    const int wl = nb[0] <= -2 ? -2 - nb[0] : -1;
+    const double Phw = wl >= 0 ? d.Phi[ppar][wl] : 0.0;
+    macro_tables(d, P, tabX[w], tabY[w]);
+    __syncthreads();
+    const size_t row = (size_t)c * nv;
+    double acc[4] = {0, 0, 0, 0};
+    for (int k = lane; k < nv; k += kWave) {
+        const int a = k % n1, b = k / n1;
+        const double v1 = d.vx[a], v2 = d.vy[b], wt = d.wx[a] * d.wy[b];
+        double g1, g2, d1[4], d2[4];
+        dg_dP(kap, P, tabX[w][a], tabY[w][b], v1, v2, g1, g2, d1, d2);
+        const T2 pk = ph[row + k];
+        const double p1 = (double)pk.x, p2 = (double)pk.y;
+        double r1 = 0, r2 = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const double s = v1 * Sx[q] + v2 * Sy[q];
+            if (s > 0) {
+                double b1 = 0, b2 = 0;
+                if (nb[q] >= 0) {
+                    const T2 u = ph[(size_t)nb[q] * nv + k];
+                    b1 = (double)u.x;
+                    b2 = (double)u.y;
+                } else if (nb[q] <= -2) {
+                    b1 = Phw - mJ_of(obj, v1, v2);
+                }
+                r1 += s * (p1 - b1);
+                r2 += s * (p2 - b2);
+            }
+        }
+        const double s1 = C0 + C1 * v1 + C2 * v2 + C3 * 0.5 * (v1 * v1 + v2 * v2), s2 = C3;
+        r1 += V * (p1 * itau - s1);
+        r2 += V * (p2 * itau - s2);
+#pragma unroll
+        for (int p = 0; p < 4; p++) acc[p] += wt * (d1[p] * r1 + d2[p] * r2);
+    }
+    wave_sum<4>(acc);
+    if (act && lane == 0) {
+        const double *M = ac + 16;
+#pragma unroll
+        for (int m = 0; m < 4; m++)
+            d.mr[4 * c + m] = ((acc[0] * M[m] + acc[1] * M[4 + m]) + acc[2] * M[8 + m]) + acc[3] * M[12 + m];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_macro_adj_apply(DevSolve d, int ppar, const double *__restrict__ x)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    double *aw = d.aW[ppar] + 8 * c;
+#pragma unroll
+    for (int a = 0; a < 4; a++) aw[a] += x[4 * c + a];
+}
+
+hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t st)
+{
+    constexpr int per_block = kBlock / kWave;
+    const int gw = (d.nc + per_block - 1) / per_block, gt = (d.nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_macro_state, dim3(gw), dim3(kBlock), 0, st, d, fpar);
+    if (hipError_t e = hipGetLastError()) return e;
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_assemble<T>, dim3(gw), dim3(kBlock), 0, st, d, fpar));
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(k_macro_transpose, dim3(gt), dim3(kBlock), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_adjoint_predict(const DevSolve &d, int ppar, int inner, hipStream_t st)
+{
+    constexpr int per_block = kBlock / kWave;
+    const int gw = (d.nc + per_block - 1) / per_block, gt = (d.nc + kBlock - 1) / kBlock;
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_adj_residual<T>, dim3(gw), dim3(kBlock), 0, st, d, ppar));
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mx[0], 4 * d.nc);
+    if (hipError_t e = hipGetLastError()) return e;
+    for (int it = 0; it < inner; it++) {
+        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, 1, d.mx[0], d.mx[1]);
+        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 1, 1, d.mx[1], d.mx[0]);
+        if (hipError_t e = hipGetLastError()) return e;
+    }
+    hipLaunchKernelGGL(k_macro_adj_apply, dim3(gt), dim3(kBlock), 0, st, d, ppar, d.mx[0]);
     return hipGetLastError();
 }
 

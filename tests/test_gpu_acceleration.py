@@ -158,3 +158,81 @@ def test_prediction_argument_errors():
     with pytest.raises(dvm.DvmError) as ei:
         dvm.Solver.from_workload(wl, equilibrium=1, order=2, accelerate=(5, 20))
     assert ei.value.code == dvm.DVM_EINVAL
+
+
+def _run_adjoint(wl, precision, n_primal, n_adjoint):
+    s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=1, accelerate=ACC)
+    o = oracle.Problem.from_workload(wl, nthreads=NTHREADS)
+    o.set_equilibrium(1)
+    o.set_acceleration(*ACC)
+    s.primal_init()
+    o.primal_init()
+    s.primal_iterate(n_primal)
+    o.primal_iterate(n_primal)
+    s.adjoint_init()
+    o.adjoint_init()
+    _, rs = s.adjoint_iterate(n_adjoint)
+    ro = o.adjoint_iterate(n_adjoint)
+    return s, o, rs, ro
+
+
+@pytest.mark.parametrize("name", ["tiny_circle", "tiny_naca", "c_nc24", "c_sinh36", "o13x7_odd", "one_row",
+                                  "o70x20_tiles"])
+def test_fp64_adjoint_prediction_parity(name):
+    wl = _case(name)
+    _say(f"[gpu-acc] adjoint {name}")
+    s, o, rs, ro = _run_adjoint(wl, dvm.FP64, 23, 29)
+    check_resid(rs, ro, f"{name} accelerated adjoint")
+    ep = _rel(s.state_array(dvm.STATE_PHI), o.phi)
+    gs, go = s.wall_sensitivity(), o.wall_sensitivity()
+    eS = _rel(gs["dJ_dnodes"], go["dJ_dnodes"])
+    _say(f"[gpu-acc] adjoint {name}: phi {ep:.2e} dJ/dnodes {eS:.2e}")
+    assert ep <= 1e-11 and eS <= 1e-10
+
+
+def test_mixed_adjoint_prediction_parity():
+    wl = _case("c_sinh36")
+    s, o, _, _ = _run_adjoint(wl, dvm.MIXED, 23, 29)
+    ep = _rel(s.state_array(dvm.STATE_PHI), o.phi)
+    _say(f"[gpu-acc mixed] adjoint c_sinh36: phi {ep:.2e}")
+    assert ep <= 2e-5
+
+
+def test_adjoint_prediction_converges_to_the_plain_solution():
+    wl = _cgrid(0.1)
+    res = {}
+    for acc in (None, (5, 50)):
+        s = dvm.Solver.from_workload(wl, equilibrium=1, accelerate=acc)
+        s.primal_init()
+        s.primal_iterate(200000, tol=1e-11, check_every=50)
+        s.adjoint_init()
+        it, r = s.adjoint_iterate(200000, tol=1e-11, check_every=50)
+        res[acc] = (it, r, s.wall_sensitivity()["dJ_dnodes"])
+        _say(f"[gpu-acc] Kn 0.1 128x64 adjoint accelerate={acc}: {it} sweeps, r {r:.2e}")
+    (ip, rp, gp), (ia, ra, ga) = res[None], res[(5, 50)]
+    assert ia < ip
+    assert _rel(ga, gp) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", [dvm.FP64, dvm.MIXED])
+def test_batched_adjoint_prediction_bitwise(precision):
+    cases = [_case("tiny_circle"), _case("o70x20_tiles")]
+
+    def make(wl):
+        s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=1, accelerate=ACC)
+        s.primal_init()
+        s.primal_sweeps(8)
+        s.adjoint_init()
+        return s
+    alone = []
+    for wl in cases:
+        s = make(wl)
+        s.adjoint_sweeps(12)
+        alone.append(s.state_save(dvm.STATE_PHI))
+    members = [make(wl) for wl in cases]
+    b = dvm.Batch(members)
+    b.run(7)
+    b.run(5)
+    b.close()
+    for a, s in zip(alone, members):
+        assert np.array_equal(a, s.state_save(dvm.STATE_PHI))

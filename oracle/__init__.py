@@ -83,8 +83,11 @@ def lib():
         L.or_eq_params.argtypes = [P, dp, dp, dp]
         L.or_set_acceleration.restype = I
         L.or_set_acceleration.argtypes = [P, I, I]
-        L.or_macro_system.argtypes = [P, dp, dp, dp]
-        L.or_adjoint_macro_residual.argtypes = [P, dp]
+        L.or_macro_system.argtypes = [P, dp, dp, dp, dp]
+        L.or_macro_gs.restype = I
+        L.or_macro_gs.argtypes = [P, dp, dp]
+        L.or_macro_gs_adj.restype = I
+        L.or_macro_gs_adj.argtypes = [P, dp, dp]
         L.or_wall_JB.restype = D
         L.or_wall_JB.argtypes = [P, I, D, D, D, D, D]
         L.or_set_scheme.restype = I
@@ -164,24 +167,37 @@ class Problem:
 
     def set_acceleration(self, every: int, inner: int):
         """Macroscopic prediction every `every` primal sweeps (0: off) with
-        `inner` red-black block Gauss-Seidel steps (first-order scheme)."""
+        `inner` red-black block Gauss-Seidel steps (first-order scheme); the
+        adjoint iteration gets the transposed step every `every` sweeps."""
         if lib().or_set_acceleration(self._h, int(every), int(inner)) != 0:
             raise ValueError("oracle: invalid acceleration")
 
     def macro_system(self):
         """The macroscopic prediction's system at the current state: r [nc,4],
-        D^-1 [nc,4,4], off-diagonal blocks [nc,4(face),4,4]."""
+        D^-1 [nc,4,4] (the pseudo-time term on the diagonal included),
+        off-diagonal blocks [nc,4(face),4,4] and the pseudo-time term [nc]."""
         r = np.zeros((self.nc, 4))
         Dinv = np.zeros((self.nc, 4, 4))
         O = np.zeros((self.nc, 4, 4, 4))
-        lib().or_macro_system(self._h, r, Dinv, O)
-        return r, Dinv, O
+        lam = np.zeros(self.nc)
+        lib().or_macro_system(self._h, r, Dinv, O, lam)
+        return r, Dinv, O, lam
 
-    def adjoint_macro_residual(self):
-        """r*_c = sum_k w (dg_c,k/dW)^T R*_c,k of the adjoint residual at the
-        current phi [nc, 4]."""
+    def macro_gs(self, r):
+        """x = L r, the red-black Gauss-Seidel map of the adjoint's frozen
+        macroscopic system (after adjoint_init with the prediction on)."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        x = np.zeros((self.nc, 4))
+        if lib().or_macro_gs(self._h, r, x) != 0:
+            raise ValueError("oracle: no frozen macroscopic system")
+        return x
+
+    def macro_gs_adj(self, s):
+        """L^T s, the transpose of macro_gs's map."""
+        s = np.ascontiguousarray(s, dtype=np.float64)
         out = np.zeros((self.nc, 4))
-        lib().or_adjoint_macro_residual(self._h, out)
+        if lib().or_macro_gs_adj(self._h, s, out) != 0:
+            raise ValueError("oracle: no frozen macroscopic system")
         return out
 
     def eq_params(self, W):

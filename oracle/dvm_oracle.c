@@ -140,10 +140,10 @@ typedef struct {
      * Gauss-Seidel steps on the macroscopic system */
     int acc_every, acc_inner, acc_sweeps;
     double acc_alpha;
-    /* adjoint prediction: the transposed system at the frozen f, the
-     * pending correction of the adjoint moments, sweeps of the adjoint phase */
-    double *aDinv, *aOT, *apred;
-    int acc_asweeps, apred_on;
+    /* adjoint prediction: the primal macroscopic system at the frozen f,
+     * sweeps of the adjoint phase */
+    double *aDinv, *aO;
+    int acc_asweeps;
 } or_problem;
 
 /* ------------------------------------------------------------------ */
@@ -343,7 +343,8 @@ static void solve4(const double A_in[4][4], const double b_in[4], double x[4])
 static void eq_params(const or_problem *p, const double *W, double P[4], double M[4][4])
 {
     prim(W, &P[0], &P[1], &P[2], &P[3]);
-    if (p->equilibrium == 1) {
+    int conservative = p->equilibrium == 1;
+    if (conservative) {
         for (int it = 0; it < OR_EQ_NEWTON; it++) {
             double m[4], J[4][4], r[4], dP[4];
             eq_moments_jac(p, P, m, J);
@@ -351,9 +352,16 @@ static void eq_params(const or_problem *p, const double *W, double P[4], double 
             solve4(J, r, dP);
             for (int a = 0; a < 4; a++) P[a] += dP[a];
         }
+        /* a grid too coarse for the state (a Maxwellian much narrower than
+         * the velocity spacing) can leave Newton without a usable root: the
+         * cell then keeps the pointwise Maxwellian of its primitive variables */
+        if (!(P[0] > 0) || !(P[3] > 0) || !isfinite(P[1]) || !isfinite(P[2])) {
+            prim(W, &P[0], &P[1], &P[2], &P[3]);
+            conservative = 0;
+        }
     }
     if (!M) return;
-    if (p->equilibrium == 1) {
+    if (conservative) {
         double m[4], J[4][4];
         eq_moments_jac(p, P, m, J);
         for (int b = 0; b < 4; b++) {
@@ -429,6 +437,7 @@ static void eq_params_z(const or_problem *p, const double complex *W, double com
     P[0] = W[0]; P[1] = W[1] / W[0]; P[2] = W[2] / W[0];
     P[3] = (2.0 / 3.0) * (W[3] / W[0] - 0.5 * (P[1] * P[1] + P[2] * P[2]));
     if (p->equilibrium != 1) return;
+    double complex P0[4] = { P[0], P[1], P[2], P[3] };
     for (int it = 0; it < OR_EQ_NEWTON; it++) {
         double complex m[4] = { 0, 0, 0, 0 }, A[4][5];
         for (int a = 0; a < 4; a++) for (int b = 0; b < 5; b++) A[a][b] = 0;
@@ -462,6 +471,8 @@ static void eq_params_z(const or_problem *p, const double complex *W, double com
         }
         for (int a = 0; a < 4; a++) P[a] += x[a];
     }
+    if (!(creal(P[0]) > 0) || !(creal(P[3]) > 0) || !isfinite(creal(P[1])) || !isfinite(creal(P[2])))
+        for (int a = 0; a < 4; a++) P[a] = P0[a];
 }
 
 int or_set_equilibrium(or_problem *p, int kind)
@@ -662,7 +673,7 @@ void or_destroy(or_problem *p)
     free(p->f); free(p->fn); free(p->W); free(p->F); free(p->phi); free(p->phin); free(p->cellred);
     free(p->nodes);
     free(p->fm); free(p->corr); free(p->dF); free(p->psi); free(p->acorr); free(p->eqP); free(p->eqM);
-    free(p->aDinv); free(p->aOT); free(p->apred);
+    free(p->aDinv); free(p->aO);
     free(p);
 }
 
@@ -985,8 +996,13 @@ void or_so_faces(or_problem *p, const double *f, double *out)
  *      diffuse value's response gbar_k dF_l (dF_l = sum_{v.n>0} w (v.n)
  *      dg1/dW dW_c) -- the exact linearisation of the transport of the
  *      discrete scheme restricted to local equilibria (a kinetic
- *      flux-vector-split Euler operator), solved approximately by
- *      red-black block Gauss-Seidel steps from dW = 0;
+ *      flux-vector-split Euler operator), with the pseudo-time term
+ *      V_c/dt_c = (|u_c| + c_c) sum_q |S_q| / CFL on its diagonal (c the
+ *      sound speed, CFL = 1000: an implicit step with a very large local
+ *      time step, which keeps the near-singular modes of the steady
+ *      operator -- a slow wake behind a trailing edge, a sonic region --
+ *      from being amplified), solved approximately by red-black block
+ *      Gauss-Seidel steps from dW = 0;
  *   3. each cell's correction is limited so that rho and theta change by
  *      at most a fraction alpha (0.2) in one step;
  *   4. the predicted moments W + dW replace W as the state the next sweep
@@ -1002,9 +1018,20 @@ void or_so_faces(or_problem *p, const double *f, double *out)
  * then does an equilibrium perturbation dg/dW dW carry the moments dW (the
  * collision term's moments then vanish identically). */
 
+#define OR_MACRO_CFL 1000.0
+
+/* the pseudo-time term V_c/dt_c of cell c at the current W */
+static double macro_shift(const or_problem *p, int c)
+{
+    double rho, u1, u2, th, sS = 0;
+    prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+    for (int q = 0; q < 4; q++) sS += hypot(p->S[8 * c + 2 * q], p->S[8 * c + 2 * q + 1]);
+    return (sqrt(u1 * u1 + u2 * u2) + sqrt(5.0 / 3.0 * th)) * sS / OR_MACRO_CFL;
+}
+
 /* the macroscopic system of the current f (first order): r [nc][4], Dinv
- * [nc][16] (inverse of the cell's own block), O [nc][4][16] (blocks of the
- * four face neighbours; zero for boundary faces) */
+ * [nc][16] (inverse of the cell's own block, pseudo-time term included), O
+ * [nc][4][16] (blocks of the four face neighbours; zero for boundary faces) */
 static void macro_assemble(or_problem *p, double *r, double *Dinv, double *O)
 {
     const int nv = p->nv;
@@ -1057,6 +1084,8 @@ static void macro_assemble(or_problem *p, double *r, double *Dinv, double *O)
             }
         }
         for (int a = 0; a < 4; a++) for (int b = 0; b < 4; b++) Dc[a][b] += wall1[a] * dF[b];
+        const double lam = macro_shift(p, c);
+        for (int a = 0; a < 4; a++) Dc[a][a] += lam;
         for (int b = 0; b < 4; b++) {
             double e[4] = { 0, 0, 0, 0 }, col[4];
             e[b] = 1.0;
@@ -1133,85 +1162,100 @@ static void macro_predict(or_problem *p)
 }
 
 /* ---- adjoint prediction ----
- * The adjoint counterpart of the step above (Sec. 3.1 accelerates the
- * adjoint system the same way): with the conservative equilibrium the
- * adjoint operator maps collision-invariant perturbations Psi . dl (dl in
- * R^4 per cell) onto residuals whose dg/dW-weighted moments are A^T dl,
- * the transpose of the primal macroscopic system at the frozen f (the
- * adjoint operator is the transpose of the primal linearisation under
- * sum_k w_k, and Psi . dl leaves the collision part unchanged).  So every K
- * adjoint sweeps r*_c = sum_k w (dg_c,k/dW)^T R*_c,k of the adjoint residual
- * R* drives A^T dl = -r* (red-black block Gauss-Seidel from 0), and dl is
- * added to the adjoint moments What that the next sweep's phi_eq is built
- * from.  r* vanishes at the adjoint solution. */
+ * The adjoint iteration is accelerated by the transpose of the primal's
+ * accelerated sweep (Sec. 3.1 accelerates the adjoint system the same way),
+ * so that the two iterations share their convergence factors.  Linearised
+ * at the converged f, a primal sweep is f' = f + D^-1 R'(f) with D the
+ * diagonal sum_out v.S + V/tau; the sweep after a prediction relaxes towards
+ * W + dW, dW = L r with r = -M R the residual's moments (M the moments,
+ * L the linear map of the Gauss-Seidel steps) and W + dW entering through
+ * g and tau: f' = f + D^-1 Q R' with Q = I - H L M, H = dg/dW V/tau +
+ * (g - f) d(V/tau)/dW.  The same step for the adjoint equation R'^T lam +
+ * dJ/df = 0, transposed under sum_k w_k, is
+ *   lam' = lam + Q^T D^-1 R*(lam) = lam_s - Psi L^T (H^T (lam_s - lam)),
+ * lam_s the plain sweep's result: every K-th adjoint sweep corrects its
+ * result by the collision invariant Psi z, z = L^T y, y_c = V_c [ What_c /
+ * tau_c - (1/tau dtau/dW)_c rho_tau,c ] of the sweep's change lam_s - lam
+ * (What and rho_tau the adjoint moments of eq. adjoint_macdefines).  The
+ * correction vanishes with the plain sweep's change, so the adjoint
+ * solution is unchanged; the accelerated adjoint cycle equals R'^-T times
+ * the transposed primal cycle times R'^T, i.e. has the primal cycle's
+ * eigenvalues. */
 
-/* the transposed system: Dinv^T is read from Dinv; OT[c][q] = O[n][q']^T for
- * the face q' of neighbour n = nbr[c][q] that faces c */
-static void macro_transpose(const or_problem *p, const double *O, double *OT)
-{
-    for (int c = 0; c < p->nc; c++)
-        for (int q = 0; q < 4; q++) {
-            double *o = OT + 64 * (size_t)c + 16 * q;
-            memset(o, 0, sizeof(double) * 16);
-            const int n = p->nbr[4 * c + q];
-            if (n < 0) continue;
-            int qb = -1;
-            for (int t = 0; t < 4; t++) if (p->nbr[4 * n + t] == c) { qb = t; break; }
-            if (qb < 0) continue;
-            const double *src = O + 64 * (size_t)n + 16 * qb;
-            for (int a = 0; a < 4; a++) for (int b = 0; b < 4; b++) o[4 * a + b] = src[4 * b + a];
-        }
-}
-
-/* A^T x = -r* by red-black block Gauss-Seidel from x = 0 */
-static void macro_solve_T(or_problem *p, const double *r, const double *Dinv, const double *OT, double *x)
+/* L^T: the transpose of the linear map r -> x of macro_solve, its half steps
+ * transposed in reverse order */
+static void macro_solve_adj(or_problem *p, const double *s, const double *Dinv, const double *O, double *rbar)
 {
     const int nc = p->nc;
-    double *y = calloc(4 * (size_t)nc, sizeof(double));
-    memset(x, 0, sizeof(double) * 4 * nc);
-    for (int it = 0; it < p->acc_inner; it++) {
-        for (int col = 0; col < 2; col++) {
-            const double *src = col == 0 ? x : y;
-            double *dst = col == 0 ? y : x;
+    double *xb = malloc(sizeof(double) * 4 * nc), *yb = malloc(sizeof(double) * 4 * nc);
+    memcpy(xb, s, sizeof(double) * 4 * nc);
+    memset(rbar, 0, sizeof(double) * 4 * nc);
+    for (int it = p->acc_inner - 1; it >= 0; it--) {
+        for (int col = 1; col >= 0; col--) {
+            /* half step col wrote dst_fwd from src_fwd: its adjoint reads the
+             * output's adjoint (ob) and writes the input's (ib) */
+            const double *ob = col == 1 ? xb : yb;
+            double *ib = col == 1 ? yb : xb;
+            memset(ib, 0, sizeof(double) * 4 * nc);
             for (int c = 0; c < nc; c++) {
                 const int i = c % p->ni, j = c / p->ni;
-                if ((i + j) % 2 != col) { for (int a = 0; a < 4; a++) dst[4 * c + a] = src[4 * c + a]; continue; }
-                double b[4];
-                for (int a = 0; a < 4; a++) b[a] = -r[4 * c + a];
+                if ((i + j) % 2 != col) { for (int a = 0; a < 4; a++) ib[4 * c + a] += ob[4 * c + a]; continue; }
+                /* x_c = Dinv_c (-r_c - sum_q O_cq src_nb): t = -Dinv_c^T ob_c */
+                double t[4];
+                for (int a = 0; a < 4; a++) {
+                    double acc = 0;
+                    for (int e = 0; e < 4; e++) acc += Dinv[16 * c + 4 * e + a] * ob[4 * c + e];
+                    t[a] = -acc;
+                }
+                for (int a = 0; a < 4; a++) rbar[4 * c + a] += t[a];
                 for (int q = 0; q < 4; q++) {
                     const int nb = p->nbr[4 * c + q];
                     if (nb < 0) continue;
-                    for (int a = 0; a < 4; a++)
-                        for (int e = 0; e < 4; e++) b[a] -= OT[64 * c + 16 * q + 4 * a + e] * src[4 * nb + e];
-                }
-                for (int a = 0; a < 4; a++) {
-                    double acc = 0;
-                    for (int e = 0; e < 4; e++) acc += Dinv[16 * c + 4 * e + a] * b[e];
-                    dst[4 * c + a] = acc;
+                    for (int e = 0; e < 4; e++) {
+                        double acc = 0;
+                        for (int a = 0; a < 4; a++) acc += O[64 * c + 16 * q + 4 * a + e] * t[a];
+                        ib[4 * nb + e] += acc;
+                    }
                 }
             }
         }
     }
-    free(y);
+    free(xb); free(yb);
 }
 
-void or_adjoint_operator(or_problem *p, const double *phi, int with_source, double *out);
-
-static void macro_adjoint_predict(or_problem *p)
+/* the correction of an accelerated adjoint sweep: phin (the plain sweep's
+ * result from phi) -= Psi z */
+static void macro_adjoint_correct(or_problem *p, const double *phi, double *phin)
 {
     const int nc = p->nc, nv = p->nv;
-    double *R = malloc(sizeof(double) * 2 * (size_t)nc * nv), *r = calloc(4 * (size_t)nc, sizeof(double));
-    or_adjoint_operator(p, p->phi, 1, R);
+    double *y = malloc(sizeof(double) * 4 * nc), *z = malloc(sizeof(double) * 4 * nc);
+    eq_cache(p);
+#pragma omp parallel for schedule(static) num_threads(p->nthreads)
+    for (int c = 0; c < nc; c++) {
+        double rho, u1, u2, th;
+        prim(p->W + 4 * c, &rho, &u1, &u2, &th);
+        const double itau = inv_tau_of(p, rho, th), V = p->vol[c];
+        double wh[4] = { 0, 0, 0, 0 }, rt = 0, dtt[4] = { 0, 0, 0, 0 };
+        for (int k = 0; k < nv; k++) {
+            double dg[2][4], g1, g2;
+            dg_dW_cell(p, c, k, dg, dtt);
+            eq_cell_g(p, c, k, &g1, &g2);
+            const size_t o = ((size_t)c * nv + k) * 2;
+            const double d0 = phin[o] - phi[o], d1 = phin[o + 1] - phi[o + 1];
+            for (int m = 0; m < 4; m++) wh[m] += p->w[k] * (d0 * dg[0][m] + d1 * dg[1][m]);
+            rt += p->w[k] * (d0 * (g1 - p->f[o]) + d1 * (g2 - p->f[o + 1])) * itau;
+        }
+        for (int m = 0; m < 4; m++) y[4 * c + m] = V * (itau * wh[m] - dtt[m] * rt);
+    }
+    macro_solve_adj(p, y, p->aDinv, p->aO, z);
     for (int c = 0; c < nc; c++)
         for (int k = 0; k < nv; k++) {
-            double dg[2][4], dtt[4];
-            dg_dW_cell(p, c, k, dg, dtt);
-            const double *Rk = R + ((size_t)c * nv + k) * 2;
-            for (int m = 0; m < 4; m++) r[4 * c + m] += p->w[k] * (dg[0][m] * Rk[0] + dg[1][m] * Rk[1]);
+            const double v1 = p->v[2 * k], v2 = p->v[2 * k + 1], *zc = z + 4 * c;
+            const size_t o = ((size_t)c * nv + k) * 2;
+            phin[o] -= zc[0] + zc[1] * v1 + zc[2] * v2 + zc[3] * 0.5 * (v1 * v1 + v2 * v2);
+            phin[o + 1] -= zc[3];
         }
-    macro_solve_T(p, r, p->aDinv, p->aOT, p->apred);
-    p->apred_on = 1;
-    free(R); free(r);
+    free(y); free(z);
 }
 
 int or_set_acceleration(or_problem *p, int every, int inner)
@@ -1225,29 +1269,29 @@ int or_set_acceleration(or_problem *p, int every, int inner)
     return 0;
 }
 
-/* the adjoint prediction's right-hand side r* [nc][4] at the current phi
- * (pins) */
-void or_adjoint_macro_residual(or_problem *p, double *rs)
+/* the Gauss-Seidel map L of the adjoint's frozen system and its transpose
+ * (pins; after or_adjoint_init with the prediction on) */
+int or_macro_gs(or_problem *p, const double *r, double *x)
 {
-    const int nc = p->nc, nv = p->nv;
-    double *R = malloc(sizeof(double) * 2 * (size_t)nc * nv);
-    or_adjoint_operator(p, p->phi, 1, R);
-    memset(rs, 0, sizeof(double) * 4 * nc);
-    for (int c = 0; c < nc; c++)
-        for (int k = 0; k < nv; k++) {
-            double dg[2][4], dtt[4];
-            dg_dW_cell(p, c, k, dg, dtt);
-            const double *Rk = R + ((size_t)c * nv + k) * 2;
-            for (int m = 0; m < 4; m++) rs[4 * c + m] += p->w[k] * (dg[0][m] * Rk[0] + dg[1][m] * Rk[1]);
-        }
-    free(R);
+    if (!p->aDinv) return -1;
+    macro_solve(p, r, p->aDinv, p->aO, x);
+    return 0;
+}
+
+int or_macro_gs_adj(or_problem *p, const double *s, double *rbar)
+{
+    if (!p->aDinv) return -1;
+    macro_solve_adj(p, s, p->aDinv, p->aO, rbar);
+    return 0;
 }
 
 /* the macroscopic system of the current state (pins): r [nc][4], D^-1
- * [nc][4][4], O [nc][4][4][4] */
-void or_macro_system(or_problem *p, double *r, double *Dinv, double *O)
+ * [nc][4][4] (pseudo-time term included), O [nc][4][4][4], and the
+ * pseudo-time term lam [nc] */
+void or_macro_system(or_problem *p, double *r, double *Dinv, double *O, double *lam)
 {
     macro_assemble(p, r, Dinv, O);
+    for (int c = 0; c < p->nc; c++) lam[c] = macro_shift(p, c);
 }
 
 /* One Jacobi sweep of eq. (numerpr_gov), every cell from f^n.  Returns the
@@ -1320,7 +1364,7 @@ void or_get_f(const or_problem *p, double *out) { memcpy(out, p->f, sizeof(doubl
 void or_set_f(or_problem *p, const double *in) { memcpy(p->f, in, sizeof(double) * (size_t)p->nc * p->nv * 2); update_W_F(p, p->f); p->corr_ok = 0; p->acc_sweeps = 0; }
 void or_get_W(const or_problem *p, double *out) { memcpy(out, p->W, sizeof(double) * 4 * p->nc); }
 void or_get_phi(const or_problem *p, double *out) { memcpy(out, p->phi, sizeof(double) * (size_t)p->nc * p->nv * 2); }
-void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); p->acorr_ok = 0; p->apred_on = 0; p->acc_asweeps = 0; }
+void or_set_phi(or_problem *p, const double *in) { memcpy(p->phi, in, sizeof(double) * (size_t)p->nc * p->nv * 2); p->acorr_ok = 0; p->acc_asweeps = 0; }
 
 /* wall value f1_{l,k}: cell value on Xi^+, F_l gbar1 on Xi^- (Sec. 3.2) */
 static double wall_f1(const or_problem *p, const double *f, int l, int k)
@@ -1704,18 +1748,15 @@ void or_adjoint_init(or_problem *p)
 {
     memset(p->phi, 0, sizeof(double) * (size_t)p->nc * p->nv * 2);
     p->acc_asweeps = 0;
-    p->apred_on = 0;
     if (p->acc_every > 0 && p->order == 1) {
-        /* the primal macroscopic system at the frozen f, transposed */
+        /* the primal macroscopic system at the frozen f */
         const size_t nc = p->nc;
-        double *r = malloc(sizeof(double) * 4 * nc), *O = malloc(sizeof(double) * 64 * nc);
-        free(p->aDinv); free(p->aOT); free(p->apred);
+        double *r = malloc(sizeof(double) * 4 * nc);
+        free(p->aDinv); free(p->aO);
         p->aDinv = malloc(sizeof(double) * 16 * nc);
-        p->aOT = malloc(sizeof(double) * 64 * nc);
-        p->apred = calloc(4 * nc, sizeof(double));
-        macro_assemble(p, r, p->aDinv, O);
-        macro_transpose(p, O, p->aOT);
-        free(r); free(O);
+        p->aO = malloc(sizeof(double) * 64 * nc);
+        macro_assemble(p, r, p->aDinv, p->aO);
+        free(r);
     }
     if (p->order == 2) {
         /* limiter factors of the converged f, frozen for the adjoint */
@@ -1736,10 +1777,6 @@ double or_adjoint_iterate(or_problem *p, int niter)
     double r = 0;
     for (int it = 0; it < niter; it++) {
         adjoint_moments(p, p->phi, What, rtau, Phi);
-        if (p->apred_on) {
-            for (int q = 0; q < 4 * p->nc; q++) What[q] += p->apred[q];
-            p->apred_on = 0;
-        }
         const int so = p->order == 2;
         if (so && (!p->acorr_ok || p->asince == p->kcorr)) {
             so_adjoint_term(p, p->phi, Phi, p->acorr);
@@ -1782,10 +1819,13 @@ double or_adjoint_iterate(or_problem *p, int niter)
         double num = 0, den = 0;
         for (int c = 0; c < p->nc; c++) { num += p->cellred[2 * c]; den += p->cellred[2 * c + 1]; }
         r = den > 0 ? sqrt(num / den) : 0.0;
+        /* every K-th sweep: the transposed prediction's correction (the
+         * residual above is the plain sweep's change) */
+        if (p->acc_every > 0 && p->aDinv && !so && (p->acc_asweeps + 1) % p->acc_every == 0)
+            macro_adjoint_correct(p, p->phi, p->phin);
         double *t = p->phi; p->phi = p->phin; p->phin = t;
         if (so) p->asince++;
         p->acc_asweeps++;
-        if (p->acc_every > 0 && p->aDinv && !so && p->acc_asweeps % p->acc_every == 0) macro_adjoint_predict(p);
     }
     free(What); free(rtau); free(Phi);
     return r;

@@ -163,23 +163,31 @@ int dvm_solver_set_scheme(dvm_solver *s, int order, int limiter, int correction_
  * in the near-continuum regime, where collisions amplify the moment error
  * every sweep; the conservative one does not. */
 int dvm_solver_set_equilibrium(dvm_solver *s, int kind);
-/* Macroscopic prediction of the primal iteration (Sec. 3.1: approximate
- * macroscopic equations from the continuum limit provide prediction
- * solutions that accelerate the kinetic iteration), first-order scheme and
- * conservative equilibrium (the macroscopic equations are conservation
- * laws; DVM_EINVAL with order 2 or the pointwise Maxwellian), set before
- * dvm_solver_bind (the workspace grows by 108 doubles per cell; DVM_ESTATE
- * once bound).  every > 0: after every
+/* Macroscopic prediction of the primal and adjoint iterations (Sec. 3.1:
+ * approximate macroscopic equations from the continuum limit provide
+ * prediction solutions that accelerate the kinetic iteration), first-order
+ * scheme and conservative equilibrium (the macroscopic equations are
+ * conservation laws; DVM_EINVAL with order 2 or the pointwise Maxwellian),
+ * set before dvm_solver_bind (the workspace grows by 108 doubles per cell,
+ * 64 more with the adjoint; DVM_ESTATE once bound).  every > 0: after every
  * `every`-th primal sweep (counted from dvm_primal_init, a loaded or
  * copied f), the moments r of the kinetic residual of eq. (numerpr_gov)
- * drive the linearised macroscopic system A dW = -r, A being the moments of
- * the scheme's upwind transport of equilibrium perturbations (each face's
- * upwind cell's dg/dW; the diffuse wall's response through F_l), solved by
- * `inner` red-black block Gauss-Seidel steps from dW = 0; W + dW, limited
- * so that rho and theta change by at most 20% per cell, is the state the
- * next sweep relaxes towards.  r vanishes at the discrete solution, so the
- * converged state is the plain iteration's.  In batches the prediction runs
- * on each member's own cadence, with the same kernels.  every = 0: off. */
+ * drive the linearised macroscopic system (A + Lambda) dW = -r, A being
+ * the moments of the scheme's upwind transport of equilibrium perturbations
+ * (each face's upwind cell's dg/dW; the diffuse wall's response through
+ * F_l) and Lambda the pseudo-time term (|u| + c) sum_q |S_q| / 1000 per
+ * cell, solved by `inner` red-black block Gauss-Seidel steps from dW = 0;
+ * W + dW, limited so that rho and theta change by at most 20% per cell, is
+ * the state the next sweep relaxes towards.  Every `every`-th adjoint sweep
+ * (counted from dvm_adjoint_init or a loaded phi) is corrected by the
+ * transpose of that step, -Psi L^T (H^T dphi) with L the Gauss-Seidel map,
+ * H the sweep's response to the predicted moments and dphi the sweep's
+ * change, so the accelerated adjoint iteration converges like the
+ * accelerated primal one.  Both corrections vanish at the discrete
+ * solutions, so the converged states are the plain iterations'; the
+ * residual reported is the plain sweep's change.  In batches the
+ * prediction runs on each member's own cadence, with the same kernels.
+ * every = 0: off. */
 int dvm_solver_set_acceleration(dvm_solver *s, int every, int inner);
 /* Exact device bytes the solver needs (used for admission by footprint). */
 size_t dvm_solver_workspace_bytes(const dvm_solver *s);

@@ -1746,6 +1746,9 @@ static void so_adjoint_term(const or_problem *p, const double *phi, const double
 
 void or_adjoint_init(or_problem *p)
 {
+    /* a primal prediction may have left the predicted moments in W for the
+     * next sweep: the adjoint is taken at the moments of f */
+    if (p->acc_every > 0) update_W_F(p, p->f);
     memset(p->phi, 0, sizeof(double) * (size_t)p->nc * p->nv * 2);
     p->acc_asweeps = 0;
     if (p->acc_every > 0 && p->order == 1) {

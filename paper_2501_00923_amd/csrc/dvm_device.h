@@ -193,6 +193,7 @@ __device__ __forceinline__ void eq_moments_jac(const DevSolve &d, const double (
 __device__ __forceinline__ void eq_conservative(const DevSolve &d, const double (&W)[4], double (&P)[4],
                                                 double *Minv)
 {
+    const double P0[4] = {P[0], P[1], P[2], P[3]};
     for (int it = 0; it < kEqNewton; it++) {
         double m[4], J[4][4], r[4], dP[4];
         eq_moments_jac(d, P, m, J);
@@ -201,6 +202,21 @@ __device__ __forceinline__ void eq_conservative(const DevSolve &d, const double 
         solve4(J, r, dP);
 #pragma unroll
         for (int a = 0; a < 4; a++) P[a] += dP[a];
+    }
+    // a grid too coarse for the state (a Maxwellian much narrower than the
+    // velocity spacing) can leave Newton without a usable root: the cell then
+    // keeps the pointwise Maxwellian of its primitive variables
+    if (!(P[0] > 0) || !(P[3] > 0) || !isfinite(P[1]) || !isfinite(P[2])) {
+#pragma unroll
+        for (int a = 0; a < 4; a++) P[a] = P0[a];
+        if (Minv) {
+            const double rho = P0[0], u1 = P0[1], u2 = P0[2], E = W[3] / W[0], ir = 1.0 / rho, k23 = 2.0 / 3.0;
+            const double J[16] = {1.0, 0.0, 0.0, 0.0, -u1 * ir, ir, 0.0, 0.0, -u2 * ir, 0.0, ir, 0.0,
+                                  k23 * (u1 * u1 + u2 * u2 - E) * ir, -k23 * u1 * ir, -k23 * u2 * ir, k23 * ir};
+#pragma unroll
+            for (int q = 0; q < 16; q++) Minv[q] = J[q];
+        }
+        return;
     }
     if (Minv) {
         double m[4], J[4][4];

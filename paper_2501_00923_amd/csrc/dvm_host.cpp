@@ -994,6 +994,9 @@ int dvm_adjoint_init(dvm_solver *s)
     if (s->phase < 0) return fail(DVM_ESTATE, "no primal state to linearise about");
     if (s->phase == 0) s->frozen_fpar = s->fpar;
     fill_dev(*s);
+    // a primal prediction may have left the predicted moments in W for the
+    // next sweep: the adjoint is taken at the moments of f
+    if (s->acc_every > 0) HIP_OK(dvm::launch_moments(s->dev, s->frozen_fpar, s->stream));
     HIP_OK(dvm::launch_adjoint_init(s->dev, s->frozen_fpar, s->stream));
     if (s->order == 2) HIP_OK(dvm::launch_so_freeze(s->dev, s->frozen_fpar, s->stream));
     if (s->acc_every > 0) HIP_OK(dvm::launch_macro_adjoint_setup(s->dev, s->frozen_fpar, s->stream));

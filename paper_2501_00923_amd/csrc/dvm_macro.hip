@@ -10,7 +10,10 @@
 //      A dW = -r with A the moments of the scheme's upwind transport of
 //      equilibrium perturbations: the outflow faces carry the cell's own
 //      dg/dW, the inflow faces the neighbour's, the far field nothing and
-//      the wall face the diffuse value's response gbar dF_l; stored as the
+//      the wall face the diffuse value's response gbar dF_l; plus the
+//      pseudo-time term (|u| + c) sum_q |S_q| / CFL (CFL 1000) on the
+//      diagonal, which keeps near-singular modes of the steady operator (a
+//      slow wake, a sonic region) from being amplified; stored as the
 //      inverse of each cell's own block and the blocks of its four face
 //      neighbours;
 //   3. k_macro_rbgs: red-black block Gauss-Seidel half steps from dW = 0
@@ -31,6 +34,7 @@
 namespace dvm {
 
 constexpr int kMacroState = 20;   // doubles per cell: P' (4), dP'/dW (16, row = parameter)
+constexpr double kMacroCFL = 1000.0;
 
 // ---------------------------------------------------------------------------
 // per-cell equilibrium parameters and their derivative, one wave per cell
@@ -206,6 +210,13 @@ __global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
         for (int x = 0; x < 4; x++)
 #pragma unroll
             for (int m = 0; m < 4; m++) Dm[x][m] += wall1[x] * dF[m];
+        // pseudo-time term V/dt of the cell
+        double sS = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) sS += hypot(Sx[q], Sy[q]);
+        const double lam = (sqrt(u1 * u1 + u2 * u2) + sqrt(5.0 / 3.0 * th)) * sS / kMacroCFL;
+#pragma unroll
+        for (int x = 0; x < 4; x++) Dm[x][x] += lam;
         double *Di = d.mDinv + 16 * c;
 #pragma unroll
         for (int b2 = 0; b2 < 4; b2++) {
@@ -272,11 +283,9 @@ __global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
 // ---------------------------------------------------------------------------
 // one colour of a red-black block Gauss-Seidel step, a thread per cell
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, int transposed,
-                                                       const double *__restrict__ src, double *__restrict__ dst)
+__global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, const double *__restrict__ src,
+                                                       double *__restrict__ dst)
 {
-    // transposed: the adjoint's A^T, diagonal D^T (read from D^-1 by
-    // columns) and the transposed neighbour blocks
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.nc) return;
     const int m = d.cell_of[c];
@@ -289,23 +298,21 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, i
     double b[4];
 #pragma unroll
     for (int a = 0; a < 4; a++) b[a] = -d.mr[4 * c + a];
-    const double *Ob = transposed ? d.mOT : d.mO;
     for (int q = 0; q < 4; q++) {
         const int n = d.nbr[4 * c + q];
         if (n < 0) continue;
-        const double *O = Ob + 64 * c + 16 * q;
+        const double *O = d.mO + 64 * c + 16 * q;
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
             for (int e = 0; e < 4; e++) b[a] -= O[4 * a + e] * src[4 * n + e];
     }
     const double *Di = d.mDinv + 16 * c;
-    const int sa = transposed ? 1 : 4, se = transposed ? 4 : 1;
 #pragma unroll
     for (int a = 0; a < 4; a++) {
         double acc = 0;
 #pragma unroll
-        for (int e = 0; e < 4; e++) acc += Di[sa * a + se * e] * b[e];
+        for (int e = 0; e < 4; e++) acc += Di[4 * a + e] * b[e];
         dst[4 * c + a] = acc;
     }
 }
@@ -352,8 +359,8 @@ hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream
     hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mx[0], 4 * d.nc);
     if (hipError_t e = hipGetLastError()) return e;
     for (int it = 0; it < inner; it++) {
-        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, 0, d.mx[0], d.mx[1]);
-        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 1, 0, d.mx[1], d.mx[0]);
+        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, d.mx[0], d.mx[1]);
+        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 1, d.mx[1], d.mx[0]);
         if (hipError_t e = hipGetLastError()) return e;
     }
     hipLaunchKernelGGL(k_macro_apply, dim3(gt), dim3(kBlock), 0, st, d, par, d.mx[0]);
@@ -361,13 +368,24 @@ hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream
 }
 
 // ---------------------------------------------------------------------------
-// adjoint prediction: with the conservative equilibrium the adjoint operator
-// maps collision-invariant perturbations Psi . dl onto residuals whose
-// dg/dW-weighted moments are A^T dl (A the primal system at the frozen f,
-// assembled once at the adjoint's start).  Every K adjoint sweeps the
-// dg/dW-weighted moments r* of the adjoint residual of eq. (numerad_gov)
-// drive A^T dl = -r*, and dl joins the adjoint moments What that the next
-// sweep builds phi_eq from.
+// adjoint prediction: the transpose of the primal's accelerated sweep.
+// Linearised at the converged f, the primal sweep after a prediction is
+// f' = f + D^-1 Q R'(f), Q = I - H L M (M the moments, L the Gauss-Seidel
+// map above, H = dg/dW V/tau + (g - f) d(V/tau)/dW: how the predicted
+// moments enter the sweep).  Its transpose for the adjoint equation is
+// phi' = phi_s - Psi L^T (H^T (phi_s - phi)), phi_s the plain adjoint
+// sweep's result: every K-th adjoint sweep
+//   1. k_macro_adj_y: y = H^T (phi_s - phi) per cell, from the adjoint
+//      moments the two sweeps left (What and rho_tau are linear in phi):
+//      y = V (What_s - What) / tau - V (1/tau dtau/dW) (rho_tau,s - rho_tau);
+//   2. k_macro_rbgs_adj: z = L^T y, the Gauss-Seidel half steps transposed
+//      in reverse order (the neighbour blocks transposed once, at the
+//      adjoint's start, by k_macro_transpose);
+//   3. k_macro_adj_correct: phi_s -= (z . Psi, z_3), then the adjoint
+//      moments of the corrected phi (k_adjoint_moments).
+// The accelerated adjoint cycle then has the eigenvalues of the primal's,
+// and the correction vanishes with the sweep's change (the adjoint solution
+// is the plain iteration's).
 // ---------------------------------------------------------------------------
 
 // the transposed neighbour blocks: OT[c][q] = O[n][q']^T for the face q' of
@@ -394,88 +412,89 @@ __global__ __launch_bounds__(kBlock) void k_macro_transpose(DevSolve d)
     }
 }
 
-// r*_c = sum_k w (dg_c,k/dW)^T R*_c,k, R* the adjoint residual of phi[ppar]
-// (downstream values: neighbour, 0 at the far field, (Phi_l - m_J, 0) at the
-// wall; source phi_eq / tau + phi_tau from the adjoint moments of phi[ppar]),
-// one wave per cell
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_macro_adj_residual(DevSolve d, int ppar)
-{
-    using T2 = typename Vec2<T>::type;
-    __shared__ double tabX[kBlock / kWave][kMaxN1D], tabY[kBlock / kWave][kMaxN1D];
-    const int w = (int)(threadIdx.x / kWave), lane = threadIdx.x % kWave;
-    const int c0 = blockIdx.x * (kBlock / kWave) + w;
-    const bool act = c0 < d.nc;                 // idle waves of the last workgroup only join the barrier
-    const int c = act ? c0 : d.nc - 1;
-    const int nv = d.nv, n1 = d.n1, obj = d.objective;
-    const T2 *__restrict__ ph = static_cast<const T2 *>(d.phi[ppar]);
-    const double *ac = d.acoef + kAcoef * c;
-    const double P[4] = {ac[0], ac[1], ac[2], ac[3]}, itau = ac[4], kap = ac[5];
-    const double *aw = d.aW[ppar] + 8 * c;
-    const double rt = aw[4];
-    const double C0 = aw[0] * itau - rt * ac[6], C1 = aw[1] * itau - rt * ac[7];
-    const double C2 = aw[2] * itau - rt * ac[8], C3 = aw[3] * itau - rt * ac[9];
-    const double V = d.vol[c];
-    int nb[4];
-    double Sx[4], Sy[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        nb[q] = d.nbr[4 * c + q];
-        Sx[q] = d.S[8 * c + 2 * q];
-        Sy[q] = d.S[8 * c + 2 * q + 1];
-    }
-    const int wl = nb[0] <= -2 ? -2 - nb[0] : -1;
-    const double Phw = wl >= 0 ? d.Phi[ppar][wl] : 0.0;
-    macro_tables(d, P, tabX[w], tabY[w]);
-    __syncthreads();
-    const size_t row = (size_t)c * nv;
-    double acc[4] = {0, 0, 0, 0};
-    for (int k = lane; k < nv; k += kWave) {
-        const int a = k % n1, b = k / n1;
-        const double v1 = d.vx[a], v2 = d.vy[b], wt = d.wx[a] * d.wy[b];
-        double g1, g2, d1[4], d2[4];
-        dg_dP(kap, P, tabX[w][a], tabY[w][b], v1, v2, g1, g2, d1, d2);
-        const T2 pk = ph[row + k];
-        const double p1 = (double)pk.x, p2 = (double)pk.y;
-        double r1 = 0, r2 = 0;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const double s = v1 * Sx[q] + v2 * Sy[q];
-            if (s > 0) {
-                double b1 = 0, b2 = 0;
-                if (nb[q] >= 0) {
-                    const T2 u = ph[(size_t)nb[q] * nv + k];
-                    b1 = (double)u.x;
-                    b2 = (double)u.y;
-                } else if (nb[q] <= -2) {
-                    b1 = Phw - mJ_of(obj, v1, v2);
-                }
-                r1 += s * (p1 - b1);
-                r2 += s * (p2 - b2);
-            }
-        }
-        const double s1 = C0 + C1 * v1 + C2 * v2 + C3 * 0.5 * (v1 * v1 + v2 * v2), s2 = C3;
-        r1 += V * (p1 * itau - s1);
-        r2 += V * (p2 * itau - s2);
-#pragma unroll
-        for (int p = 0; p < 4; p++) acc[p] += wt * (d1[p] * r1 + d2[p] * r2);
-    }
-    wave_sum<4>(acc);
-    if (act && lane == 0) {
-        const double *M = ac + 16;
-#pragma unroll
-        for (int m = 0; m < 4; m++)
-            d.mr[4 * c + m] = ((acc[0] * M[m] + acc[1] * M[4 + m]) + acc[2] * M[8 + m]) + acc[3] * M[12 + m];
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_macro_adj_apply(DevSolve d, int ppar, const double *__restrict__ x)
+// y_c = H_c^T (phi_s - phi) from the adjoint moments of phi_s (aW[pnew]) and
+// of phi (aW[pnew ^ 1]), written as the seed of the transposed solve
+__global__ __launch_bounds__(kBlock) void k_macro_adj_y(DevSolve d, int pnew, double *__restrict__ y)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.nc) return;
-    double *aw = d.aW[ppar] + 8 * c;
+    const double *an = d.aW[pnew] + 8 * c, *ao = d.aW[pnew ^ 1] + 8 * c;
+    const double *ac = d.acoef + kAcoef * c;
+    const double V = d.vol[c], itau = ac[4], drt = an[4] - ao[4];
 #pragma unroll
-    for (int a = 0; a < 4; a++) aw[a] += x[4 * c + a];
+    for (int m = 0; m < 4; m++) y[4 * c + m] = V * (itau * (an[m] - ao[m]) - ac[6 + m] * drt);
+}
+
+__device__ __forceinline__ bool macro_colour(const DevSolve &d, int c, int colour)
+{
+    const int m = d.cell_of[c];
+    return (((m % d.ni) + (m / d.ni)) & 1) == colour;
+}
+
+// one transposed half step of k_macro_rbgs (colour `colour`), a thread per
+// cell: the forward step set x_c = Dinv_c (-r_c - sum_q O_cq src_nbr) on its
+// colour and copied the rest; given the adjoint ob of its output, t_c =
+// -Dinv_c^T ob_c joins rbar on the colour, and the adjoint of its input is
+// ib_m = (m off the colour: ob_m) + sum_q OT_mq t_nbr (neighbours on the
+// colour)
+__global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colour, const double *__restrict__ ob,
+                                                           double *__restrict__ ib, double *__restrict__ rbar)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= d.nc) return;
+    double acc[4];
+    const bool on = macro_colour(d, m, colour);
+#pragma unroll
+    for (int a = 0; a < 4; a++) acc[a] = on ? 0.0 : ob[4 * m + a];
+    for (int q = 0; q < 4; q++) {
+        const int n = d.nbr[4 * m + q];
+        if (n < 0 || !macro_colour(d, n, colour)) continue;
+        const double *Di = d.mDinv + 16 * n;
+        double t[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            double s = 0;
+#pragma unroll
+            for (int e = 0; e < 4; e++) s += Di[4 * e + a] * ob[4 * n + e];
+            t[a] = -s;
+        }
+        const double *OT = d.mOT + 64 * m + 16 * q;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[a] += OT[4 * a + e] * t[e];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++) ib[4 * m + a] = acc[a];
+    if (on) {
+        const double *Di = d.mDinv + 16 * m;
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            double s = 0;
+#pragma unroll
+            for (int e = 0; e < 4; e++) s += Di[4 * e + a] * ob[4 * m + e];
+            rbar[4 * m + a] -= s;
+        }
+    }
+}
+
+// phi[pnew] -= (z . Psi, z_3), a thread per (cell, velocity)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_macro_adj_correct(DevSolve d, int pnew, const double *__restrict__ z)
+{
+    using T2 = typename Vec2<T>::type;
+    T2 *__restrict__ ph = static_cast<T2 *>(d.phi[pnew]);
+    const size_t n = (size_t)d.nc * d.nv, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int c = (int)(i / d.nv), k = (int)(i % d.nv);
+        const double v1 = d.vx[k % d.n1], v2 = d.vy[k / d.n1];
+        const double *zc = z + 4 * c;
+        T2 p = ph[i];
+        const double s1 = ((zc[0] + zc[1] * v1) + zc[2] * v2) + zc[3] * (0.5 * (v1 * v1 + v2 * v2));
+        p.x = (T)((double)p.x - s1);
+        p.y = (T)((double)p.y - zc[3]);
+        ph[i] = p;
+    }
 }
 
 hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t st)
@@ -490,21 +509,24 @@ hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_macro_adjoint_predict(const DevSolve &d, int ppar, int inner, hipStream_t st)
+hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, hipStream_t st)
 {
-    constexpr int per_block = kBlock / kWave;
-    const int gw = (d.nc + per_block - 1) / per_block, gt = (d.nc + kBlock - 1) / kBlock;
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_adj_residual<T>, dim3(gw), dim3(kBlock), 0, st, d, ppar));
+    const int gt = (d.nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_macro_adj_y, dim3(gt), dim3(kBlock), 0, st, d, pnew, d.mx[0]);
+    hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mr, 4 * d.nc);
     if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mx[0], 4 * d.nc);
-    if (hipError_t e = hipGetLastError()) return e;
+    // the forward steps ran it = 0 .. inner-1, colour 0 (x -> y) then 1
+    // (y -> x); here it = inner-1 .. 0, colour 1 (adjoint of x -> of y) then 0
     for (int it = 0; it < inner; it++) {
-        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, 1, d.mx[0], d.mx[1]);
-        hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 1, 1, d.mx[1], d.mx[0]);
+        hipLaunchKernelGGL(k_macro_rbgs_adj, dim3(gt), dim3(kBlock), 0, st, d, 1, d.mx[0], d.mx[1], d.mr);
+        hipLaunchKernelGGL(k_macro_rbgs_adj, dim3(gt), dim3(kBlock), 0, st, d, 0, d.mx[1], d.mx[0], d.mr);
         if (hipError_t e = hipGetLastError()) return e;
     }
-    hipLaunchKernelGGL(k_macro_adj_apply, dim3(gt), dim3(kBlock), 0, st, d, ppar, d.mx[0]);
-    return hipGetLastError();
+    const size_t pairs = (size_t)d.nc * d.nv;
+    const int gp = (int)std::min<size_t>((pairs + kBlock - 1) / kBlock, 16384);
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_adj_correct<T>, dim3(gp), dim3(kBlock), 0, st, d, pnew, d.mr));
+    if (hipError_t e = hipGetLastError()) return e;
+    return launch_adjoint_moments(d, pnew, st);
 }
 
 }  // namespace dvm

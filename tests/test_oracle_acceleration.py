@@ -131,6 +131,22 @@ def test_prediction_is_limited_and_accelerates_near_the_continuum():
     assert r_q > 1e-5, r_q
 
 
+def test_adjoint_is_taken_at_the_moments_of_f():
+    """A prediction leaves the predicted moments in W for the next sweep;
+    the adjoint linearises about f, so its start puts the moments of f back."""
+    p = oracle.Problem.from_workload(I.tiny_naca(Kn=0.02, Ma=0.9), nthreads=2)
+    p.set_equilibrium(1)
+    p.set_acceleration(5, 20)
+    p.primal_init()
+    p.primal_iterate(10)                 # ends with a prediction
+    v, w = p.vgrid()
+    f = p.f
+    Wf = np.array([oracle.moments(v, w, f[c]) for c in range(p.nc)])
+    assert np.max(np.abs(p.W - Wf)) > 1e-6 * np.max(np.abs(Wf))
+    p.adjoint_init()
+    assert np.max(np.abs(p.W - Wf)) <= 1e-14 * np.max(np.abs(Wf))
+
+
 def test_prediction_needs_the_conservative_equilibrium():
     p = oracle.Problem.from_workload(I.tiny_circle(), nthreads=1)
     with pytest.raises(ValueError):

@@ -176,7 +176,7 @@ def batch_roofline(n_members, seed, sweeps=20, warmup=3):
     return out
 
 
-def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every):
+def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every, accel_below_kn=None, accel=(5, 50)):
     """Solve server on a seeded request stream (circle / NACA shapes, meshes
     {64x32, 128x64, 256x128}, velocity grids {16^2, 32^2, 64^2} on [-6, 6],
     Kn log-uniform in [1e-3, 10], Ma in [0.3, 2], half wanting the adjoint).
@@ -196,17 +196,20 @@ def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every):
                         adjoint_tol=tol, max_iter=cap)
     reqs = I.poisson_stream(n_requests, 1.0, seed=seed)
     t0 = time.perf_counter()
-    cap_run = S.serve(reqs, S.GpuBackend(dvm.MIXED), cfg, realtime=False)
+
+    def backend(prec):
+        return S.GpuBackend(prec, accelerate_below_kn=accel_below_kn, accelerate=accel)
+    cap_run = S.serve(reqs, backend(dvm.MIXED), cfg, realtime=False)
     capacity = cap_run["solves_per_s"]
     print(f"[bench] serving capacity {capacity:.2f} solves/s ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
     rate = 0.8 * capacity
     stream = I.poisson_stream(n_requests, rate, seed=seed)
-    mix = S.serve(stream, S.GpuBackend(dvm.MIXED), cfg, realtime=True)
+    mix = S.serve(stream, backend(dvm.MIXED), cfg, realtime=True)
     c = mix["converged"]
     print(f"[bench] batched mixed: {c['count']} converged, {c['solves_per_s']:.2f} solves/s p50 {c['p50_ms']:.0f} ms "
           f"p99 {c['p99_ms']:.0f} ms; {mix['notconv']} capped", file=sys.stderr, flush=True)
-    one = S.serve_one_at_a_time(stream, S.GpuBackend(dvm.FP64), cfg, realtime=True)
+    one = S.serve_one_at_a_time(stream, backend(dvm.FP64), cfg, realtime=True)
     c = one["converged"]
     print(f"[bench] one-at-a-time fp64: {c['count']} converged, {c['solves_per_s']:.2f} solves/s p50 "
           f"{c['p50_ms']:.0f} ms p99 {c['p99_ms']:.0f} ms; {one['notconv']} capped", file=sys.stderr, flush=True)
@@ -223,10 +226,13 @@ def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every):
                 "all_finished": {"solves_per_s": o["solves_per_s"], "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
                                  "mean_ms": o["mean_ms"], "count": o["completed"]},
                 "failed": o["failed"], "wall_s": o["wall_s"], "peak_resident": o["peak_resident"],
-                "peak_GB": o["peak_bytes"] / 1e9}
+                "peak_GB": o["peak_bytes"] / 1e9,
+                "failed_requests": [{"rid": r.rid, "workload": next(q.workload.name for q in stream if q.rid == r.rid),
+                                     "error": r.error} for r in o["results"] if r.status == "failed"]}
     cm, co = mix["converged"], one["converged"]
     return {"requests": n_requests, "seed": seed, "arrival_rate_per_s": rate, "capacity_solves_per_s": capacity,
             "tol": tol, "iteration_cap": cap, "sweeps_per_check": check_every, "memory_budget_GB": budget_gb,
+            "accelerate_below_kn": accel_below_kn, "accelerate_every_inner": list(accel),
             "batched_mixed": summary(mix), "one_at_a_time_fp64": summary(one),
             "drag_rel_diff_mixed_vs_fp64_converged_in_both": {
                 "count": int(len(rel)), "median": float(np.median(rel)) if len(rel) else None,
@@ -477,6 +483,48 @@ def cst_fd_check(n_wake, n_half, nj, nv, Kn, Ma, h, tol, radius, order=1, limite
             "exact": stats(np.array([r["adjoint_exact"] for r in rows])), "rows": rows}
 
 
+def accel_check(kns, every, inner, cap, tol, plain_cap, precision_name="fp64"):
+    """The 256x128 NACA0012 C-grid with 64x64 sinh velocities (Ma 0.5),
+    conservative equilibrium: primal then adjoint solves to `tol` with the
+    macroscopic prediction (every `every` sweeps, `inner` red-black steps),
+    and the plain iteration with at most `plain_cap` sweeps per phase, for
+    each Kn: sweeps, residual reached, seconds, drag and its agreement."""
+    import numpy as np
+
+    from paper_2501_00923_amd import dvm
+    from paper_2501_00923_amd import inputs as I
+
+    prec = dvm.FP64 if precision_name == "fp64" else dvm.MIXED
+    rows = []
+    for Kn in kns:
+        wl = I.c3_naca_sinh(Kn)
+        row = {"Kn": Kn, "workload": wl.name}
+        for label, acc, mx in (("accelerated", (every, inner), cap), ("plain", None, plain_cap)):
+            s = dvm.Solver.from_workload(wl, precision=prec, equilibrium=dvm.EQ_CONSERVATIVE, accelerate=acc)
+            s.primal_init()
+            t0 = time.perf_counter()
+            itp, rp = s.primal_iterate(mx, tol=tol, check_every=25, raise_notconv=False)
+            tp = time.perf_counter() - t0
+            J, Cd = s.objective()
+            s.adjoint_init()
+            t0 = time.perf_counter()
+            ita, ra = s.adjoint_iterate(mx, tol=tol, check_every=25, raise_notconv=False)
+            ta = time.perf_counter() - t0
+            g = s.param_sensitivity(wl.grid.wall_jac)
+            row[label] = {"primal_sweeps": itp, "primal_resid": rp, "primal_s": tp, "adjoint_sweeps": ita,
+                          "adjoint_resid": ra, "adjoint_s": ta, "J": J, "Cd": Cd, "dJda": g.tolist()}
+            print(f"[accel] Kn {Kn:g} {label}: primal {itp} sweeps r {rp:.1e} ({tp:.1f} s), adjoint {ita} sweeps "
+                  f"r {ra:.1e} ({ta:.1f} s), C_d {Cd:.8f}", file=sys.stderr, flush=True)
+            del s
+        a, b = row["accelerated"], row["plain"]
+        row["J_rel_diff"] = abs(a["J"] - b["J"]) / abs(b["J"])
+        row["dJda_rel_diff"] = float(np.max(np.abs(np.array(a["dJda"]) - np.array(b["dJda"]))) /
+                                     np.max(np.abs(np.array(b["dJda"]))))
+        rows.append(row)
+    return {"every": every, "inner": inner, "tol": tol, "cap": cap, "plain_cap": plain_cap,
+            "precision": precision_name, "rows": rows}
+
+
 def stream_reference(nbytes_total):
     """Plain HIP streams (csrc/dvm_stream.hip) with the read/write mixes of
     the sweeps, moving `nbytes_total` bytes per launch: 1 read + 1 write
@@ -630,6 +678,20 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=64,
                     help="requests in the solve-server leg (0 skips it; 512 is the full stream)")
     ap.add_argument("--serving-cap", type=int, default=1000, help="sweep cap per phase per request")
+    ap.add_argument("--accel-check", action="store_true",
+                    help="the 256x128 C-grid with 64x64 sinh velocities at Kn 1e-3 .. 10: solves to --accel-tol with "
+                         "the macroscopic prediction against the plain iteration, and exit")
+    ap.add_argument("--accel-every", type=int, default=5)
+    ap.add_argument("--accel-inner", type=int, default=200)
+    ap.add_argument("--accel-tol", type=float, default=1e-8)
+    ap.add_argument("--accel-cap", type=int, default=20000)
+    ap.add_argument("--accel-plain-cap", type=int, default=3000)
+    ap.add_argument("--accel-kn", type=str, default="1e-3,1e-2,0.1,1,10")
+    ap.add_argument("--accel-precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--serving-accel-below-kn", type=float, default=0.5,
+                    help="requests below this Kn use the conservative equilibrium and the macroscopic prediction "
+                         "(0: none)")
+    ap.add_argument("--serving-accel-inner", type=int, default=50)
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 256x128 C-grid with 64x64 sinh velocities (134 M pairs) leg")
     ap.add_argument("--batch-members", type=int, default=24,
@@ -710,6 +772,11 @@ def main():
     if args.fd_check:
         print(json.dumps({"fd_check": fd_check(args.fd_h, args.fd_tol, order=args.fd_order,
                                                limiter=not args.fd_no_limiter)}))
+        return
+    if args.accel_check:
+        kns = [float(x) for x in args.accel_kn.split(",")]
+        print(json.dumps({"accel_check": accel_check(kns, args.accel_every, args.accel_inner, args.accel_cap,
+                                                     args.accel_tol, args.accel_plain_cap, args.accel_precision)}))
         return
     if args.deform_scale:
         print(json.dumps({"deform_scale": deform_scale()}))
@@ -849,7 +916,8 @@ def main():
     if args.serving_requests > 0:
         print(f"[bench] serving leg: {args.serving_requests} requests", file=sys.stderr, flush=True)
         serving = serving_leg(args.serving_requests, args.serving_seed, args.serving_cap, args.serving_tol,
-                              64.0, 20)
+                              64.0, 20, None if args.serving_accel_below_kn <= 0 else args.serving_accel_below_kn,
+                              (args.accel_every, args.serving_accel_inner))
     optimization = None
     if not args.no_optimize_leg:
         # a whole optimisation (Sec. 3.4) on a 128x64 NACA0012 C-grid, 32x32 velocities, Kn 1, Ma 0.5

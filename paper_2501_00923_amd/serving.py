@@ -244,17 +244,32 @@ class GpuBackend(Backend):
     advanced by one batch (rebuilt whenever the resident set or a phase
     changes)."""
 
-    def __init__(self, precision, stream=None, shape_params: bool = True):
+    def __init__(self, precision, stream=None, shape_params: bool = True, accelerate_below_kn=None,
+                 accelerate=(5, 50)):
+        """accelerate_below_kn: requests below this Kn (first order) solve
+        with the conservative equilibrium and the macroscopic prediction
+        `accelerate` = (every, inner) of both phases; None: never."""
         import torch
 
         from . import dvm
         self.dvm, self.torch = dvm, torch
         self.precision = precision
+        self.accelerate_below_kn = accelerate_below_kn
+        self.accelerate = tuple(accelerate)
         self.shape_params = shape_params
         self.stream = stream
         self._batch = None
         self._key = None
         self._fp_cache: Dict = {}
+
+    def _options(self, req):
+        """Solver options of a request: second-order requests as asked; below
+        the Kn threshold (first order), the conservative equilibrium and the
+        macroscopic prediction."""
+        order = getattr(req, "order", 1)
+        if (self.accelerate_below_kn is not None and order == 1 and req.workload.flow.Kn < self.accelerate_below_kn):
+            return dict(order=order, equilibrium=self.dvm.EQ_CONSERVATIVE, accelerate=self.accelerate)
+        return dict(order=order)
 
     def footprint(self, req) -> int:
         key = req.rid
@@ -262,7 +277,7 @@ class GpuBackend(Backend):
             wl = req.workload
             s = self.dvm.Solver(self.dvm.Mesh.from_grid(wl.grid), self.dvm.VGrid.from_spec(wl.vgrid), wl.flow.Kn,
                                 wl.flow.Ma, wl.flow.Tw, wl.flow.objective, self.precision, req.want_adjoint,
-                                bind=False, order=getattr(req, "order", 1))
+                                bind=False, **self._options(req))
             self._fp_cache[key] = s.workspace_bytes
         return self._fp_cache[key]
 
@@ -270,7 +285,7 @@ class GpuBackend(Backend):
         wl = req.workload
         s = self.dvm.Solver(self.dvm.Mesh.from_grid(wl.grid), self.dvm.VGrid.from_spec(wl.vgrid), wl.flow.Kn,
                             wl.flow.Ma, wl.flow.Tw, wl.flow.objective, self.precision, req.want_adjoint,
-                            stream=self.stream, order=getattr(req, "order", 1))
+                            stream=self.stream, **self._options(req))
         s.primal_init()
         return s
 

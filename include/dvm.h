@@ -168,8 +168,8 @@ int dvm_solver_set_equilibrium(dvm_solver *s, int kind);
  * prediction solutions that accelerate the kinetic iteration), first-order
  * scheme and conservative equilibrium (the macroscopic equations are
  * conservation laws; DVM_EINVAL with order 2 or the pointwise Maxwellian),
- * set before dvm_solver_bind (the workspace grows by 108 doubles per cell,
- * 64 more with the adjoint; DVM_ESTATE once bound).  every > 0: after every
+ * set before dvm_solver_bind (the workspace grows by 108 doubles per cell;
+ * DVM_ESTATE once bound).  every > 0: after every
  * `every`-th primal sweep (counted from dvm_primal_init, a loaded or
  * copied f), the moments r of the kinetic residual of eq. (numerpr_gov)
  * drive the linearised macroscopic system (A + Lambda) dW = -r, A being

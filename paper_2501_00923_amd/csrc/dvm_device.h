@@ -34,6 +34,18 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *lds)
     }
 }
 
+// Sum N doubles over each aligned group of G lanes (xor butterfly: every
+// lane of a group ends with the same bits, the order is fixed).
+template <int G, int N>
+__device__ __forceinline__ void group_sum(double (&v)[N])
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < N; i++) v[i] += __shfl_xor(v[i], off, G);
+    }
+}
+
 // Sum N doubles over the wave (xor butterfly: every lane ends with the same
 // bits, the order is fixed).
 template <int N>
@@ -123,18 +135,20 @@ __device__ __forceinline__ void solve4(double (&A)[4][4], double (&b)[4], double
 // variables of W, kEqNewton steps.  The Maxwellian factors as
 // rho/(2 pi theta) X(v1) Y(v2) on the tensor grid, so each step needs only
 // the 1-D sums R_p = sum_a wx_a X_a vx_a^p, T_p = sum_b wy_b Y_b vy_b^p
-// (p <= 4), summed per lane and reduced across the wave in a fixed order:
-// every lane ends with the same P.  Minv (may be null) receives
+// (p <= 4), summed per lane and reduced across a group of G lanes (the
+// wave, or a part of it that serves one cell) in a fixed order: every lane
+// of the group ends with the same P.  Minv (may be null) receives
 // (dm/dP)^{-1} = dP/dW at the final P, row q = parameter, column m = moment.
 constexpr int kEqNewton = 6;
 
+template <int G = kWave>
 __device__ __forceinline__ void eq_moments_jac(const DevSolve &d, const double (&P)[4], double (&m)[4],
                                                double (&J)[4][4])
 {
-    const int lane = threadIdx.x % kWave;
+    const int lane = threadIdx.x % G;
     const double u1 = P[1], u2 = P[2], th = P[3], h = 0.5 / th;
     double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = lane; i < d.n1; i += kWave) {
+    for (int i = lane; i < d.n1; i += G) {
         const double v = d.vx[i], e = v - u1, X = d.wx[i] * exp(-e * e * h);
         s[0] += X;
         s[1] += X * v;
@@ -142,7 +156,7 @@ __device__ __forceinline__ void eq_moments_jac(const DevSolve &d, const double (
         s[3] += X * v * v * v;
         s[4] += X * v * v * v * v;
     }
-    for (int i = lane; i < d.n2; i += kWave) {
+    for (int i = lane; i < d.n2; i += G) {
         const double v = d.vy[i], e = v - u2, Y = d.wy[i] * exp(-e * e * h);
         s[5] += Y;
         s[6] += Y * v;
@@ -150,7 +164,7 @@ __device__ __forceinline__ void eq_moments_jac(const DevSolve &d, const double (
         s[8] += Y * v * v * v;
         s[9] += Y * v * v * v * v;
     }
-    wave_sum<10>(s);
+    group_sum<G, 10>(s);
     const double *R = s, *T = s + 5;
     const double kap = P[0] / (2.0 * kPi * th);
     // d R_p / d u1 and d R_p / d theta (p = 0..2), likewise T with u2
@@ -190,13 +204,14 @@ __device__ __forceinline__ void eq_moments_jac(const DevSolve &d, const double (
                      0.5 * th * db0 - b3 / th);
 }
 
+template <int G = kWave>
 __device__ __forceinline__ void eq_conservative(const DevSolve &d, const double (&W)[4], double (&P)[4],
                                                 double *Minv)
 {
     const double P0[4] = {P[0], P[1], P[2], P[3]};
     for (int it = 0; it < kEqNewton; it++) {
         double m[4], J[4][4], r[4], dP[4];
-        eq_moments_jac(d, P, m, J);
+        eq_moments_jac<G>(d, P, m, J);
 #pragma unroll
         for (int a = 0; a < 4; a++) r[a] = W[a] - m[a];
         solve4(J, r, dP);
@@ -220,7 +235,7 @@ __device__ __forceinline__ void eq_conservative(const DevSolve &d, const double 
     }
     if (Minv) {
         double m[4], J[4][4];
-        eq_moments_jac(d, P, m, J);
+        eq_moments_jac<G>(d, P, m, J);
 #pragma unroll
         for (int b = 0; b < 4; b++) {
             double A[4][4], e[4] = {0, 0, 0, 0}, x[4];

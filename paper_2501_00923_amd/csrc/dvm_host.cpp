@@ -273,7 +273,7 @@ struct dvm_solver {
     struct {
         size_t nbr, patch, cell_of, S, vol, wall_cell, wA, wn, wa, wb, D, vx, vy, wx, wy, fd, gM, gw2;
         size_t f[2], W[2], F[2], red, phi[2], aW[2], Phi[2], acoef, Jl, sens, dJdn, jac, dJda, msens, dJdx, out;
-        size_t mstate, mr, mDinv, mO, mx[2], mOT;
+        size_t mstate, mr, mDinv, mO, mx[2];
         size_t rf, rn, G, corr, psi, dF, total;
     } off;
     char *base = nullptr;
@@ -355,16 +355,15 @@ void layout(dvm_solver &s)
     } else {
         o.rf = o.rn = o.G = o.corr = o.dF = o.psi = (size_t)-1;
     }
+    o.mstate = s.equil == DVM_EQ_CONSERVATIVE ? take(dvm::kEqState * nc * sizeof(double)) : (size_t)-1;
     if (s.acc_every > 0) {
-        o.mstate = take(20 * nc * sizeof(double));
         o.mr = take(4 * nc * sizeof(double));
         o.mDinv = take(16 * nc * sizeof(double));
         o.mO = take(64 * nc * sizeof(double));
         o.mx[0] = take(4 * nc * sizeof(double));
         o.mx[1] = take(4 * nc * sizeof(double));
-        o.mOT = s.want_adjoint ? take(64 * nc * sizeof(double)) : (size_t)-1;
     } else {
-        o.mstate = o.mr = o.mDinv = o.mO = o.mx[0] = o.mx[1] = o.mOT = (size_t)-1;
+        o.mr = o.mDinv = o.mO = o.mx[0] = o.mx[1] = (size_t)-1;
     }
     o.total = cur;
 }
@@ -445,7 +444,6 @@ void fill_dev(dvm_solver &s)
     d.mO = at<double>(s, s.off.mO);
     d.mx[0] = at<double>(s, s.off.mx[0]);
     d.mx[1] = at<double>(s, s.off.mx[1]);
-    d.mOT = at<double>(s, s.off.mOT);
 }
 
 int upload(dvm_solver &s, size_t off, const void *src, size_t bytes)
@@ -515,6 +513,10 @@ int sweeps(dvm_solver &s, int adjoint, int n)
             if (s.acc_every > 0 && ++s.acc_acount % s.acc_every == 0)
                 HIP_OK(dvm::launch_macro_adjoint_predict(s.dev, s.ppar, s.acc_inner, s.stream));
         } else {
+            if (s.equil == DVM_EQ_CONSERVATIVE) {
+                if (!s.dev.mstate) return fail(DVM_ESTATE, "no equilibrium parameter buffer");
+                HIP_OK(dvm::launch_eq_params(s.dev, s.fpar, 0, s.stream));
+            }
             HIP_OK(dvm::launch_primal_sweep(s.dev, s.fpar, s.stream));
             s.fpar ^= 1;
             if (s.acc_every > 0 && ++s.acc_count % s.acc_every == 0)
@@ -846,6 +848,7 @@ int dvm_solver_set_equilibrium(dvm_solver *s, int kind)
     if (kind != DVM_EQ_CONSERVATIVE && s->acc_every > 0)
         return fail(DVM_EINVAL, "the macroscopic prediction needs the conservative equilibrium");
     s->equil = kind;
+    layout(*s);             // the conservative equilibrium keeps its parameters per cell
     return DVM_OK;
 }
 
@@ -1446,6 +1449,15 @@ int dvm_batch_run(dvm_batch *b, int iters)
                 s->since[ph] = 0;
             }
             s->since[ph]++;
+        }
+        // primal members with the conservative equilibrium: its parameters
+        // of the current state, which their sweep reads
+        for (int m = 0; m < b->n; m++) {
+            dvm_solver *s = b->members[m];
+            if (s->phase == 0 && s->equil == DVM_EQ_CONSERVATIVE) {
+                if (!s->dev.mstate) return fail(DVM_ESTATE, "no equilibrium parameter buffer");
+                HIP_OK(dvm::launch_eq_params(s->dev, s->fpar ^ (it & 1), 0, b->stream));
+            }
         }
         int off = 0;
         for (int g = 0; g < 4; g++) {

@@ -13,6 +13,7 @@ constexpr int kWave = 64;          // wavefront width
 constexpr int kMaxN1D = 128;       // max velocity nodes per direction
 constexpr int kMaxParams = 64;
 constexpr int kAcoef = 32;         // doubles per cell of the adjoint coefficients
+constexpr int kEqState = 20;       // doubles per cell of mstate: P' (4), dP'/dW (16, row = parameter)
 
 // The sweeps give each workgroup a patch of kPatchI x kPatchJ cells, one
 // wave per cell; patches tile kTileI x kTileJ tiles, which follow each
@@ -84,12 +85,11 @@ struct DevSolve {
     void *psi;               // [nc][nv][2] limiter factors of the frozen f (storage type)
     double *dF;              // [nw] held wall-flux correction
     // macroscopic prediction (primal acceleration; null when off)
-    double *mstate;          // [nc][20] equilibrium parameters P' and dP'/dW
+    double *mstate;          // [nc][kEqState] equilibrium parameters P' and dP'/dW (conservative equilibrium)
     double *mr;              // [nc][4] moments of the kinetic residual
     double *mDinv;           // [nc][16] inverse of the cell's own block
-    double *mO;              // [nc][4][16] blocks of the face neighbours
+    double *mO;              // [nc][4][16] outflow block of each face (dg/dW form)
     double *mx[2];           // [nc][4] red-black iterates
-    double *mOT;             // [nc][4][16] transposed neighbour blocks (adjoint prediction)
 };
 
 // launches (all on `st`); par = index of the current f / phi buffer
@@ -102,6 +102,8 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st);
 hipError_t launch_adjoint_sweep(const DevSolve &d, int par, hipStream_t st);
 // adjoint moments (What, rho_tau) and wall multipliers of phi[par] (a loaded phi)
 hipError_t launch_adjoint_moments(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_adjoint_correct_moments(const DevSolve &d, int par, const double *z, hipStream_t st);
+hipError_t launch_eq_params(const DevSolve &d, int par, int with_M, hipStream_t st);
 hipError_t launch_wall_sens(const DevSolve &d, int fpar, int ppar, int n_params, hipStream_t st);
 hipError_t launch_mesh_sens(const DevSolve &d, int fpar, int ppar, hipStream_t st);
 // macroscopic prediction of the moments W[par] of f[par] (first-order

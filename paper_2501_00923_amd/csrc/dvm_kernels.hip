@@ -137,13 +137,13 @@ __device__ __forceinline__ void primal_patch(const DevSolve &d, int p, int par)
     const double itau = d.inv_tau_inf * rho * sqrt(2.0 * th);
     const double Vt = d.vol[c] * itau;
     // the equilibrium's parameters: the primitive variables, or those whose
-    // grid moments equal W (tau keeps the cell's own rho and theta)
+    // grid moments equal W (found by k_eq_params before the sweep; tau keeps
+    // the cell's own rho and theta)
     double Pe[4] = {rho, u1, u2, th};
     if (d.equil) {
-        const double Wv[4] = {W0, W1, W2, W3};
-        eq_conservative(d, Wv, Pe, nullptr);
+        const double *pe = d.mstate + kEqState * c;
 #pragma unroll
-        for (int a = 0; a < 4; a++) Pe[a] = uni(Pe[a]);
+        for (int a = 0; a < 4; a++) Pe[a] = uni(pe[a]);
     }
     patch_tables<T, false>(d, sm, w, lane, Pe[1], Pe[2], 0.5 / Pe[3]);
 
@@ -693,9 +693,11 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
 // Adjoint moments What, rho_tau and wall multipliers Phi_l of phi[par] with
 // no update (a loaded phi): the lane <-> velocity map, expressions and
 // summation order of the adjoint sweep's epilogue, so the next sweep sees
-// what a sweep that had produced this phi would have left.
-template <typename T>
-__device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, int par)
+// what a sweep that had produced this phi would have left.  CORR: phi is
+// first corrected in place by the collision invariant -(z . Psi, z_3) of the
+// adjoint prediction (z [nc][4]), and the moments are those of the result.
+template <typename T, bool CORR = false>
+__device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, int par, const double *z = nullptr)
 {
     using T2 = typename Vec2<T>::type;
     __shared__ PatchLds<T, false> sm;
@@ -704,7 +706,8 @@ __device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, 
     const bool act = w < cnt;
     const int c = c0 + (act ? w : 0);
     const int nv = d.nv, n1 = d.n1;
-    const T2 *__restrict__ pin = static_cast<const T2 *>(d.phi[par]);
+    // read and (CORR) written in place: no restrict
+    const T2 *pin = static_cast<const T2 *>(d.phi[par]);
     const T2 *__restrict__ fst = static_cast<const T2 *>(d.fstar);
     const T *__restrict__ gM = static_cast<const T *>(d.gM);
     const double *ac = d.acoef + kAcoef * c;
@@ -722,8 +725,20 @@ __device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, 
     const size_t row = (size_t)c * nv;
     __syncthreads();
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, R = 0, Pw = 0;
+    T2 *pio = static_cast<T2 *>(d.phi[par]);
+    double zc[4] = {0, 0, 0, 0};
+    if (CORR) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) zc[i] = uni(z[4 * c + i]);
+    }
     auto accumulate = [&](int a, int b, int k, T2 r, T2 fs) {
         const double v1d = sm.vx[a], v2d = sm.vy[b];
+        if (CORR) {
+            const double s1 = ((zc[0] + zc[1] * v1d) + zc[2] * v2d) + zc[3] * (0.5 * (v1d * v1d + v2d * v2d));
+            r.x = (T)((double)r.x - s1);
+            r.y = (T)((double)r.y - zc[3]);
+            pio[row + k] = r;
+        }
         const double wt = sm.wx[a] * sm.wy[b];
         const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
         const double g2 = (double)(th2 * (T)g1);
@@ -798,6 +813,14 @@ __global__ __launch_bounds__(kPatchBlock) void k_adjoint_moments(DevSolve d, int
     const int p = xcd_item(d.np, blockIdx.x);
     if (p < 0) return;
     adjoint_moments_patch<T>(d, p, par);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPatchBlock) void k_adjoint_correct_moments(DevSolve d, int par, const double *z)
+{
+    const int p = xcd_item(d.np, blockIdx.x);
+    if (p < 0) return;
+    adjoint_moments_patch<T, true>(d, p, par, z);
 }
 
 // one sweep of the primal-phase (or adjoint-phase) members of a batch that
@@ -1112,6 +1135,46 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
         if (hipError_t e = hipGetLastError()) return e;
     }
     DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_wall_phi0<T>, dim3(d.nw), dim3(kBlock), 0, st, d, 0));
+    return hipGetLastError();
+}
+
+// Discrete-conservative equilibrium parameters P'(W[par]) of every cell
+// (and dP'/dW if with_M) into mstate: kEqGroup lanes per cell, so one wave
+// serves several cells and the Newton steps' reductions span a few lanes.
+constexpr int kEqGroup = 16;
+
+__global__ __launch_bounds__(kBlock) void k_eq_params(DevSolve d, int par, int with_M)
+{
+    const int c = blockIdx.x * (kBlock / kEqGroup) + (int)(threadIdx.x / kEqGroup);
+    if (c >= d.nc) return;                      // whole groups; shuffles stay inside a group
+    const double *Wc = d.W[par] + 4 * c;
+    const double W[4] = {Wc[0], Wc[1], Wc[2], Wc[3]};
+    const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho;
+    const double th = (2.0 / 3.0) * (W[3] / rho - 0.5 * (u1 * u1 + u2 * u2));
+    double P[4] = {rho, u1, u2, th}, M[16];
+    eq_conservative<kEqGroup>(d, W, P, with_M ? M : nullptr);
+    if (threadIdx.x % kEqGroup != 0) return;
+    double *o = d.mstate + kEqState * c;
+#pragma unroll
+    for (int a = 0; a < 4; a++) o[a] = P[a];
+    if (with_M) {
+#pragma unroll
+        for (int q = 0; q < 16; q++) o[4 + q] = M[q];
+    }
+}
+
+hipError_t launch_eq_params(const DevSolve &d, int par, int with_M, hipStream_t st)
+{
+    if (!d.mstate || !d.equil) return hipErrorInvalidValue;
+    constexpr int per_block = kBlock / kEqGroup;
+    hipLaunchKernelGGL(k_eq_params, dim3((d.nc + per_block - 1) / per_block), dim3(kBlock), 0, st, d, par, with_M);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_correct_moments(const DevSolve &d, int par, const double *z, hipStream_t st)
+{
+    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_adjoint_correct_moments<T>, dim3(xcd_grid(d.np)), dim3(kPatchBlock), 0,
+                                             st, d, par, z));
     return hipGetLastError();
 }
 

@@ -3,19 +3,19 @@
 // Sec. 3.1 accelerates the kinetic iterations with "prediction" solutions of
 // approximate macroscopic equations from the continuum limit.  Every K
 // sweeps (first-order scheme):
-//   1. k_macro_state: each cell's equilibrium parameters P' and dP'/dW (the
-//      pointwise ones, or the discrete-conservative ones by Newton);
-//   2. k_macro_assemble: the moments r of the kinetic residual of eq.
-//      (numerpr_gov) at the current f, and the linearised macroscopic system
-//      A dW = -r with A the moments of the scheme's upwind transport of
+//   1. k_eq_params: each cell's discrete-conservative equilibrium
+//      parameters P' and dP'/dW by Newton;
+//   2. k_macro_resid, k_macro_blocks: the moments r of the kinetic residual
+//      of eq. (numerpr_gov) at the current f, and the linearised macroscopic
+//      system A dW = -r with A the moments of the scheme's upwind transport of
 //      equilibrium perturbations: the outflow faces carry the cell's own
 //      dg/dW, the inflow faces the neighbour's, the far field nothing and
 //      the wall face the diffuse value's response gbar dF_l; plus the
 //      pseudo-time term (|u| + c) sum_q |S_q| / CFL (CFL 1000) on the
 //      diagonal, which keeps near-singular modes of the steady operator (a
 //      slow wake, a sonic region) from being amplified; stored as the
-//      inverse of each cell's own block and the blocks of its four face
-//      neighbours;
+//      inverse of each cell's own block and the outflow block of each face
+//      (the neighbours' inflow blocks);
 //   3. k_macro_rbgs: red-black block Gauss-Seidel half steps from dW = 0
 //      (colour (i + j) % 2 in mesh numbering, each half step reading one
 //      array and writing the other);
@@ -33,52 +33,32 @@
 
 namespace dvm {
 
-constexpr int kMacroState = 20;   // doubles per cell: P' (4), dP'/dW (16, row = parameter)
 constexpr double kMacroCFL = 1000.0;
-
-// ---------------------------------------------------------------------------
-// per-cell equilibrium parameters and their derivative, one wave per cell
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_macro_state(DevSolve d, int par)
-{
-    const int c = blockIdx.x * (kBlock / kWave) + (int)(threadIdx.x / kWave);
-    if (c >= d.nc) return;                      // whole waves; the kernel has no block barrier
-    const double *W = d.W[par] + 4 * c;
-    const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho, E = W[3] / rho;
-    const double th = (2.0 / 3.0) * (E - 0.5 * (u1 * u1 + u2 * u2));
-    double P[4] = {rho, u1, u2, th}, M[16];
-    if (d.equil) {
-        const double Wv[4] = {W[0], W[1], W[2], W[3]};
-        eq_conservative(d, Wv, P, M);
-    } else {
-        const double ir = 1.0 / rho, k23 = 2.0 / 3.0;
-        const double J[16] = {1.0, 0.0, 0.0, 0.0, -u1 * ir, ir, 0.0, 0.0, -u2 * ir, 0.0, ir, 0.0,
-                              k23 * (u1 * u1 + u2 * u2 - E) * ir, -k23 * u1 * ir, -k23 * u2 * ir, k23 * ir};
-#pragma unroll
-        for (int q = 0; q < 16; q++) M[q] = J[q];
-    }
-    if (threadIdx.x % kWave != 0) return;
-    double *o = d.mstate + kMacroState * c;
-#pragma unroll
-    for (int a = 0; a < 4; a++) o[a] = P[a];
-#pragma unroll
-    for (int q = 0; q < 16; q++) o[4 + q] = M[q];
-}
 
 // derivatives of (g1, g2) with respect to the equilibrium parameters
 // (rho, u1, u2, theta) at velocity (v1, v2), with g1 = kap X Y from the tables
-__device__ __forceinline__ void dg_dP(double kap, const double *P, double X, double Y, double v1, double v2,
-                                      double &g1, double &g2, double (&d1)[4], double (&d2)[4])
+// (ir = 1/rho, it = 1/theta, ih = 1/(2 theta^2) of the cell, computed once)
+struct DgCell {
+    double kap, u1, u2, hth, ir, it, ih;
+};
+
+__device__ __forceinline__ DgCell dg_cell(const double *P)
 {
-    const double th = P[3], c1 = v1 - P[1], c2 = v2 - P[2];
-    g1 = kap * X * Y;
-    g2 = 0.5 * th * g1;
-    d1[0] = g1 / P[0];
-    d1[1] = g1 * c1 / th;
-    d1[2] = g1 * c2 / th;
-    d1[3] = g1 * ((c1 * c1 + c2 * c2) / (2.0 * th * th) - 1.0 / th);
+    return {P[0] / (2.0 * kPi * P[3]), P[1], P[2], 0.5 * P[3], 1.0 / P[0], 1.0 / P[3], 1.0 / (2.0 * P[3] * P[3])};
+}
+
+__device__ __forceinline__ void dg_dP(const DgCell &q, double X, double Y, double v1, double v2, double &g1,
+                                      double &g2, double (&d1)[4], double (&d2)[4])
+{
+    const double c1 = v1 - q.u1, c2 = v2 - q.u2;
+    g1 = q.kap * X * Y;
+    g2 = q.hth * g1;
+    d1[0] = g1 * q.ir;
+    d1[1] = g1 * c1 * q.it;
+    d1[2] = g1 * c2 * q.it;
+    d1[3] = g1 * ((c1 * c1 + c2 * c2) * q.ih - q.it);
 #pragma unroll
-    for (int p = 0; p < 4; p++) d2[p] = 0.5 * th * d1[p];
+    for (int p = 0; p < 4; p++) d2[p] = q.hth * d1[p];
     d2[3] += 0.5 * g1;
 }
 
@@ -98,28 +78,29 @@ __device__ __forceinline__ void macro_tables(const DevSolve &d, const double *P,
 }
 
 // ---------------------------------------------------------------------------
-// assembly, one wave per cell; every wave of a workgroup runs the same
-// passes (the table exchange between passes is a workgroup barrier)
+// r_c, the moments of the kinetic residual at the current f, one wave per
+// cell: the own row, the upwind neighbours' rows (far-field table, diffuse
+// wall), the collision part V/tau (f - g).  A workgroup per sweep patch in
+// the sweeps' XCD order, so neighbour rows are read from the XCD's own L2.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
+__global__ __launch_bounds__(kPatchCells * kWave) void k_macro_resid(DevSolve d, int par)
 {
     using T2 = typename Vec2<T>::type;
-    __shared__ double tabX[kBlock / kWave][kMaxN1D], tabY[kBlock / kWave][kMaxN1D];
+    __shared__ double tabX[kPatchCells][kMaxN1D], tabY[kPatchCells][kMaxN1D];
+    const int p = xcd_item(d.np, blockIdx.x);
+    if (p < 0) return;                          // whole workgroups
     const int w = (int)(threadIdx.x / kWave), lane = threadIdx.x % kWave;
-    const int c0 = blockIdx.x * (kBlock / kWave) + w;
-    const bool act = c0 < d.nc;
-    const int c = act ? c0 : d.nc - 1;
+    const int c0 = d.patch[p], cnt = d.patch[p + 1] - c0;
+    const bool act = w < cnt;                   // idle waves of a partial patch only join the barrier
+    const int c = c0 + (act ? w : 0);
     const int nv = d.nv, n1 = d.n1;
     const T2 *__restrict__ f = static_cast<const T2 *>(d.f[par]);
     const T2 *__restrict__ fd = static_cast<const T2 *>(d.fd);
     const T *__restrict__ gM = static_cast<const T *>(d.gM);
-    const double *ms = d.mstate + kMacroState * c;
-    double P[4];
-#pragma unroll
-    for (int a = 0; a < 4; a++) P[a] = ms[a];
-    const double kap = P[0] / (2.0 * kPi * P[3]);
-    // 1/tau of the cell's own rho and theta
+    const double *ms = d.mstate + kEqState * c;
+    const double P[4] = {ms[0], ms[1], ms[2], ms[3]};
+    const double kap = P[0] / (2.0 * kPi * P[3]), th2 = 0.5 * P[3];
     const double *W = d.W[par] + 4 * c;
     const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho;
     const double th = (2.0 / 3.0) * (W[3] / rho - 0.5 * (u1 * u1 + u2 * u2));
@@ -134,26 +115,19 @@ __global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
     }
     const int wl = nb[0] <= -2 ? -2 - nb[0] : -1;
     const double Fw = wl >= 0 ? d.F[par][wl] : 0.0, Dw = wl >= 0 ? d.D[wl] : 1.0;
-    const double n1w = wl >= 0 ? d.wall_n[2 * wl] : 0.0, n2w = wl >= 0 ? d.wall_n[2 * wl + 1] : 0.0;
     const double thw2 = 0.5 * d.theta_w;
     const size_t row = (size_t)c * nv;
-
-    // pass 0: r, the cell's own block (in dg/dP' form), the wall coupling
     macro_tables(d, P, tabX[w], tabY[w]);
     __syncthreads();
-    double acc[28];
-#pragma unroll
-    for (int i = 0; i < 28; i++) acc[i] = 0.0;
-    double *r = acc, *Dp = acc + 4, *wall1 = acc + 20, *dFp = acc + 24;
+    double r[4] = {0, 0, 0, 0};
     for (int k = lane; k < nv; k += kWave) {
         const int a = k % n1, b = k / n1;
         const double v1 = d.vx[a], v2 = d.vy[b], wt = d.wx[a] * d.wy[b];
         const double psi[4] = {1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2)};
-        double g1, g2, d1[4], d2[4];
-        dg_dP(kap, P, tabX[w][a], tabY[w][b], v1, v2, g1, g2, d1, d2);
+        const double g1 = kap * tabX[w][a] * tabY[w][b], g2 = th2 * g1;
         const T2 fk = f[row + k];
         const double f1 = (double)fk.x, f2 = (double)fk.y;
-        const double e1 = Vt * (f1 - g1), e2 = Vt * (f2 - g2);
+        double in1 = Vt * (f1 - g1), in2 = Vt * (f2 - g2);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const double s = v1 * Sx[q] + v2 * Sy[q];
@@ -161,10 +135,6 @@ __global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
             if (s > 0) {
                 a1 = f1;
                 a2 = f2;
-#pragma unroll
-                for (int x = 0; x < 4; x++)
-#pragma unroll
-                    for (int p = 0; p < 4; p++) Dp[4 * x + p] += wt * s * (psi[x] * d1[p] + (x == 3 ? d2[p] : 0.0));
             } else if (nb[q] >= 0) {
                 const T2 u = f[(size_t)nb[q] * nv + k];
                 a1 = (double)u.x;
@@ -174,18 +144,124 @@ __global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
                 a1 = (double)u.x;
                 a2 = (double)u.y;
             } else {
-                const double gb1 = (double)gM[k] / Dw, gb2 = thw2 * gb1;
+                const double gb1 = (double)gM[k] / Dw;
                 a1 = Fw * gb1;
-                a2 = Fw * gb2;
+                a2 = Fw * (thw2 * gb1);
+            }
+            in1 += s * a1;
+            in2 += s * a2;
+        }
+#pragma unroll
+        for (int x = 0; x < 4; x++) r[x] += wt * (psi[x] * in1 + (x == 3 ? in2 : 0.0));
+    }
+    wave_sum<4>(r);
+    if (act && lane == 0) {
+#pragma unroll
+        for (int x = 0; x < 4; x++) d.mr[4 * c + x] = r[x];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the macroscopic blocks of each cell, two waves per cell (faces 0-1 and
+// 2-3), no distribution read: each face q gets its outflow block
+//   B_cq = sum_{k: v.S_q > 0} w (v.S_q) Psi_k dg_c,k/dW,
+// and the cell's own block is D_c = sum_q B_cq + wall1 dF + lam I (wall1 dF:
+// the diffuse wall's re-emission of the outgoing flux; lam the pseudo-time
+// term).  The inflow block of the neighbour n across face q is -B_nq' (q'
+// the face of n that faces c: S_nq' = -S_cq, so n's outflow half-space
+// through q' is c's inflow half-space through q and the sums agree term by
+// term).  The Gauss-Seidel steps read the neighbours' B instead of a
+// separate off-diagonal table.
+// ---------------------------------------------------------------------------
+constexpr int kBlkCells = kBlock / (2 * kWave);
+
+__global__ __launch_bounds__(kBlock) void k_macro_blocks(DevSolve d, int par)
+{
+    __shared__ double tabX[kBlkCells][kMaxN1D], tabY[kBlkCells][kMaxN1D];
+    __shared__ double vx[kMaxN1D], vy[kMaxN1D], wx[kMaxN1D], wy[kMaxN1D];
+    __shared__ double Dpart[kBlkCells][2][16];
+    const int wv = (int)(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+    const int cl = wv >> 1, h = wv & 1;          // cell of the workgroup, half (faces 2h, 2h+1)
+    const int c0 = blockIdx.x * kBlkCells + cl;
+    const bool act = c0 < d.nc;                 // idle waves of the last workgroup only join the barriers
+    const int c = act ? c0 : d.nc - 1;
+    const int nv = d.nv, n1 = d.n1, n2 = d.n2;
+    const double *ms = d.mstate + kEqState * c;
+    const double P[4] = {ms[0], ms[1], ms[2], ms[3]};
+    const DgCell qc = dg_cell(P);
+    const double hh = 0.5 / P[3];
+    for (int i = threadIdx.x; i < n1; i += kBlock) {
+        vx[i] = d.vx[i];
+        wx[i] = d.wx[i];
+    }
+    for (int i = threadIdx.x; i < n2; i += kBlock) {
+        vy[i] = d.vy[i];
+        wy[i] = d.wy[i];
+    }
+    // the cell's 1-D factor tables: X by the first wave of the cell, Y by the second
+    if (h == 0)
+        for (int i = lane; i < n1; i += kWave) {
+            const double e = d.vx[i] - P[1];
+            tabX[cl][i] = exp(-e * e * hh);
+        }
+    else
+        for (int i = lane; i < n2; i += kWave) {
+            const double e = d.vy[i] - P[2];
+            tabY[cl][i] = exp(-e * e * hh);
+        }
+    double Sx[2], Sy[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+        Sx[t] = d.S[8 * c + 2 * (2 * h + t)];
+        Sy[t] = d.S[8 * c + 2 * (2 * h + t) + 1];
+    }
+    const int nb0 = d.nbr[4 * c];
+    const int wl = (h == 0 && nb0 <= -2) ? -2 - nb0 : -1;     // the wall face is face 0
+    const double Dw = wl >= 0 ? d.D[wl] : 1.0;
+    const double n1w = wl >= 0 ? d.wall_n[2 * wl] : 0.0, n2w = wl >= 0 ? d.wall_n[2 * wl + 1] : 0.0;
+    const double thw2 = 0.5 * d.theta_w;
+    const double *gMd = static_cast<const double *>(d.gM);
+    const float *gMf = static_cast<const float *>(d.gM);
+    __syncthreads();
+    // acc: B of the two faces in dg/dP form (2 x 16), wall1 (4), dF in dg/dP form (4)
+    double acc[40];
+#pragma unroll
+    for (int i = 0; i < 40; i++) acc[i] = 0.0;
+    double *Bp = acc, *wall1 = acc + 32, *dFp = acc + 36;
+    for (int k = lane; k < nv; k += kWave) {
+        const int a = k % n1, b = k / n1;
+        const double v1 = vx[a], v2 = vy[b], wt = wx[a] * wy[b];
+        const double psi[4] = {1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2)};
+        double g1, g2, d1[4], d2[4];
+        dg_dP(qc, tabX[cl][a], tabY[cl][b], v1, v2, g1, g2, d1, d2);
+        const double s0 = v1 * Sx[0] + v2 * Sy[0], s1 = v1 * Sx[1] + v2 * Sy[1];
+        if (s0 > 0 || s1 > 0) {
+            // Psi_x dg/dP_p, the (x == 3) row with the second distribution's term
+            double pd[16];
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int p = 0; p < 4; p++) pd[4 * x + p] = psi[x] * d1[p] + (x == 3 ? d2[p] : 0.0);
+            if (s0 > 0) {
+                const double ws = wt * s0;
+#pragma unroll
+                for (int i = 0; i < 16; i++) Bp[i] += ws * pd[i];
+            }
+            if (s1 > 0) {
+                const double ws = wt * s1;
+#pragma unroll
+                for (int i = 0; i < 16; i++) Bp[16 + i] += ws * pd[i];
+            }
+        }
+        if (wl >= 0) {
+            // the wall face (face 0): where it is inflow, the diffuse value's
+            // response; the outgoing flux's response dF
+            const double s = v1 * Sx[0] + v2 * Sy[0];
+            if (!(s > 0)) {
+                const double gb1 = (d.mixed ? (double)gMf[k] : gMd[k]) / Dw, gb2 = thw2 * gb1;
 #pragma unroll
                 for (int x = 0; x < 4; x++) wall1[x] += wt * s * (psi[x] * gb1 + (x == 3 ? gb2 : 0.0));
             }
-#pragma unroll
-            for (int x = 0; x < 4; x++) r[x] += wt * s * (psi[x] * a1 + (x == 3 ? a2 : 0.0));
-        }
-#pragma unroll
-        for (int x = 0; x < 4; x++) r[x] += wt * (psi[x] * e1 + (x == 3 ? e2 : 0.0));
-        if (wl >= 0) {
             const double vn = v1 * n1w + v2 * n2w;
             if (vn > 0) {
 #pragma unroll
@@ -193,91 +269,76 @@ __global__ __launch_bounds__(kBlock) void k_macro_assemble(DevSolve d, int par)
             }
         }
     }
-    wave_sum<28>(acc);
+    wave_sum<40>(acc);
     const double *M = ms + 4;
     if (act && lane == 0) {
-        // D = Dp M + wall1 (dFp M)
-        double Dm[4][4], dF[4];
+        // this half's faces: B_q = Bp_q M into the table, and their share of D
+        double Dm[16];
 #pragma unroll
-        for (int m = 0; m < 4; m++) {
-            dF[m] = ((dFp[0] * M[m] + dFp[1] * M[4 + m]) + dFp[2] * M[8 + m]) + dFp[3] * M[12 + m];
+        for (int i = 0; i < 16; i++) Dm[i] = 0.0;
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            const double *Bq = Bp + 16 * t;
+            double *Bo = d.mO + 64 * c + 16 * (2 * h + t);
 #pragma unroll
             for (int x = 0; x < 4; x++)
-                Dm[x][m] = ((Dp[4 * x] * M[m] + Dp[4 * x + 1] * M[4 + m]) + Dp[4 * x + 2] * M[8 + m]) +
-                           Dp[4 * x + 3] * M[12 + m];
+#pragma unroll
+                for (int m = 0; m < 4; m++) {
+                    const double v = ((Bq[4 * x] * M[m] + Bq[4 * x + 1] * M[4 + m]) + Bq[4 * x + 2] * M[8 + m]) +
+                                     Bq[4 * x + 3] * M[12 + m];
+                    Bo[4 * x + m] = v;
+                    Dm[4 * x + m] += v;
+                }
         }
+        if (wl >= 0) {
 #pragma unroll
-        for (int x = 0; x < 4; x++)
+            for (int m = 0; m < 4; m++) {
+                const double dF = ((dFp[0] * M[m] + dFp[1] * M[4 + m]) + dFp[2] * M[8 + m]) + dFp[3] * M[12 + m];
 #pragma unroll
-            for (int m = 0; m < 4; m++) Dm[x][m] += wall1[x] * dF[m];
-        // pseudo-time term V/dt of the cell
-        double sS = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; q++) sS += hypot(Sx[q], Sy[q]);
-        const double lam = (sqrt(u1 * u1 + u2 * u2) + sqrt(5.0 / 3.0 * th)) * sS / kMacroCFL;
-#pragma unroll
-        for (int x = 0; x < 4; x++) Dm[x][x] += lam;
-        double *Di = d.mDinv + 16 * c;
-#pragma unroll
-        for (int b2 = 0; b2 < 4; b2++) {
-            double A[4][4], e[4] = {0, 0, 0, 0}, x[4];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < 4; j++) A[i][j] = Dm[i][j];
-            e[b2] = 1.0;
-            solve4(A, e, x);
-#pragma unroll
-            for (int a2 = 0; a2 < 4; a2++) Di[4 * a2 + b2] = x[a2];
-        }
-#pragma unroll
-        for (int x = 0; x < 4; x++) d.mr[4 * c + x] = r[x];
-    }
-
-    // passes 1-4: the blocks of the face neighbours (inflow faces, the
-    // neighbour's equilibrium)
-    for (int q = 0; q < 4; q++) {
-        const int n = nb[q];
-        const double *mn = d.mstate + kMacroState * (n >= 0 ? n : c);
-        double Pn[4];
-#pragma unroll
-        for (int a = 0; a < 4; a++) Pn[a] = mn[a];
-        const double kapn = Pn[0] / (2.0 * kPi * Pn[3]);
-        __syncthreads();                         // the previous pass is done with the tables
-        macro_tables(d, Pn, tabX[w], tabY[w]);
-        __syncthreads();
-        double Op[16];
-#pragma unroll
-        for (int i = 0; i < 16; i++) Op[i] = 0.0;
-        if (n >= 0) {
-            for (int k = lane; k < nv; k += kWave) {
-                const int a = k % n1, b = k / n1;
-                const double v1 = d.vx[a], v2 = d.vy[b];
-                const double s = v1 * Sx[q] + v2 * Sy[q];
-                if (s > 0) continue;
-                const double wt = d.wx[a] * d.wy[b];
-                const double psi[4] = {1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2)};
-                double g1, g2, d1[4], d2[4];
-                dg_dP(kapn, Pn, tabX[w][a], tabY[w][b], v1, v2, g1, g2, d1, d2);
-#pragma unroll
-                for (int x = 0; x < 4; x++)
-#pragma unroll
-                    for (int p = 0; p < 4; p++) Op[4 * x + p] += wt * s * (psi[x] * d1[p] + (x == 3 ? d2[p] : 0.0));
+                for (int x = 0; x < 4; x++) Dm[4 * x + m] += wall1[x] * dF;
             }
         }
-        wave_sum<16>(Op);
-        if (act && lane == 0) {
-            const double *Mn = mn + 4;
-            double *Oq = d.mO + 64 * c + 16 * q;
 #pragma unroll
-            for (int x = 0; x < 4; x++)
-#pragma unroll
-                for (int m = 0; m < 4; m++)
-                    Oq[4 * x + m] = n >= 0 ? ((Op[4 * x] * Mn[m] + Op[4 * x + 1] * Mn[4 + m]) + Op[4 * x + 2] * Mn[8 + m]) +
-                                                 Op[4 * x + 3] * Mn[12 + m]
-                                           : 0.0;
-        }
+        for (int i = 0; i < 16; i++) Dpart[cl][h][i] = Dm[i];
     }
+    __syncthreads();
+    if (!act || h != 0 || lane != 0) return;
+    // D = both halves + the pseudo-time term V/dt of the cell, inverted
+    const double *W = d.W[par] + 4 * c;
+    const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho;
+    const double th = (2.0 / 3.0) * (W[3] / rho - 0.5 * (u1 * u1 + u2 * u2));
+    double sS = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) sS += hypot(d.S[8 * c + 2 * q], d.S[8 * c + 2 * q + 1]);
+    const double lam = (sqrt(u1 * u1 + u2 * u2) + sqrt(5.0 / 3.0 * th)) * sS / kMacroCFL;
+    double Dm[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int m = 0; m < 4; m++) Dm[x][m] = Dpart[cl][0][4 * x + m] + Dpart[cl][1][4 * x + m] + (x == m ? lam : 0.0);
+    double *Di = d.mDinv + 16 * c;
+#pragma unroll
+    for (int b2 = 0; b2 < 4; b2++) {
+        double A[4][4], e[4] = {0, 0, 0, 0}, x[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) A[i][j] = Dm[i][j];
+        e[b2] = 1.0;
+        solve4(A, e, x);
+#pragma unroll
+        for (int a2 = 0; a2 < 4; a2++) Di[4 * a2 + b2] = x[a2];
+    }
+}
+
+// the face of cell n that faces cell c (n a face neighbour of c)
+__device__ __forceinline__ int back_face(const DevSolve &d, int n, int c)
+{
+    int qb = 0;
+#pragma unroll
+    for (int t = 3; t >= 0; t--)
+        if (d.nbr[4 * n + t] == c) qb = t;
+    return qb;
 }
 
 // ---------------------------------------------------------------------------
@@ -301,11 +362,12 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, c
     for (int q = 0; q < 4; q++) {
         const int n = d.nbr[4 * c + q];
         if (n < 0) continue;
-        const double *O = d.mO + 64 * c + 16 * q;
+        // the inflow block of n across face q is -B_nq'
+        const double *B = d.mO + 64 * n + 16 * back_face(d, n, c);
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
-            for (int e = 0; e < 4; e++) b[a] -= O[4 * a + e] * src[4 * n + e];
+            for (int e = 0; e < 4; e++) b[a] += B[4 * a + e] * src[4 * n + e];
     }
     const double *Di = d.mDinv + 16 * c;
 #pragma unroll
@@ -348,14 +410,23 @@ __global__ __launch_bounds__(kBlock) void k_macro_apply(DevSolve d, int par, con
     for (int a = 0; a < 4; a++) W[a] += fac * x[4 * c + a];
 }
 
+// P' and dP'/dW of W[par], then the blocks; with_r: also the residual's moments
+static hipError_t macro_system(const DevSolve &d, int par, bool with_r, hipStream_t st)
+{
+    if (hipError_t e = launch_eq_params(d, par, 1, st)) return e;
+    if (with_r) {
+        DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_resid<T>, dim3(xcd_grid(d.np)), dim3(kPatchCells * kWave), 0,
+                                                 st, d, par));
+        if (hipError_t e = hipGetLastError()) return e;
+    }
+    hipLaunchKernelGGL(k_macro_blocks, dim3((d.nc + kBlkCells - 1) / kBlkCells), dim3(kBlock), 0, st, d, par);
+    return hipGetLastError();
+}
+
 hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream_t st)
 {
-    constexpr int per_block = kBlock / kWave;
-    const int gw = (d.nc + per_block - 1) / per_block, gt = (d.nc + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_macro_state, dim3(gw), dim3(kBlock), 0, st, d, par);
-    if (hipError_t e = hipGetLastError()) return e;
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_assemble<T>, dim3(gw), dim3(kBlock), 0, st, d, par));
-    if (hipError_t e = hipGetLastError()) return e;
+    const int gt = (d.nc + kBlock - 1) / kBlock;
+    if (hipError_t e = macro_system(d, par, true, st)) return e;
     hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mx[0], 4 * d.nc);
     if (hipError_t e = hipGetLastError()) return e;
     for (int it = 0; it < inner; it++) {
@@ -379,38 +450,13 @@ hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream
 //      moments the two sweeps left (What and rho_tau are linear in phi):
 //      y = V (What_s - What) / tau - V (1/tau dtau/dW) (rho_tau,s - rho_tau);
 //   2. k_macro_rbgs_adj: z = L^T y, the Gauss-Seidel half steps transposed
-//      in reverse order (the neighbour blocks transposed once, at the
-//      adjoint's start, by k_macro_transpose);
-//   3. k_macro_adj_correct: phi_s -= (z . Psi, z_3), then the adjoint
-//      moments of the corrected phi (k_adjoint_moments).
+//      in reverse order;
+//   3. k_adjoint_correct_moments: phi_s -= (z . Psi, z_3) and the adjoint
+//      moments of the corrected phi, in one pass.
 // The accelerated adjoint cycle then has the eigenvalues of the primal's,
 // and the correction vanishes with the sweep's change (the adjoint solution
 // is the plain iteration's).
 // ---------------------------------------------------------------------------
-
-// the transposed neighbour blocks: OT[c][q] = O[n][q']^T for the face q' of
-// n = nbr[c][q] that faces c, a thread per cell
-__global__ __launch_bounds__(kBlock) void k_macro_transpose(DevSolve d)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.nc) return;
-    for (int q = 0; q < 4; q++) {
-        double *o = d.mOT + 64 * c + 16 * q;
-        const int n = d.nbr[4 * c + q];
-        int qb = -1;
-        if (n >= 0)
-            for (int t = 0; t < 4; t++)
-                if (d.nbr[4 * n + t] == c) {
-                    qb = t;
-                    break;
-                }
-        const double *src = d.mO + 64 * (size_t)(n >= 0 ? n : c) + 16 * (qb >= 0 ? qb : 0);
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int b = 0; b < 4; b++) o[4 * a + b] = qb >= 0 ? src[4 * b + a] : 0.0;
-    }
-}
 
 // y_c = H_c^T (phi_s - phi) from the adjoint moments of phi_s (aW[pnew]) and
 // of phi (aW[pnew ^ 1]), written as the seed of the transposed solve
@@ -435,8 +481,8 @@ __device__ __forceinline__ bool macro_colour(const DevSolve &d, int c, int colou
 // cell: the forward step set x_c = Dinv_c (-r_c - sum_q O_cq src_nbr) on its
 // colour and copied the rest; given the adjoint ob of its output, t_c =
 // -Dinv_c^T ob_c joins rbar on the colour, and the adjoint of its input is
-// ib_m = (m off the colour: ob_m) + sum_q OT_mq t_nbr (neighbours on the
-// colour)
+// ib_m = (m off the colour: ob_m) + sum_q O_nq'^T t_n over neighbours n on
+// the colour, where O_nq' (n's inflow block from m) is -B_mq
 __global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colour, const double *__restrict__ ob,
                                                            double *__restrict__ ib, double *__restrict__ rbar)
 {
@@ -458,11 +504,11 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colou
             for (int e = 0; e < 4; e++) s += Di[4 * e + a] * ob[4 * n + e];
             t[a] = -s;
         }
-        const double *OT = d.mOT + 64 * m + 16 * q;
+        const double *B = d.mO + 64 * m + 16 * q;
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
-            for (int e = 0; e < 4; e++) acc[a] += OT[4 * a + e] * t[e];
+            for (int e = 0; e < 4; e++) acc[a] -= B[4 * e + a] * t[e];
     }
 #pragma unroll
     for (int a = 0; a < 4; a++) ib[4 * m + a] = acc[a];
@@ -478,35 +524,9 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colou
     }
 }
 
-// phi[pnew] -= (z . Psi, z_3), a thread per (cell, velocity)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_macro_adj_correct(DevSolve d, int pnew, const double *__restrict__ z)
-{
-    using T2 = typename Vec2<T>::type;
-    T2 *__restrict__ ph = static_cast<T2 *>(d.phi[pnew]);
-    const size_t n = (size_t)d.nc * d.nv, stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int c = (int)(i / d.nv), k = (int)(i % d.nv);
-        const double v1 = d.vx[k % d.n1], v2 = d.vy[k / d.n1];
-        const double *zc = z + 4 * c;
-        T2 p = ph[i];
-        const double s1 = ((zc[0] + zc[1] * v1) + zc[2] * v2) + zc[3] * (0.5 * (v1 * v1 + v2 * v2));
-        p.x = (T)((double)p.x - s1);
-        p.y = (T)((double)p.y - zc[3]);
-        ph[i] = p;
-    }
-}
-
 hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t st)
 {
-    constexpr int per_block = kBlock / kWave;
-    const int gw = (d.nc + per_block - 1) / per_block, gt = (d.nc + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_macro_state, dim3(gw), dim3(kBlock), 0, st, d, fpar);
-    if (hipError_t e = hipGetLastError()) return e;
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_assemble<T>, dim3(gw), dim3(kBlock), 0, st, d, fpar));
-    if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_macro_transpose, dim3(gt), dim3(kBlock), 0, st, d);
-    return hipGetLastError();
+    return macro_system(d, fpar, false, st);
 }
 
 hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, hipStream_t st)
@@ -522,11 +542,8 @@ hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, 
         hipLaunchKernelGGL(k_macro_rbgs_adj, dim3(gt), dim3(kBlock), 0, st, d, 0, d.mx[1], d.mx[0], d.mr);
         if (hipError_t e = hipGetLastError()) return e;
     }
-    const size_t pairs = (size_t)d.nc * d.nv;
-    const int gp = (int)std::min<size_t>((pairs + kBlock - 1) / kBlock, 16384);
-    DVM_DISPATCH(d.mixed, hipLaunchKernelGGL(k_macro_adj_correct<T>, dim3(gp), dim3(kBlock), 0, st, d, pnew, d.mr));
-    if (hipError_t e = hipGetLastError()) return e;
-    return launch_adjoint_moments(d, pnew, st);
+    // phi -= (z . Psi, z_3) and the adjoint moments of the result, one pass
+    return launch_adjoint_correct_moments(d, pnew, d.mr, st);
 }
 
 }  // namespace dvm

@@ -106,6 +106,22 @@ def test_workspace_bytes_exact_and_monotone():
     assert dvm.lib().dvm_batch_work_bytes(3, 1000) > 0
 
 
+def test_equilibrium_and_prediction_workspace():
+    """The conservative equilibrium keeps P' and dP'/dW per cell (20
+    doubles); the prediction adds r, D^-1, the four face blocks and two
+    Gauss-Seidel arrays (92 doubles per cell).  Regression: setting the
+    equilibrium alone must grow the workspace (its parameter buffer was
+    laid out only with the prediction)."""
+    wl = I.tiny_naca()
+    m, g = dvm.Mesh.from_grid(wl.grid), dvm.VGrid.from_spec(wl.vgrid)
+    base = dvm.Solver(m, g, 0.5, 0.8, bind=False)
+    cons = dvm.Solver(m, g, 0.5, 0.8, bind=False, equilibrium=dvm.EQ_CONSERVATIVE)
+    acc = dvm.Solver(m, g, 0.5, 0.8, bind=False, equilibrium=dvm.EQ_CONSERVATIVE, accelerate=(5, 20))
+    nc = base.nc
+    assert 20 * 8 * nc <= cons.workspace_bytes - base.workspace_bytes <= 20 * 8 * nc + 256
+    assert 92 * 8 * nc <= acc.workspace_bytes - cons.workspace_bytes <= 92 * 8 * nc + 6 * 256
+
+
 def test_second_order_scheme_setting_and_workspace():
     """dvm_solver_set_scheme checks its arguments and grows the workspace by
     the second-order buffers (slopes, correction, limiter factors, face

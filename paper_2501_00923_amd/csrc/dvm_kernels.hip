@@ -402,12 +402,14 @@ struct AdjCell {
 // adjoint_macdefines, formula_adjointbgk): phi . dg/dP for P = (rho, u1, u2,
 // theta) summed as A0..A4, the rho_tau sum R and the wall multiplier sum Pw
 // (incoming velocities of the wall face).  g1, g2: the frozen Maxwellian at
-// this velocity; gMk: g_M1(1, 0, theta_w) there.  Shared by the adjoint
-// sweep's epilogue and k_adjoint_moments, so both give the same bits.
+// this velocity; gM[k]: g_M1(1, 0, theta_w) there, read only in wall cells.
+// Shared by the adjoint sweep's epilogue and k_adjoint_moments, so both give
+// the same bits.
+template <typename T>
 __device__ __forceinline__ void adjoint_terms(double &A0, double &A1, double &A2, double &A3, double &A4, double &R,
                                               double &Pw, const AdjCell &q, double v1d, double v2d, double wt,
                                               double g1, double g2, double p1, double p2, double fs1, double fs2,
-                                              double gMk)
+                                              const T *__restrict__ gM, int k)
 {
     const double qq = fma(q.hth, p2, p1);
     const double c1 = v1d - q.u1, c2 = v2d - q.u2;
@@ -420,7 +422,7 @@ __device__ __forceinline__ void adjoint_terms(double &A0, double &A1, double &A2
     R = fma(wt, fma(p1, g1 - fs1, p2 * (g2 - fs2)), R);
     if (q.wl >= 0) {
         const double s0 = v1d * q.S0x + v2d * q.S0y;
-        if (s0 <= 0) Pw += wt * s0 * gMk * ((p1 + mJ_of(q.obj, v1d, v2d)) + q.thw2 * p2);
+        if (s0 <= 0) Pw += wt * s0 * (double)gM[k] * ((p1 + mJ_of(q.obj, v1d, v2d)) + q.thw2 * p2);
     }
 }
 
@@ -553,8 +555,7 @@ __device__ __forceinline__ void adjoint_patch(const DevSolve &d, int p, int par)
         const double p1 = (double)r.x, p2 = (double)r.y;
         const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
         const double g2 = (double)(th2 * (T)g1);
-        adjoint_terms(A0, A1, A2, A3, A4, R, Pw, cq, v1d, v2d, wt, g1, g2, p1, p2, (double)fs.x, (double)fs.y,
-                      wl >= 0 ? (double)gM[k] : 0.0);
+        adjoint_terms(A0, A1, A2, A3, A4, R, Pw, cq, v1d, v2d, wt, g1, g2, p1, p2, (double)fs.x, (double)fs.y, gM, k);
         const double e1 = p1 - (double)old.x, e2 = p2 - (double)old.y;
         dn = fma(wt, fma(e1, e1, e2 * e2), dn);
         dd = fma(wt, fma(p1, p1, p2 * p2), dd);
@@ -743,7 +744,7 @@ __device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, 
         const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
         const double g2 = (double)(th2 * (T)g1);
         adjoint_terms(A0, A1, A2, A3, A4, R, Pw, cq, v1d, v2d, wt, g1, g2, (double)r.x, (double)r.y, (double)fs.x,
-                      (double)fs.y, wl >= 0 ? (double)gM[k] : 0.0);
+                      (double)fs.y, gM, k);
     };
     if (act) {
         if (pair_velocities<T>(n1)) {

@@ -33,7 +33,10 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
 # the sweep and second-order kernels, their layout constants and the host-built sweep order
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2501_00923_amd", "csrc", f)
                for f in ("dvm_kernels.hip", "dvm_so.hip", "dvm_device.h", "dvm_internal.h", "dvm_host.cpp")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_naca0012_c256x128_v48_traffic.json")
+# scaled FETCH_SIZE + WRITE_SIZE per launch of the sweeps, from the counter
+# runs of each workload (bench.py --workload c2 | c3)
+TRAFFIC_FILES = {"c2": os.path.join(ROOT, "profiles", "sweeps_naca0012_c256x128_v48_traffic.json"),
+                 "c3": os.path.join(ROOT, "profiles", "sweeps_naca0012_c256x128_v64sinh_traffic.json")}
 
 
 def kernel_hash() -> str:
@@ -42,6 +45,17 @@ def kernel_hash() -> str:
         with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def load_traffic(key: str) -> dict:
+    """The counted traffic of a workload, or {} when the counters were taken
+    on other kernel code."""
+    path = TRAFFIC_FILES[key]
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        tr = json.load(fh)
+    return tr if tr.get("kernel_sha") == kernel_hash() else {}
 
 
 def bytes_per_update(kind: str, mixed: bool) -> int:
@@ -199,17 +213,23 @@ def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every, accel_below_
 
     def backend(prec):
         return S.GpuBackend(prec, accelerate_below_kn=accel_below_kn, accelerate=accel)
-    cap_run = S.serve(reqs, backend(dvm.MIXED), cfg, realtime=False)
+    def progress(label):
+        def f(res, n):
+            if n % 64 == 0:
+                print(f"[bench] serving {label}: {n}/{n_requests} finished ({time.perf_counter() - t0:.0f} s)",
+                      file=sys.stderr, flush=True)
+        return f
+    cap_run = S.serve(reqs, backend(dvm.MIXED), cfg, realtime=False, on_finish=progress("capacity"))
     capacity = cap_run["solves_per_s"]
     print(f"[bench] serving capacity {capacity:.2f} solves/s ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
     rate = 0.8 * capacity
     stream = I.poisson_stream(n_requests, rate, seed=seed)
-    mix = S.serve(stream, backend(dvm.MIXED), cfg, realtime=True)
+    mix = S.serve(stream, backend(dvm.MIXED), cfg, realtime=True, on_finish=progress("batched mixed"))
     c = mix["converged"]
     print(f"[bench] batched mixed: {c['count']} converged, {c['solves_per_s']:.2f} solves/s p50 {c['p50_ms']:.0f} ms "
           f"p99 {c['p99_ms']:.0f} ms; {mix['notconv']} capped", file=sys.stderr, flush=True)
-    one = S.serve_one_at_a_time(stream, backend(dvm.FP64), cfg, realtime=True)
+    one = S.serve_one_at_a_time(stream, backend(dvm.FP64), cfg, realtime=True, on_finish=progress("one at a time"))
     c = one["converged"]
     print(f"[bench] one-at-a-time fp64: {c['count']} converged, {c['solves_per_s']:.2f} solves/s p50 "
           f"{c['p50_ms']:.0f} ms p99 {c['p99_ms']:.0f} ms; {one['notconv']} capped", file=sys.stderr, flush=True)
@@ -692,6 +712,10 @@ def main():
                     help="requests below this Kn use the conservative equilibrium and the macroscopic prediction "
                          "(0: none)")
     ap.add_argument("--serving-accel-inner", type=int, default=50)
+    ap.add_argument("--workload", choices=("c2", "c3"), default="c2",
+                    help="the timed workload: c2 (the benchmark's: 48x48 Newton-Cotes velocities, Kn 0.1, Ma 0.8) "
+                         "or c3 (64x64 sinh velocities, Kn 0.1, Ma 0.5) on the 256x128 NACA0012 C-grid; c3 is for "
+                         "its counter runs")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 256x128 C-grid with 64x64 sinh velocities (134 M pairs) leg")
     ap.add_argument("--batch-members", type=int, default=24,
@@ -796,7 +820,7 @@ def main():
                                                    max_sweeps=args.opt_max_sweeps, mixed=args.opt_mixed,
                                                    adjoint_tol=args.opt_adjoint_tol)}))
         return
-    wl = I.c2_naca(seed=0)
+    wl = I.c2_naca(seed=0) if args.workload == "c2" else I.c3_naca_sinh(0.1)
     print(f"[bench] {wl.name}: FP64 steps={args.steps} warmup={args.warmup} sweeps={args.sweeps}",
           file=sys.stderr, flush=True)
     r64 = run_gpu(wl, dvm.FP64, args.sweeps, args.steps, args.warmup)
@@ -818,13 +842,8 @@ def main():
     b_adj = bytes_per_update("adjoint", False) * pairs
     b_pri = bytes_per_update("primal", False) * pairs
     achieved = b_adj / t_adj / 1e9
-    traffic, tr = None, {}
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("kernel_sha") != kernel_hash():
-            tr = {}            # counters taken on other kernel code: not this code's traffic
-        traffic = tr.get("adjoint_fp64_bytes_per_launch")
+    tr = load_traffic(args.workload)
+    traffic = tr.get("adjoint_fp64_bytes_per_launch")
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_adjoint_sweep<double>",
@@ -890,8 +909,9 @@ def main():
                                "dtype": "f32 state / f64 moments and limiter"}
             print(f"[bench] second order mixed {r2m['updates_per_s']:.3e} upd/s", file=sys.stderr, flush=True)
     c3 = None
-    if not args.no_c3:
+    if not args.no_c3 and args.workload == "c2":
         wl3 = I.c3_naca_sinh(0.1)
+        tr3 = load_traffic("c3")
         print(f"[bench] {wl3.name}: FP64 and mixed", file=sys.stderr, flush=True)
         r3 = run_gpu(wl3, dvm.FP64, args.sweeps, max(2, args.steps // 2), args.warmup)
         r3m = run_gpu(wl3, dvm.MIXED, args.sweeps, max(2, args.steps // 2), args.warmup)
@@ -906,7 +926,8 @@ def main():
                 bb = bytes_per_update(kind, mixed_) * p3
                 c3["roofline"][f"{kind}_{prec}"] = {
                     "kernel": f"k_{kind}_sweep<{'float' if mixed_ else 'double'}>", "avg_launch_ms": t * 1e3,
-                    "algorithmic_bytes_per_launch": bb, "achieved": bb / t / 1e9, "frac": bb / t / 1e9 / HBM_PEAK_GBS}
+                    "algorithmic_bytes_per_launch": bb, "achieved": bb / t / 1e9, "frac": bb / t / 1e9 / HBM_PEAK_GBS,
+                    "traffic": tr3.get(f"{kind}_{prec}_bytes_per_launch")}
         print(f"[bench] C3 fp64 {r3['updates_per_s']:.3e} upd/s, mixed {r3m['updates_per_s']:.3e} upd/s",
               file=sys.stderr, flush=True)
     batch_roof = None
@@ -939,7 +960,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded NACA0012 C-grid and Hicks-Henne bump positions)",
-        "config": {"workload": wl.name, "cells": 32768, "velocities": 2304, "pairs": pairs,
+        "config": {"workload": wl.name, "cells": wl.grid.ni * wl.grid.nj, "velocities": wl.vgrid.n1 * wl.vgrid.n2,
+                   "pairs": pairs,
                    "sweeps_per_step": {"primal": args.sweeps, "adjoint": args.sweeps},
                    "Kn": wl.flow.Kn, "Ma": wl.flow.Ma, "shape_params": int(wl.grid.wall_jac.shape[-1]),
                    "parallelism": "single GPU"},

@@ -80,10 +80,11 @@ class _Slot:
 
 
 def serve(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_counter,
-          realtime: bool = True, sleep=time.sleep) -> Dict:
+          realtime: bool = True, sleep=time.sleep, on_finish=None) -> Dict:
     """Run the request stream to completion.  ``requests`` carry ``rid``,
     ``arrival`` (s after start) and ``want_adjoint``.  With realtime=False
-    all requests are available at once (closed loop, capacity)."""
+    all requests are available at once (closed loop, capacity).
+    on_finish(result, n_finished) is called as each request leaves."""
     order = sorted(requests, key=lambda r: r.arrival)
     results = {r.rid: SolveResult(r.rid, r.arrival if realtime else 0.0) for r in order}
     pending: List = []
@@ -94,6 +95,7 @@ def serve(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_co
     launches = 0
     peak_used = 0
     peak_resident = 0
+    n_finished = 0
 
     def now():
         return clock() - t0
@@ -111,6 +113,9 @@ def serve(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_co
             if fp > cfg.memory_budget:
                 res = results[req.rid]
                 res.status, res.error, res.finished = "failed", "footprint exceeds budget", now()
+                n_finished += 1
+                if on_finish is not None:
+                    on_finish(res, n_finished)
                 continue
             if used + fp <= cfg.memory_budget and len(active) < cfg.max_resident:
                 try:
@@ -118,6 +123,9 @@ def serve(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_co
                 except Exception as e:       # allocation or setup failure: fail this request only
                     res = results[req.rid]
                     res.status, res.error, res.finished = "failed", str(e), now()
+                    n_finished += 1
+                    if on_finish is not None:
+                        on_finish(res, n_finished)
                     continue
                 used += fp
                 res = results[req.rid]
@@ -171,6 +179,9 @@ def serve(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_co
                 slot.res.finished = now()
                 backend.release(slot.h)
                 used -= backend.footprint(slot.req)
+                n_finished += 1
+                if on_finish is not None:
+                    on_finish(slot.res, n_finished)
             else:
                 keep.append(slot)
         active = keep
@@ -228,11 +239,11 @@ def capped_by_kn(requests: List, results: List[SolveResult]) -> Dict:
 
 
 def serve_one_at_a_time(requests: List, backend: Backend, cfg: ServeConfig, clock=time.perf_counter,
-                        realtime: bool = True, sleep=time.sleep) -> Dict:
+                        realtime: bool = True, sleep=time.sleep, on_finish=None) -> Dict:
     """Baseline: one solve at a time in arrival order, each alone on the GPU."""
     big = ServeConfig(memory_budget=cfg.memory_budget, sweeps_per_check=cfg.sweeps_per_check, tol=cfg.tol,
                       adjoint_tol=cfg.adjoint_tol, max_iter=cfg.max_iter, max_resident=1)
-    return serve(requests, backend, big, clock, realtime, sleep)
+    return serve(requests, backend, big, clock, realtime, sleep, on_finish)
 
 
 # ---------------------------------------------------------------------------

@@ -75,6 +75,17 @@ def test_oversized_and_failing_requests_fail_alone():
     assert len(fb.live) == 0
 
 
+def test_on_finish_reports_every_request_once():
+    reqs = _stream(n=20)
+    fb = S.FakeBackend(fail_create={3})
+    seen = []
+    out = S.serve(reqs, fb, S.ServeConfig(memory_budget=1 << 40, sweeps_per_check=10, tol=1e-6),
+                  clock=fb.clock, sleep=fb.sleep, on_finish=lambda res, n: seen.append((res.rid, n)))
+    assert sorted(r for r, _ in seen) == sorted(r.rid for r in reqs)
+    assert [n for _, n in seen] == list(range(1, len(reqs) + 1))
+    assert out["failed"] == 1
+
+
 def test_iteration_cap_marks_notconv_but_returns_result():
     reqs = [_req(0, 0.0, adj=True)]
     fb = S.FakeBackend()

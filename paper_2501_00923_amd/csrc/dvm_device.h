@@ -251,6 +251,20 @@ __device__ __forceinline__ void eq_conservative(const DevSolve &d, const double 
     }
 }
 
+// The member of a group that owns launch cell i (pre ascending, pre[0] = 0).
+__device__ __forceinline__ int group_member(const MacroGroup &g, int i)
+{
+    int lo = 0, hi = g.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.pre[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // Instantiate for the storage type of a solve: float (mixed) or double (FP64).
 #define DVM_DISPATCH(mixed, ...) \
     do {                          \

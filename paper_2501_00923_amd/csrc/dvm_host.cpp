@@ -1423,6 +1423,15 @@ int dvm_batch_create_static(dvm_solver *const *solvers, int n, void *hip_stream,
     return DVM_OK;
 }
 
+// append member m (nc cells, state buffer par) to a launch group
+static void group_add(dvm::MacroGroup &g, int m, int nc, int par)
+{
+    g.idx[g.n] = m;
+    g.par[g.n] = par;
+    g.pre[g.n + 1] = g.pre[g.n] + nc;
+    g.n++;
+}
+
 int dvm_batch_run(dvm_batch *b, int iters)
 {
     if (!b) return fail(DVM_EINVAL, "null batch");
@@ -1432,6 +1441,7 @@ int dvm_batch_run(dvm_batch *b, int iters)
     const auto *bs = reinterpret_cast<const int32_t *>(w + b->off_bs);
     const auto *bc = reinterpret_cast<const int32_t *>(w + b->off_bc);
     const auto *par = reinterpret_cast<const int32_t *>(w + b->off_par);
+    std::vector<int> due[2];
     for (int it = 0; it < iters; it++) {
         // second-order members: the held correction of the current state,
         // on the same cadence as a single solve's
@@ -1451,13 +1461,23 @@ int dvm_batch_run(dvm_batch *b, int iters)
             s->since[ph]++;
         }
         // primal members with the conservative equilibrium: its parameters
-        // of the current state, which their sweep reads
-        for (int m = 0; m < b->n; m++) {
-            dvm_solver *s = b->members[m];
-            if (s->phase == 0 && s->equil == DVM_EQ_CONSERVATIVE) {
+        // of the current state, which their sweep reads (one launch per
+        // group of members)
+        {
+            dvm::MacroGroup g;
+            g.n = 0;
+            g.pre[0] = 0;
+            for (int m = 0; m < b->n; m++) {
+                dvm_solver *s = b->members[m];
+                if (s->phase != 0 || s->equil != DVM_EQ_CONSERVATIVE) continue;
                 if (!s->dev.mstate) return fail(DVM_ESTATE, "no equilibrium parameter buffer");
-                HIP_OK(dvm::launch_eq_params(s->dev, s->fpar ^ (it & 1), 0, b->stream));
+                group_add(g, m, s->nc, s->fpar ^ (it & 1));
+                if (g.n == dvm::kMacroGroup) {
+                    HIP_OK(dvm::launch_eq_params_group(tab, g, 0, b->stream));
+                    g.n = 0;
+                }
             }
+            HIP_OK(dvm::launch_eq_params_group(tab, g, 0, b->stream));
         }
         int off = 0;
         for (int g = 0; g < 4; g++) {
@@ -1465,15 +1485,52 @@ int dvm_batch_run(dvm_batch *b, int iters)
                                      g & 1, b->stream));
             off += b->nb_group[g];
         }
-        // primal members with the macroscopic prediction, on their own cadence
-        // (the state after this sweep sits in buffer fpar ^ ((it + 1) & 1))
+        // members with the macroscopic prediction, on their own cadence (the
+        // state after this sweep sits in buffer par ^ ((it + 1) & 1)): each
+        // member's own set-up and finishing kernels, and the Gauss-Seidel
+        // steps of all members due with the same inner count in shared
+        // launches (the per-cell arithmetic is the single solve's)
+        due[0].clear();
+        due[1].clear();
         for (int m = 0; m < b->n; m++) {
             dvm_solver *s = b->members[m];
             if (s->acc_every <= 0) continue;
-            if (s->phase == 0 && ++s->acc_count % s->acc_every == 0)
-                HIP_OK(dvm::launch_macro_predict(s->dev, s->fpar ^ ((it + 1) & 1), s->acc_inner, b->stream));
-            if (s->phase == 1 && ++s->acc_acount % s->acc_every == 0)
-                HIP_OK(dvm::launch_macro_adjoint_predict(s->dev, s->ppar ^ ((it + 1) & 1), s->acc_inner, b->stream));
+            if (s->phase == 0 && ++s->acc_count % s->acc_every == 0) due[0].push_back(m);
+            if (s->phase == 1 && ++s->acc_acount % s->acc_every == 0) due[1].push_back(m);
+        }
+        for (int adj = 0; adj < 2; adj++) {
+            if (due[adj].empty()) continue;
+            for (int m : due[adj]) {
+                dvm_solver *s = b->members[m];
+                const int par = (adj ? s->ppar : s->fpar) ^ ((it + 1) & 1);
+                HIP_OK(adj ? dvm::launch_macro_adjoint_begin(s->dev, par, b->stream)
+                           : dvm::launch_macro_predict_begin(s->dev, par, b->stream));
+            }
+            std::vector<int> inners;
+            for (int m : due[adj])
+                if (std::find(inners.begin(), inners.end(), b->members[m]->acc_inner) == inners.end())
+                    inners.push_back(b->members[m]->acc_inner);
+            for (int inner : inners) {
+                dvm::MacroGroup g;
+                g.n = 0;
+                g.pre[0] = 0;
+                for (int m : due[adj]) {
+                    dvm_solver *s = b->members[m];
+                    if (s->acc_inner != inner) continue;
+                    group_add(g, m, s->nc, 0);
+                    if (g.n == dvm::kMacroGroup) {
+                        HIP_OK(dvm::launch_macro_gs_group(tab, g, inner, adj, b->stream));
+                        g.n = 0;
+                    }
+                }
+                HIP_OK(dvm::launch_macro_gs_group(tab, g, inner, adj, b->stream));
+            }
+            for (int m : due[adj]) {
+                dvm_solver *s = b->members[m];
+                const int par = (adj ? s->ppar : s->fpar) ^ ((it + 1) & 1);
+                HIP_OK(adj ? dvm::launch_macro_adjoint_end(s->dev, par, b->stream)
+                           : dvm::launch_macro_predict_end(s->dev, par, b->stream));
+            }
         }
     }
     b->step += iters;

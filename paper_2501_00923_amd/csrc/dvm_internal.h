@@ -115,6 +115,22 @@ hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream
 // phi[ppar] += dl
 hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t st);
 hipError_t launch_macro_adjoint_predict(const DevSolve &d, int ppar, int inner, hipStream_t st);
+// A group of batch members for one launch of a per-cell kernel: member a is
+// tab[idx[a]], owns cells pre[a] .. pre[a+1]-1 of the launch and its state
+// is in buffer par[a].
+constexpr int kMacroGroup = 64;
+struct MacroGroup {
+    int n;
+    int idx[kMacroGroup];
+    int par[kMacroGroup];
+    int pre[kMacroGroup + 1];
+};
+hipError_t launch_macro_predict_begin(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_macro_predict_end(const DevSolve &d, int par, hipStream_t st);
+hipError_t launch_macro_adjoint_begin(const DevSolve &d, int pnew, hipStream_t st);
+hipError_t launch_macro_adjoint_end(const DevSolve &d, int pnew, hipStream_t st);
+hipError_t launch_macro_gs_group(const DevSolve *tab, const MacroGroup &g, int inner, int adjoint, hipStream_t st);
+hipError_t launch_eq_params_group(const DevSolve *tab, const MacroGroup &g, int with_M, hipStream_t st);
 
 // second-order scheme: the slopes G and dF of f[par]; the held primal
 // correction c (with G and dF) from f[par]; the

@@ -1144,10 +1144,8 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
 // serves several cells and the Newton steps' reductions span a few lanes.
 constexpr int kEqGroup = 16;
 
-__global__ __launch_bounds__(kBlock) void k_eq_params(DevSolve d, int par, int with_M)
+__device__ __forceinline__ void eq_params_cell(const DevSolve &d, int c, int par, int with_M)
 {
-    const int c = blockIdx.x * (kBlock / kEqGroup) + (int)(threadIdx.x / kEqGroup);
-    if (c >= d.nc) return;                      // whole groups; shuffles stay inside a group
     const double *Wc = d.W[par] + 4 * c;
     const double W[4] = {Wc[0], Wc[1], Wc[2], Wc[3]};
     const double rho = W[0], u1 = W[1] / rho, u2 = W[2] / rho;
@@ -1164,11 +1162,38 @@ __global__ __launch_bounds__(kBlock) void k_eq_params(DevSolve d, int par, int w
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_eq_params(DevSolve d, int par, int with_M)
+{
+    const int c = blockIdx.x * (kBlock / kEqGroup) + (int)(threadIdx.x / kEqGroup);
+    if (c >= d.nc) return;                      // whole groups; shuffles stay inside a group
+    eq_params_cell(d, c, par, with_M);
+}
+
+// the same for a group of batch members (member a: tab[idx[a]], state in
+// buffer par[a]), bitwise the single-solve kernel's results
+__global__ __launch_bounds__(kBlock) void k_eq_params_group(const DevSolve *__restrict__ tab, MacroGroup g,
+                                                            int with_M)
+{
+    const int i = blockIdx.x * (kBlock / kEqGroup) + (int)(threadIdx.x / kEqGroup);
+    if (i >= g.pre[g.n]) return;                // whole lane groups
+    const int a = group_member(g, i);
+    eq_params_cell(tab[g.idx[a]], i - g.pre[a], g.par[a], with_M);
+}
+
 hipError_t launch_eq_params(const DevSolve &d, int par, int with_M, hipStream_t st)
 {
     if (!d.mstate || !d.equil) return hipErrorInvalidValue;
     constexpr int per_block = kBlock / kEqGroup;
     hipLaunchKernelGGL(k_eq_params, dim3((d.nc + per_block - 1) / per_block), dim3(kBlock), 0, st, d, par, with_M);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq_params_group(const DevSolve *tab, const MacroGroup &g, int with_M, hipStream_t st)
+{
+    if (g.n <= 0) return hipSuccess;
+    constexpr int per_block = kBlock / kEqGroup;
+    hipLaunchKernelGGL(k_eq_params_group, dim3((g.pre[g.n] + per_block - 1) / per_block), dim3(kBlock), 0, st, tab, g,
+                       with_M);
     return hipGetLastError();
 }
 

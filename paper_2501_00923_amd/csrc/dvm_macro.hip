@@ -344,11 +344,9 @@ __device__ __forceinline__ int back_face(const DevSolve &d, int n, int c)
 // ---------------------------------------------------------------------------
 // one colour of a red-black block Gauss-Seidel step, a thread per cell
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, const double *__restrict__ src,
-                                                       double *__restrict__ dst)
+__device__ __forceinline__ void rbgs_cell(const DevSolve &d, int c, int colour, const double *__restrict__ src,
+                                          double *__restrict__ dst)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.nc) return;
     const int m = d.cell_of[c];
     const int i = m % d.ni, j = m / d.ni;
     if (((i + j) & 1) != colour) {
@@ -377,6 +375,27 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, c
         for (int e = 0; e < 4; e++) acc += Di[4 * a + e] * b[e];
         dst[4 * c + a] = acc;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, const double *__restrict__ src,
+                                                       double *__restrict__ dst)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < d.nc) rbgs_cell(d, c, colour, src, dst);
+}
+
+// Several solves of a batch in one launch: a thread per cell of the
+// group's members in turn (member a owns cells pre[a] .. pre[a+1]-1), each
+// member's DevSolve read from the batch's table; the per-cell arithmetic
+// is the single-solve kernel's, so the results are bitwise the same.
+__global__ __launch_bounds__(kBlock) void k_macro_rbgs_group(const DevSolve *__restrict__ tab, MacroGroup g,
+                                                             int colour, int from)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.pre[g.n]) return;
+    const int a = group_member(g, i);
+    const DevSolve &d = tab[g.idx[a]];
+    rbgs_cell(d, i - g.pre[a], colour, d.mx[from], d.mx[from ^ 1]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_macro_zero(double *x, int n)
@@ -423,19 +442,29 @@ static hipError_t macro_system(const DevSolve &d, int par, bool with_r, hipStrea
     return hipGetLastError();
 }
 
+hipError_t launch_macro_predict_begin(const DevSolve &d, int par, hipStream_t st)
+{
+    if (hipError_t e = macro_system(d, par, true, st)) return e;
+    hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mx[0], 4 * d.nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_predict_end(const DevSolve &d, int par, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_macro_apply, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d, par, d.mx[0]);
+    return hipGetLastError();
+}
+
 hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream_t st)
 {
     const int gt = (d.nc + kBlock - 1) / kBlock;
-    if (hipError_t e = macro_system(d, par, true, st)) return e;
-    hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mx[0], 4 * d.nc);
-    if (hipError_t e = hipGetLastError()) return e;
+    if (hipError_t e = launch_macro_predict_begin(d, par, st)) return e;
     for (int it = 0; it < inner; it++) {
         hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, d.mx[0], d.mx[1]);
         hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 1, d.mx[1], d.mx[0]);
         if (hipError_t e = hipGetLastError()) return e;
     }
-    hipLaunchKernelGGL(k_macro_apply, dim3(gt), dim3(kBlock), 0, st, d, par, d.mx[0]);
-    return hipGetLastError();
+    return launch_macro_predict_end(d, par, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,11 +512,9 @@ __device__ __forceinline__ bool macro_colour(const DevSolve &d, int c, int colou
 // -Dinv_c^T ob_c joins rbar on the colour, and the adjoint of its input is
 // ib_m = (m off the colour: ob_m) + sum_q O_nq'^T t_n over neighbours n on
 // the colour, where O_nq' (n's inflow block from m) is -B_mq
-__global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colour, const double *__restrict__ ob,
-                                                           double *__restrict__ ib, double *__restrict__ rbar)
+__device__ __forceinline__ void rbgs_adj_cell(const DevSolve &d, int m, int colour, const double *__restrict__ ob,
+                                              double *__restrict__ ib, double *__restrict__ rbar)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= d.nc) return;
     double acc[4];
     const bool on = macro_colour(d, m, colour);
 #pragma unroll
@@ -524,17 +551,46 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colou
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colour, const double *__restrict__ ob,
+                                                           double *__restrict__ ib, double *__restrict__ rbar)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < d.nc) rbgs_adj_cell(d, m, colour, ob, ib, rbar);
+}
+
+__global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj_group(const DevSolve *__restrict__ tab, MacroGroup g,
+                                                                 int colour, int from)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.pre[g.n]) return;
+    const int a = group_member(g, i);
+    const DevSolve &d = tab[g.idx[a]];
+    rbgs_adj_cell(d, i - g.pre[a], colour, d.mx[from], d.mx[from ^ 1], d.mr);
+}
+
 hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t st)
 {
     return macro_system(d, fpar, false, st);
 }
 
-hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, hipStream_t st)
+hipError_t launch_macro_adjoint_begin(const DevSolve &d, int pnew, hipStream_t st)
 {
     const int gt = (d.nc + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_macro_adj_y, dim3(gt), dim3(kBlock), 0, st, d, pnew, d.mx[0]);
     hipLaunchKernelGGL(k_macro_zero, dim3((4 * d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d.mr, 4 * d.nc);
-    if (hipError_t e = hipGetLastError()) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_adjoint_end(const DevSolve &d, int pnew, hipStream_t st)
+{
+    // phi -= (z . Psi, z_3) and the adjoint moments of the result, one pass
+    return launch_adjoint_correct_moments(d, pnew, d.mr, st);
+}
+
+hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, hipStream_t st)
+{
+    const int gt = (d.nc + kBlock - 1) / kBlock;
+    if (hipError_t e = launch_macro_adjoint_begin(d, pnew, st)) return e;
     // the forward steps ran it = 0 .. inner-1, colour 0 (x -> y) then 1
     // (y -> x); here it = inner-1 .. 0, colour 1 (adjoint of x -> of y) then 0
     for (int it = 0; it < inner; it++) {
@@ -542,8 +598,26 @@ hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, 
         hipLaunchKernelGGL(k_macro_rbgs_adj, dim3(gt), dim3(kBlock), 0, st, d, 0, d.mx[1], d.mx[0], d.mr);
         if (hipError_t e = hipGetLastError()) return e;
     }
-    // phi -= (z . Psi, z_3) and the adjoint moments of the result, one pass
-    return launch_adjoint_correct_moments(d, pnew, d.mr, st);
+    return launch_macro_adjoint_end(d, pnew, st);
+}
+
+// the Gauss-Seidel steps of a group of batch members with the same inner
+// count, one launch per half step for the whole group
+hipError_t launch_macro_gs_group(const DevSolve *tab, const MacroGroup &g, int inner, int adjoint, hipStream_t st)
+{
+    if (g.n <= 0) return hipSuccess;
+    const int gt = (g.pre[g.n] + kBlock - 1) / kBlock;
+    for (int it = 0; it < inner; it++) {
+        if (adjoint) {
+            hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 1, 0);
+            hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 0, 1);
+        } else {
+            hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 0, 0);
+            hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 1, 1);
+        }
+        if (hipError_t e = hipGetLastError()) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace dvm

@@ -98,7 +98,10 @@ def test_batched_prediction_bitwise(precision):
     cases = [_case("tiny_circle"), _case("tiny_naca"), _case("o70x20_tiles")]
 
     def make(i, wl):
-        s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=1, accelerate=ACC if i != 1 else None)
+        # member 1 without the prediction, member 2 with another inner count
+        # (the batch groups the Gauss-Seidel launches by inner count)
+        acc = None if i == 1 else (ACC if i == 0 else (ACC[0], ACC[1] + 3))
+        s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=1, accelerate=acc)
         s.primal_init()
         return s
     alone = []
@@ -216,20 +219,21 @@ def test_adjoint_prediction_converges_to_the_plain_solution():
 
 @pytest.mark.parametrize("precision", [dvm.FP64, dvm.MIXED])
 def test_batched_adjoint_prediction_bitwise(precision):
-    cases = [_case("tiny_circle"), _case("o70x20_tiles")]
+    cases = [_case("tiny_circle"), _case("o70x20_tiles"), _case("tiny_naca")]
+    accs = [ACC, ACC, (ACC[0], ACC[1] + 3)]      # two share the Gauss-Seidel launches, one has its own
 
-    def make(wl):
-        s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=1, accelerate=ACC)
+    def make(wl, acc):
+        s = dvm.Solver.from_workload(wl, precision=precision, equilibrium=1, accelerate=acc)
         s.primal_init()
         s.primal_sweeps(8)
         s.adjoint_init()
         return s
     alone = []
-    for wl in cases:
-        s = make(wl)
+    for wl, acc in zip(cases, accs):
+        s = make(wl, acc)
         s.adjoint_sweeps(12)
         alone.append(s.state_save(dvm.STATE_PHI))
-    members = [make(wl) for wl in cases]
+    members = [make(wl, acc) for wl, acc in zip(cases, accs)]
     b = dvm.Batch(members)
     b.run(7)
     b.run(5)

@@ -161,6 +161,28 @@ def test_server_results_alone_equal_mix(precision):
             assert np.array_equal(a.dJ, b.dJ)
 
 
+@pytest.mark.parametrize("precision", [dvm.FP64, dvm.MIXED])
+def test_server_with_prediction_alone_equals_mix(precision):
+    """Requests below Kn 0.5 solve with the conservative equilibrium and the
+    macroscopic prediction: their batched results (shared Gauss-Seidel
+    launches, equilibrium parameters per member group) equal one-at-a-time
+    results bit for bit, and both reach the tolerance."""
+    reqs = _small_stream(8, 13, 1e6)
+    for i, r in enumerate(reqs):        # half near the continuum, half not
+        r.workload.flow.Kn = 0.02 if i % 2 == 0 else 0.6
+    cfg = S.ServeConfig(memory_budget=1 << 34, sweeps_per_check=10, tol=1e-5, adjoint_tol=1e-5, max_iter=2000)
+    _say(f"[gpu] server with prediction, precision={precision}")
+    mix = S.serve(reqs, S.GpuBackend(precision, accelerate_below_kn=0.5, accelerate=(5, 20)), cfg, realtime=False)
+    assert mix["peak_resident"] > 1
+    one = S.serve_one_at_a_time(reqs, S.GpuBackend(precision, accelerate_below_kn=0.5, accelerate=(5, 20)), cfg,
+                                realtime=False)
+    for a, b in zip(mix["results"], one["results"]):
+        assert a.status == b.status == "ok", (a.rid, a.status, a.error)
+        assert a.J == b.J and a.primal_iters == b.primal_iters and a.adjoint_iters == b.adjoint_iters
+        if a.dJ is not None:
+            assert np.array_equal(a.dJ, b.dJ)
+
+
 def test_server_admission_respects_budget():
     reqs = _small_stream(8, 5, 1e6)
     for r in reqs:

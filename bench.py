@@ -695,8 +695,8 @@ def main():
                     help="skip the second-order leg (Green-Gauss slopes, Venkatakrishnan limiter)")
     ap.add_argument("--correction-every", type=int, default=40,
                     help="second-order leg: sweeps between evaluations of the held correction")
-    ap.add_argument("--serving-requests", type=int, default=64,
-                    help="requests in the solve-server leg (0 skips it; 512 is the full stream)")
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests in the solve-server leg (0 skips it; the default is the full stream)")
     ap.add_argument("--serving-cap", type=int, default=1000, help="sweep cap per phase per request")
     ap.add_argument("--accel-check", action="store_true",
                     help="the 256x128 C-grid with 64x64 sinh velocities at Kn 1e-3 .. 10: solves to --accel-tol with "

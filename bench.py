@@ -708,7 +708,7 @@ def main():
     ap.add_argument("--accel-plain-cap", type=int, default=3000)
     ap.add_argument("--accel-kn", type=str, default="1e-3,1e-2,0.1,1,10")
     ap.add_argument("--accel-precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--serving-accel-below-kn", type=float, default=0.5,
+    ap.add_argument("--serving-accel-below-kn", type=float, default=1.0,
                     help="requests below this Kn use the conservative equilibrium and the macroscopic prediction "
                          "(0: none)")
     ap.add_argument("--serving-accel-inner", type=int, default=50)

@@ -950,6 +950,8 @@ def main():
         optimization["Cd_initial"], optimization["Cd_final"] = o["Cd"][0], o["Cd"][-1]
         optimization["drag_change"] = o["drag_change"]
         optimization["Q_over_vmin_final"] = o["Q_over_vmin"][-1]
+        optimization["paper_context"] = ("a full optimisation in 5-20 minutes on 40-160 CPU cores "
+                                         "(the paper's channel and supersonic airfoil cases, Sec. 4)")
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)

@@ -127,6 +127,42 @@ def run_gpu(wl, precision, sweeps, steps, warmup, order=1, correction_every=40):
     return out
 
 
+def c1_leg(repeats=5):
+    """The circle O-grid 64x32 with 16x16 midpoint velocities on [-5, 5] (Kn 1,
+    Ma 0.5), FP64: one whole solve -- primal to a relative residual of 1e-8
+    (checked every 50 sweeps), drag, adjoint to 1e-8, the 8 Fourier-mode
+    sensitivities -- timed on the host clock with the device synchronised
+    on both sides; the solver's buffer is allocated once, outside the timed
+    region.  One untimed solve first, then `repeats` timed ones."""
+    import torch
+
+    from paper_2501_00923_amd import dvm
+    from paper_2501_00923_amd import inputs as I
+
+    wl = I.c1_circle()
+    s = dvm.Solver.from_workload(wl, precision=dvm.FP64)
+    times = []
+    for rep in range(repeats + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.primal_init()
+        itp, rp = s.primal_iterate(20000, tol=1e-8, check_every=50)
+        J, Cd = s.objective()
+        s.adjoint_init()
+        ita, ra = s.adjoint_iterate(20000, tol=1e-8, check_every=50)
+        g = s.param_sensitivity(wl.grid.wall_jac)
+        torch.cuda.synchronize()
+        if rep > 0:
+            times.append(time.perf_counter() - t0)
+    times.sort()
+    med = times[len(times) // 2]
+    pairs = wl.grid.ni * wl.grid.nj * wl.vgrid.n1 * wl.vgrid.n2
+    return {"workload": wl.name, "precision": "fp64", "tol": 1e-8, "primal_sweeps": itp, "adjoint_sweeps": ita,
+            "primal_resid": rp, "adjoint_resid": ra, "Cd": Cd, "dJ_dparams": [float(x) for x in g],
+            "solve_ms_median": med * 1e3, "solve_ms_min": times[0] * 1e3, "repeats": repeats,
+            "updates_per_s": pairs * (itp + ita) / med}
+
+
 def batch_roofline(n_members, seed, sweeps=20, warmup=3):
     """Achieved HBM rate of the batched sweep kernels on a serving mix: the
     first `n_members` requests of the seeded serving stream (circle / NACA,
@@ -716,6 +752,8 @@ def main():
                     help="the timed workload: c2 (the benchmark's: 48x48 Newton-Cotes velocities, Kn 0.1, Ma 0.8) "
                          "or c3 (64x64 sinh velocities, Kn 0.1, Ma 0.5) on the 256x128 NACA0012 C-grid; c3 is for "
                          "its counter runs")
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the whole-solve latency of the circle O-grid 64x32 with 16x16 velocities")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 256x128 C-grid with 64x64 sinh velocities (134 M pairs) leg")
     ap.add_argument("--batch-members", type=int, default=24,
@@ -930,6 +968,11 @@ def main():
                     "traffic": tr3.get(f"{kind}_{prec}_bytes_per_launch")}
         print(f"[bench] C3 fp64 {r3['updates_per_s']:.3e} upd/s, mixed {r3m['updates_per_s']:.3e} upd/s",
               file=sys.stderr, flush=True)
+    c1 = None
+    if not args.no_c1:
+        c1 = c1_leg()
+        print(f"[bench] C1 whole solve: {c1['primal_sweeps']} + {c1['adjoint_sweeps']} sweeps, "
+              f"{c1['solve_ms_median']:.1f} ms (median of {c1['repeats']})", file=sys.stderr, flush=True)
     batch_roof = None
     if args.batch_members > 0:
         batch_roof = batch_roofline(args.batch_members, args.serving_seed)
@@ -967,7 +1010,7 @@ def main():
                    "sweeps_per_step": {"primal": args.sweeps, "adjoint": args.sweeps},
                    "Kn": wl.flow.Kn, "Ma": wl.flow.Ma, "shape_params": int(wl.grid.wall_jac.shape[-1]),
                    "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "c3": c3, "batched_sweep_roofline": batch_roof,
+        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "c3": c3, "c1": c1, "batched_sweep_roofline": batch_roof,
         "second_order": second, "serving": serving,
         "optimization": optimization, "J": r64["J"], "Cd": r64["Cd"],
     }

@@ -223,11 +223,10 @@ __global__ __launch_bounds__(kBlock) void k_macro_blocks(DevSolve d, int par)
     const double *gMd = static_cast<const double *>(d.gM);
     const float *gMf = static_cast<const float *>(d.gM);
     __syncthreads();
-    // acc: B of the two faces in dg/dP form (2 x 16), wall1 (4), dF in dg/dP form (4)
-    double acc[40];
+    // Bp: B of the two faces in dg/dP form (2 x 16)
+    double Bp[32];
 #pragma unroll
-    for (int i = 0; i < 40; i++) acc[i] = 0.0;
-    double *Bp = acc, *wall1 = acc + 32, *dFp = acc + 36;
+    for (int i = 0; i < 32; i++) Bp[i] = 0.0;
     for (int k = lane; k < nv; k += kWave) {
         const int a = k % n1, b = k / n1;
         const double v1 = vx[a], v2 = vy[b], wt = wx[a] * wy[b];
@@ -235,41 +234,26 @@ __global__ __launch_bounds__(kBlock) void k_macro_blocks(DevSolve d, int par)
         double g1, g2, d1[4], d2[4];
         dg_dP(qc, tabX[cl][a], tabY[cl][b], v1, v2, g1, g2, d1, d2);
         const double s0 = v1 * Sx[0] + v2 * Sy[0], s1 = v1 * Sx[1] + v2 * Sy[1];
-        if (s0 > 0 || s1 > 0) {
-            // Psi_x dg/dP_p, the (x == 3) row with the second distribution's term
-            double pd[16];
+        // B_q[x][p] += w s Psi_x dg1/dP_p (+ w s dg2/dP_p in row x = 3) for
+        // each outflow face, as fused multiply-adds on (w s Psi_x)
 #pragma unroll
-            for (int x = 0; x < 4; x++)
+        for (int t = 0; t < 2; t++) {
+            const double st = t == 0 ? s0 : s1;
+            if (st > 0) {
+                const double ws = wt * st;
+                double *Bq = Bp + 16 * t;
 #pragma unroll
-                for (int p = 0; p < 4; p++) pd[4 * x + p] = psi[x] * d1[p] + (x == 3 ? d2[p] : 0.0);
-            if (s0 > 0) {
-                const double ws = wt * s0;
+                for (int x = 0; x < 4; x++) {
+                    const double wsp = ws * psi[x];
 #pragma unroll
-                for (int i = 0; i < 16; i++) Bp[i] += ws * pd[i];
-            }
-            if (s1 > 0) {
-                const double ws = wt * s1;
+                    for (int p = 0; p < 4; p++) Bq[4 * x + p] = fma(wsp, d1[p], Bq[4 * x + p]);
+                }
 #pragma unroll
-                for (int i = 0; i < 16; i++) Bp[16 + i] += ws * pd[i];
-            }
-        }
-        if (wl >= 0) {
-            // the wall face (face 0): where it is inflow, the diffuse value's
-            // response; the outgoing flux's response dF
-            const double s = v1 * Sx[0] + v2 * Sy[0];
-            if (!(s > 0)) {
-                const double gb1 = (d.mixed ? (double)gMf[k] : gMd[k]) / Dw, gb2 = thw2 * gb1;
-#pragma unroll
-                for (int x = 0; x < 4; x++) wall1[x] += wt * s * (psi[x] * gb1 + (x == 3 ? gb2 : 0.0));
-            }
-            const double vn = v1 * n1w + v2 * n2w;
-            if (vn > 0) {
-#pragma unroll
-                for (int p = 0; p < 4; p++) dFp[p] += wt * vn * d1[p];
+                for (int p = 0; p < 4; p++) Bq[12 + p] = fma(ws, d2[p], Bq[12 + p]);
             }
         }
     }
-    wave_sum<40>(acc);
+    wave_sum<32>(Bp);
     const double *M = ms + 4;
     if (act && lane == 0) {
         // this half's faces: B_q = Bp_q M into the table, and their share of D
@@ -290,16 +274,45 @@ __global__ __launch_bounds__(kBlock) void k_macro_blocks(DevSolve d, int par)
                     Dm[4 * x + m] += v;
                 }
         }
-        if (wl >= 0) {
+#pragma unroll
+        for (int i = 0; i < 16; i++) Dpart[cl][h][i] = Dm[i];
+    }
+    // the wall face (face 0, first wave of a wall cell), in a loop of its
+    // own so that the face sums above need not stay live beside its sums:
+    // where the face is inflow, the diffuse value's response wall1; the
+    // outgoing flux's response dF (dg/dP form)
+    if (wl >= 0) {
+        double wacc[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) wacc[i] = 0.0;
+        double *wall1 = wacc, *dFp = wacc + 4;
+        for (int k = lane; k < nv; k += kWave) {
+            const int a = k % n1, b = k / n1;
+            const double v1 = vx[a], v2 = vy[b], wt = wx[a] * wy[b];
+            const double psi[4] = {1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2)};
+            double g1, g2, d1[4], d2[4];
+            dg_dP(qc, tabX[cl][a], tabY[cl][b], v1, v2, g1, g2, d1, d2);
+            const double s = v1 * Sx[0] + v2 * Sy[0];
+            if (!(s > 0)) {
+                const double gb1 = (d.mixed ? (double)gMf[k] : gMd[k]) / Dw, gb2 = thw2 * gb1;
+#pragma unroll
+                for (int x = 0; x < 4; x++) wall1[x] += wt * s * (psi[x] * gb1 + (x == 3 ? gb2 : 0.0));
+            }
+            const double vn = v1 * n1w + v2 * n2w;
+            if (vn > 0) {
+#pragma unroll
+                for (int p = 0; p < 4; p++) dFp[p] += wt * vn * d1[p];
+            }
+        }
+        wave_sum<8>(wacc);
+        if (act && lane == 0) {
 #pragma unroll
             for (int m = 0; m < 4; m++) {
                 const double dF = ((dFp[0] * M[m] + dFp[1] * M[4 + m]) + dFp[2] * M[8 + m]) + dFp[3] * M[12 + m];
 #pragma unroll
-                for (int x = 0; x < 4; x++) Dm[4 * x + m] += wall1[x] * dF;
+                for (int x = 0; x < 4; x++) Dpart[cl][h][4 * x + m] += wall1[x] * dF;
             }
         }
-#pragma unroll
-        for (int i = 0; i < 16; i++) Dpart[cl][h][i] = Dm[i];
     }
     __syncthreads();
     if (!act || h != 0 || lane != 0) return;

@@ -117,42 +117,71 @@ __global__ __launch_bounds__(kPatchCells * kWave) void k_macro_resid(DevSolve d,
     const double Fw = wl >= 0 ? d.F[par][wl] : 0.0, Dw = wl >= 0 ? d.D[wl] : 1.0;
     const double thw2 = 0.5 * d.theta_w;
     const size_t row = (size_t)c * nv;
+    // the 1-D velocity tables in LDS (threads 0 .. n1 + n2 - 1)
+    __shared__ double svx[kMaxN1D], svy[kMaxN1D], swx[kMaxN1D], swy[kMaxN1D];
+    {
+        const int t = threadIdx.x, n2 = d.n2;
+        if (t < n1) {
+            svx[t] = d.vx[t];
+            swx[t] = d.wx[t];
+        } else if (t - n1 < n2) {
+            svy[t - n1] = d.vy[t - n1];
+            swy[t - n1] = d.wy[t - n1];
+        }
+    }
     macro_tables(d, P, tabX[w], tabY[w]);
+    // one source row per face for its inflow velocities: the neighbour's
+    // row or the far-field table (the wall's value is computed)
+    const T2 *src[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) src[q] = nb[q] >= 0 ? f + (size_t)nb[q] * nv : (nb[q] == -1 ? fd : f + row);
     __syncthreads();
     double r[4] = {0, 0, 0, 0};
+    int a = lane % n1, b = lane / n1;
+    const int da = kWave % n1, db = kWave / n1;
     for (int k = lane; k < nv; k += kWave) {
-        const int a = k % n1, b = k / n1;
-        const double v1 = d.vx[a], v2 = d.vy[b], wt = d.wx[a] * d.wy[b];
+        const double v1 = svx[a], v2 = svy[b], wt = swx[a] * swy[b];
         const double psi[4] = {1.0, v1, v2, 0.5 * (v1 * v1 + v2 * v2)};
         const double g1 = kap * tabX[w][a] * tabY[w][b], g2 = th2 * g1;
+        // every load of this velocity before its arithmetic: the own row,
+        // and each face's source row where the face is inflow
         const T2 fk = f[row + k];
+        double s[4];
+        T2 u[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            s[q] = v1 * Sx[q] + v2 * Sy[q];
+            u[q] = T2{0, 0};
+            if (!(s[q] > 0) && nb[q] >= -1) u[q] = src[q][k];
+        }
+        const double gw = wl >= 0 ? (double)gM[k] : 0.0;
         const double f1 = (double)fk.x, f2 = (double)fk.y;
         double in1 = Vt * (f1 - g1), in2 = Vt * (f2 - g2);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            const double s = v1 * Sx[q] + v2 * Sy[q];
             double a1, a2;
-            if (s > 0) {
+            if (s[q] > 0) {
                 a1 = f1;
                 a2 = f2;
-            } else if (nb[q] >= 0) {
-                const T2 u = f[(size_t)nb[q] * nv + k];
-                a1 = (double)u.x;
-                a2 = (double)u.y;
-            } else if (nb[q] == -1) {
-                const T2 u = fd[k];
-                a1 = (double)u.x;
-                a2 = (double)u.y;
+            } else if (nb[q] >= -1) {
+                a1 = (double)u[q].x;
+                a2 = (double)u[q].y;
             } else {
-                const double gb1 = (double)gM[k] / Dw;
+                const double gb1 = gw / Dw;
                 a1 = Fw * gb1;
                 a2 = Fw * (thw2 * gb1);
             }
-            in1 += s * a1;
-            in2 += s * a2;
+            in1 += s[q] * a1;
+            in2 += s[q] * a2;
         }
 #pragma unroll
         for (int x = 0; x < 4; x++) r[x] += wt * (psi[x] * in1 + (x == 3 ? in2 : 0.0));
+        a += da;
+        b += db;
+        if (a >= n1) {
+            a -= n1;
+            b++;
+        }
     }
     wave_sum<4>(r);
     if (act && lane == 0) {

@@ -384,46 +384,48 @@ __device__ __forceinline__ int back_face(const DevSolve &d, int n, int c)
 }
 
 // ---------------------------------------------------------------------------
-// one colour of a red-black block Gauss-Seidel step, a thread per cell
+// one colour of a red-black block Gauss-Seidel step for cell c: on its colour
+// x_c = Dinv_c (-r_c - sum_q O_cq src_nbr), the rest copied.  The cell's four
+// components sit on four lanes (component a = lane % 4): each lane sums its
+// row of the neighbours' blocks, the lanes exchange the right-hand side and
+// each applies its row of D^-1, so a launch has four threads per cell (the
+// kernel is latency-bound: one thread per cell gives 2 waves per CU on
+// 32,768 cells).  All four lanes of a cell take the same branches; callers
+// launch whole cells.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void rbgs_cell(const DevSolve &d, int c, int colour, const double *__restrict__ src,
-                                          double *__restrict__ dst)
+__device__ __forceinline__ void rbgs_cell(const DevSolve &d, int c, int a, int colour, const double *__restrict__ src,
+                                           double *__restrict__ dst)
 {
     const int m = d.cell_of[c];
     const int i = m % d.ni, j = m / d.ni;
     if (((i + j) & 1) != colour) {
-#pragma unroll
-        for (int a = 0; a < 4; a++) dst[4 * c + a] = src[4 * c + a];
+        dst[4 * c + a] = src[4 * c + a];
         return;
     }
-    double b[4];
-#pragma unroll
-    for (int a = 0; a < 4; a++) b[a] = -d.mr[4 * c + a];
+    double ba = -d.mr[4 * c + a];
     for (int q = 0; q < 4; q++) {
         const int n = d.nbr[4 * c + q];
         if (n < 0) continue;
         // the inflow block of n across face q is -B_nq'
         const double *B = d.mO + 64 * n + 16 * back_face(d, n, c);
 #pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) b[a] += B[4 * a + e] * src[4 * n + e];
+        for (int e = 0; e < 4; e++) ba += B[4 * a + e] * src[4 * n + e];
     }
+    double b[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) b[e] = __shfl(ba, e, 4);
     const double *Di = d.mDinv + 16 * c;
+    double acc = 0;
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-        double acc = 0;
-#pragma unroll
-        for (int e = 0; e < 4; e++) acc += Di[4 * a + e] * b[e];
-        dst[4 * c + a] = acc;
-    }
+    for (int e = 0; e < 4; e++) acc += Di[4 * a + e] * b[e];
+    dst[4 * c + a] = acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, const double *__restrict__ src,
                                                        double *__restrict__ dst)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < d.nc) rbgs_cell(d, c, colour, src, dst);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;     // 4 lanes per cell
+    if ((t >> 2) < d.nc) rbgs_cell(d, t >> 2, t & 3, colour, src, dst);
 }
 
 // Several solves of a batch in one launch: a thread per cell of the
@@ -433,11 +435,12 @@ __global__ __launch_bounds__(kBlock) void k_macro_rbgs(DevSolve d, int colour, c
 __global__ __launch_bounds__(kBlock) void k_macro_rbgs_group(const DevSolve *__restrict__ tab, MacroGroup g,
                                                              int colour, int from)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;     // 4 lanes per cell
+    const int i = t >> 2;
     if (i >= g.pre[g.n]) return;
     const int a = group_member(g, i);
     const DevSolve &d = tab[g.idx[a]];
-    rbgs_cell(d, i - g.pre[a], colour, d.mx[from], d.mx[from ^ 1]);
+    rbgs_cell(d, i - g.pre[a], t & 3, colour, d.mx[from], d.mx[from ^ 1]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_macro_zero(double *x, int n)
@@ -499,7 +502,7 @@ hipError_t launch_macro_predict_end(const DevSolve &d, int par, hipStream_t st)
 
 hipError_t launch_macro_predict(const DevSolve &d, int par, int inner, hipStream_t st)
 {
-    const int gt = (d.nc + kBlock - 1) / kBlock;
+    const int gt = (4 * d.nc + kBlock - 1) / kBlock;          // k_macro_rbgs: 4 lanes per cell
     if (hipError_t e = launch_macro_predict_begin(d, par, st)) return e;
     for (int it = 0; it < inner; it++) {
         hipLaunchKernelGGL(k_macro_rbgs, dim3(gt), dim3(kBlock), 0, st, d, 0, d.mx[0], d.mx[1]);
@@ -649,13 +652,14 @@ hipError_t launch_macro_gs_group(const DevSolve *tab, const MacroGroup &g, int i
 {
     if (g.n <= 0) return hipSuccess;
     const int gt = (g.pre[g.n] + kBlock - 1) / kBlock;
+    const int gt4 = (4 * g.pre[g.n] + kBlock - 1) / kBlock;  // k_macro_rbgs_group: 4 lanes per cell
     for (int it = 0; it < inner; it++) {
         if (adjoint) {
             hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 1, 0);
             hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 0, 1);
         } else {
-            hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 0, 0);
-            hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 1, 1);
+            hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt4), dim3(kBlock), 0, st, tab, g, 0, 0);
+            hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt4), dim3(kBlock), 0, st, tab, g, 1, 1);
         }
         if (hipError_t e = hipGetLastError()) return e;
     }

@@ -551,66 +551,62 @@ __device__ __forceinline__ bool macro_colour(const DevSolve &d, int c, int colou
     return (((m % d.ni) + (m / d.ni)) & 1) == colour;
 }
 
-// one transposed half step of k_macro_rbgs (colour `colour`), a thread per
-// cell: the forward step set x_c = Dinv_c (-r_c - sum_q O_cq src_nbr) on its
-// colour and copied the rest; given the adjoint ob of its output, t_c =
-// -Dinv_c^T ob_c joins rbar on the colour, and the adjoint of its input is
+// one transposed half step of k_macro_rbgs (colour `colour`) for cell m: the
+// forward step set x_c = Dinv_c (-r_c - sum_q O_cq src_nbr) on its colour and
+// copied the rest; given the adjoint ob of its output, t_c = -Dinv_c^T ob_c
+// joins rbar on the colour, and the adjoint of its input is
 // ib_m = (m off the colour: ob_m) + sum_q O_nq'^T t_n over neighbours n on
-// the colour, where O_nq' (n's inflow block from m) is -B_mq
-__device__ __forceinline__ void rbgs_adj_cell(const DevSolve &d, int m, int colour, const double *__restrict__ ob,
-                                              double *__restrict__ ib, double *__restrict__ rbar)
+// the colour, where O_nq' (n's inflow block from m) is -B_mq.  Four lanes
+// per cell as in rbgs_cell: lane a computes component a of each t_n, the
+// lanes exchange t_n, and each accumulates its component of ib_m and rbar_m
+// (the sums in the order of one thread per cell: bitwise the same).
+__device__ __forceinline__ void rbgs_adj_cell(const DevSolve &d, int m, int a, int colour,
+                                              const double *__restrict__ ob, double *__restrict__ ib,
+                                              double *__restrict__ rbar)
 {
-    double acc[4];
     const bool on = macro_colour(d, m, colour);
-#pragma unroll
-    for (int a = 0; a < 4; a++) acc[a] = on ? 0.0 : ob[4 * m + a];
+    double acc = on ? 0.0 : ob[4 * m + a];
     for (int q = 0; q < 4; q++) {
         const int n = d.nbr[4 * m + q];
         if (n < 0 || !macro_colour(d, n, colour)) continue;
         const double *Di = d.mDinv + 16 * n;
+        double s = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) s += Di[4 * e + a] * ob[4 * n + e];
+        const double ta = -s;
         double t[4];
 #pragma unroll
-        for (int a = 0; a < 4; a++) {
-            double s = 0;
-#pragma unroll
-            for (int e = 0; e < 4; e++) s += Di[4 * e + a] * ob[4 * n + e];
-            t[a] = -s;
-        }
+        for (int e = 0; e < 4; e++) t[e] = __shfl(ta, e, 4);
         const double *B = d.mO + 64 * m + 16 * q;
 #pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) acc[a] -= B[4 * e + a] * t[e];
+        for (int e = 0; e < 4; e++) acc -= B[4 * e + a] * t[e];
     }
-#pragma unroll
-    for (int a = 0; a < 4; a++) ib[4 * m + a] = acc[a];
+    ib[4 * m + a] = acc;
     if (on) {
         const double *Di = d.mDinv + 16 * m;
+        double s = 0;
 #pragma unroll
-        for (int a = 0; a < 4; a++) {
-            double s = 0;
-#pragma unroll
-            for (int e = 0; e < 4; e++) s += Di[4 * e + a] * ob[4 * m + e];
-            rbar[4 * m + a] -= s;
-        }
+        for (int e = 0; e < 4; e++) s += Di[4 * e + a] * ob[4 * m + e];
+        rbar[4 * m + a] -= s;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj(DevSolve d, int colour, const double *__restrict__ ob,
                                                            double *__restrict__ ib, double *__restrict__ rbar)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < d.nc) rbgs_adj_cell(d, m, colour, ob, ib, rbar);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;     // 4 lanes per cell
+    if ((t >> 2) < d.nc) rbgs_adj_cell(d, t >> 2, t & 3, colour, ob, ib, rbar);
 }
 
 __global__ __launch_bounds__(kBlock) void k_macro_rbgs_adj_group(const DevSolve *__restrict__ tab, MacroGroup g,
                                                                  int colour, int from)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;     // 4 lanes per cell
+    const int i = t >> 2;
     if (i >= g.pre[g.n]) return;
     const int a = group_member(g, i);
     const DevSolve &d = tab[g.idx[a]];
-    rbgs_adj_cell(d, i - g.pre[a], colour, d.mx[from], d.mx[from ^ 1], d.mr);
+    rbgs_adj_cell(d, i - g.pre[a], t & 3, colour, d.mx[from], d.mx[from ^ 1], d.mr);
 }
 
 hipError_t launch_macro_adjoint_setup(const DevSolve &d, int fpar, hipStream_t st)
@@ -634,7 +630,7 @@ hipError_t launch_macro_adjoint_end(const DevSolve &d, int pnew, hipStream_t st)
 
 hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, hipStream_t st)
 {
-    const int gt = (d.nc + kBlock - 1) / kBlock;
+    const int gt = (4 * d.nc + kBlock - 1) / kBlock;          // k_macro_rbgs_adj: 4 lanes per cell
     if (hipError_t e = launch_macro_adjoint_begin(d, pnew, st)) return e;
     // the forward steps ran it = 0 .. inner-1, colour 0 (x -> y) then 1
     // (y -> x); here it = inner-1 .. 0, colour 1 (adjoint of x -> of y) then 0
@@ -651,12 +647,11 @@ hipError_t launch_macro_adjoint_predict(const DevSolve &d, int pnew, int inner, 
 hipError_t launch_macro_gs_group(const DevSolve *tab, const MacroGroup &g, int inner, int adjoint, hipStream_t st)
 {
     if (g.n <= 0) return hipSuccess;
-    const int gt = (g.pre[g.n] + kBlock - 1) / kBlock;
-    const int gt4 = (4 * g.pre[g.n] + kBlock - 1) / kBlock;  // k_macro_rbgs_group: 4 lanes per cell
+    const int gt4 = (4 * g.pre[g.n] + kBlock - 1) / kBlock;  // 4 lanes per cell
     for (int it = 0; it < inner; it++) {
         if (adjoint) {
-            hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 1, 0);
-            hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt), dim3(kBlock), 0, st, tab, g, 0, 1);
+            hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt4), dim3(kBlock), 0, st, tab, g, 1, 0);
+            hipLaunchKernelGGL(k_macro_rbgs_adj_group, dim3(gt4), dim3(kBlock), 0, st, tab, g, 0, 1);
         } else {
             hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt4), dim3(kBlock), 0, st, tab, g, 0, 0);
             hipLaunchKernelGGL(k_macro_rbgs_group, dim3(gt4), dim3(kBlock), 0, st, tab, g, 1, 1);

@@ -1142,7 +1142,9 @@ hipError_t launch_adjoint_init(const DevSolve &d, int fpar, hipStream_t st)
 // Discrete-conservative equilibrium parameters P'(W[par]) of every cell
 // (and dP'/dW if with_M) into mstate: kEqGroup lanes per cell, so one wave
 // serves several cells and the Newton steps' reductions span a few lanes.
-constexpr int kEqGroup = 16;
+// On the 256x128 grid with 64x64 velocities: 1, 2, 4, 8, 16 and 32 lanes
+// per cell take 113, 79, 78, 100, 149 and 243 us.
+constexpr int kEqGroup = 4;
 
 __device__ __forceinline__ void eq_params_cell(const DevSolve &d, int c, int par, int with_M)
 {

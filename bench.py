@@ -226,7 +226,7 @@ def batch_roofline(n_members, seed, sweeps=20, warmup=3):
     return out
 
 
-def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every, accel_below_kn=None, accel=(5, 50)):
+def serving_leg(n_requests, seed, cap, tol, budget_gb, check_every, accel_below_kn=None, accel=(5, 75)):
     """Solve server on a seeded request stream (circle / NACA shapes, meshes
     {64x32, 128x64, 256x128}, velocity grids {16^2, 32^2, 64^2} on [-6, 6],
     Kn log-uniform in [1e-3, 10], Ma in [0.3, 2], half wanting the adjoint).
@@ -747,7 +747,7 @@ def main():
     ap.add_argument("--serving-accel-below-kn", type=float, default=1.0,
                     help="requests below this Kn use the conservative equilibrium and the macroscopic prediction "
                          "(0: none)")
-    ap.add_argument("--serving-accel-inner", type=int, default=50)
+    ap.add_argument("--serving-accel-inner", type=int, default=75)
     ap.add_argument("--workload", choices=("c2", "c3"), default="c2",
                     help="the timed workload: c2 (the benchmark's: 48x48 Newton-Cotes velocities, Kn 0.1, Ma 0.8) "
                          "or c3 (64x64 sinh velocities, Kn 0.1, Ma 0.5) on the 256x128 NACA0012 C-grid; c3 is for "

@@ -256,7 +256,7 @@ class GpuBackend(Backend):
     changes)."""
 
     def __init__(self, precision, stream=None, shape_params: bool = True, accelerate_below_kn=None,
-                 accelerate=(5, 50)):
+                 accelerate=(5, 75)):
         """accelerate_below_kn: requests below this Kn (first order) solve
         with the conservative equilibrium and the macroscopic prediction
         `accelerate` = (every, inner) of both phases; None: never."""

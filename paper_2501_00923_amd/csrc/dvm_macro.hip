@@ -393,6 +393,7 @@ __device__ __forceinline__ int back_face(const DevSolve &d, int n, int c)
 // 32,768 cells).  All four lanes of a cell take the same branches; callers
 // launch whole cells.
 // ---------------------------------------------------------------------------
+static_assert(kBlock % 4 == 0, "the Gauss-Seidel launches keep a cell's four lanes in one workgroup");
 __device__ __forceinline__ void rbgs_cell(const DevSolve &d, int c, int a, int colour, const double *__restrict__ src,
                                            double *__restrict__ dst)
 {

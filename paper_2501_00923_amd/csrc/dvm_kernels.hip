@@ -732,27 +732,46 @@ __device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, 
 #pragma unroll
         for (int i = 0; i < 4; i++) zc[i] = uni(z[4 * c + i]);
     }
+    // one velocity: (CORR) the corrected value, returned for the store, and
+    // its share of the sums
     auto accumulate = [&](int a, int b, int k, T2 r, T2 fs) {
         const double v1d = sm.vx[a], v2d = sm.vy[b];
         if (CORR) {
             const double s1 = ((zc[0] + zc[1] * v1d) + zc[2] * v2d) + zc[3] * (0.5 * (v1d * v1d + v2d * v2d));
             r.x = (T)((double)r.x - s1);
             r.y = (T)((double)r.y - zc[3]);
-            pio[row + k] = r;
         }
         const double wt = sm.wx[a] * sm.wy[b];
         const double g1 = (double)(gc * sm.ex[w][a] * sm.ey[w][b]);
         const double g2 = (double)(th2 * (T)g1);
         adjoint_terms(A0, A1, A2, A3, A4, R, Pw, cq, v1d, v2d, wt, g1, g2, (double)r.x, (double)r.y, (double)fs.x,
                       (double)fs.y, gM, k);
+        return r;
     };
+    // streaming access as in the sweeps: the frozen f and the corrected row
+    // are not read again here (non-temporal), FP32 pairs move 16 bytes
     if (act) {
         if (pair_velocities<T>(n1)) {
             int a = (2 * lane) % n1, b = (2 * lane) / n1;
             const int da = (2 * kWave) % n1, db = (2 * kWave) / n1;
             for (int k = 2 * lane; k < nv; k += 2 * kWave) {
-                accumulate(a, b, k, pin[row + k], fst[row + k]);
-                accumulate(a + 1, b, k + 1, pin[row + k + 1], fst[row + k + 1]);
+                const f4 p4 = *reinterpret_cast<const f4 *>(pin + row + k);
+                const f4 s4 = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(fst + row + k));
+                T2 r0, r1, fs0, fs1;
+                r0.x = p4.x;
+                r0.y = p4.y;
+                r1.x = p4.z;
+                r1.y = p4.w;
+                fs0.x = s4.x;
+                fs0.y = s4.y;
+                fs1.x = s4.z;
+                fs1.y = s4.w;
+                r0 = accumulate(a, b, k, r0, fs0);
+                r1 = accumulate(a + 1, b, k + 1, r1, fs1);
+                if (CORR) {
+                    const f4 o4 = {(float)r0.x, (float)r0.y, (float)r1.x, (float)r1.y};
+                    __builtin_nontemporal_store(o4, reinterpret_cast<f4 *>(pio + row + k));
+                }
                 a += da;
                 b += db;
                 if (a >= n1) {
@@ -764,7 +783,11 @@ __device__ __forceinline__ void adjoint_moments_patch(const DevSolve &d, int p, 
             int a = lane % n1, b = lane / n1;
             const int da = kWave % n1, db = kWave / n1;
             for (int k = lane; k < nv; k += kWave) {
-                accumulate(a, b, k, pin[row + k], fst[row + k]);
+                const T2 r = accumulate(a, b, k, pin[row + k], ntload2(&fst[row + k]));
+                if (CORR) {
+                    __builtin_nontemporal_store(r.x, &pio[row + k].x);
+                    __builtin_nontemporal_store(r.y, &pio[row + k].y);
+                }
                 a += da;
                 b += db;
                 if (a >= n1) {

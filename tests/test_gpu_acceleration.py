@@ -7,7 +7,8 @@ convergence.
   equilibrium, which the prediction needs); O- and C-grids, odd grid sizes (the red-black
   colouring meets itself across the periodic seam), one cell row, ragged
   velocity passes; mixed precision <= 2e-5.
-* Batched members with the prediction end bitwise where they would alone.
+* Batched members with the prediction end bitwise where they would alone,
+  also with more members due at once than one grouped launch takes.
 * On a 128x64 C-grid at Kn 0.1 both iterations converge to 1e-11 and to
   the same drag; at Kn 0.01 the accelerated one reaches 1e-8 while the
   plain one, after the same sweeps, is orders of magnitude away.
@@ -239,4 +240,40 @@ def test_batched_adjoint_prediction_bitwise(precision):
     b.run(5)
     b.close()
     for a, s in zip(alone, members):
+        assert np.array_equal(a, s.state_save(dvm.STATE_PHI))
+
+
+def test_batched_prediction_more_members_than_one_launch_group():
+    """70 members due for their prediction on the same sweeps, more than the
+    64 of one grouped launch (equilibrium parameters, Gauss-Seidel steps):
+    the launches split, and every member ends bitwise where it would alone,
+    in the primal phase and then in the adjoint phase."""
+    _say("[gpu-acc] batch of 70 predicted members")
+    wls = [I.tiny_circle(Kn=float(kn), Ma=0.6) for kn in np.geomspace(0.02, 0.2, 70)]
+
+    def make(wl):
+        s = dvm.Solver.from_workload(wl, equilibrium=1, accelerate=ACC)
+        s.primal_init()
+        return s
+    alone_f, alone_phi = [], []
+    for wl in wls:
+        s = make(wl)
+        s.primal_sweeps(10)
+        alone_f.append(s.state_save(dvm.STATE_F))
+        s.adjoint_init()
+        s.adjoint_sweeps(10)
+        alone_phi.append(s.state_save(dvm.STATE_PHI))
+        del s
+    members = [make(wl) for wl in wls]
+    b = dvm.Batch(members)
+    b.run(10)
+    b.close()
+    for a, s in zip(alone_f, members):
+        assert np.array_equal(a, s.state_save(dvm.STATE_F))
+    for s in members:
+        s.adjoint_init()
+    b = dvm.Batch(members)
+    b.run(10)
+    b.close()
+    for a, s in zip(alone_phi, members):
         assert np.array_equal(a, s.state_save(dvm.STATE_PHI))

@@ -2,7 +2,8 @@
 with a caller-owned work buffer (dvm_batch_create), through the C ABI.
 
 Two creates in a row on the device's fixed table array, the second with a
-smaller batch (fewer, smaller members) after the first is destroyed: every
+smaller batch (fewer, smaller members) after the first is destroyed (the
+first with a member that runs the macroscopic prediction): every
 member's f / phi, moments and residuals bitwise equal to the same members
 run in a dvm_batch_create batch (the same kernels, the same block map).  A
 second live static batch on the device and oversized batches are refused.
@@ -30,10 +31,12 @@ SMALL = [I.tiny_circle(Kn=2.0, Ma=0.4), I.circle_case(12, 6, 17, 5.0, 0.7, 0.8, 
 
 def _members(cases, precision):
     """Fresh solvers: the first in its adjoint phase, the second of the
-    second-order scheme, the others primal."""
+    second-order scheme, the fourth with the conservative equilibrium and
+    the macroscopic prediction, the others primal."""
     out = []
     for i, wl in enumerate(cases):
-        s = dvm.Solver.from_workload(wl, precision=precision, order=2 if i == 1 else 1, correction_every=3)
+        extra = dict(equilibrium=1, accelerate=(3, 5)) if i == 3 else {}
+        s = dvm.Solver.from_workload(wl, precision=precision, order=2 if i == 1 else 1, correction_every=3, **extra)
         s.primal_init()
         s.primal_sweeps(4)
         if i == 0:
